@@ -1,0 +1,203 @@
+"""Sec. 4 of the paper: the recursive sweeping preconditioner.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+* ``LineFactors``    -- one quasi-1D auxiliary problem (Sec. 4.1, moving PML next to the
+                        y-group, Fig. 3), factored by the block LDU of Sec. 3 with the x1
+                        index as block index ("dimension 3 and 2 first and dimension 1 last").
+* ``SlabSweep``      -- one quasi-2D auxiliary problem (H_b or H_m of Sec. 3) and its inner
+                        sweep: Algorithm 3 (setup) and Algorithm 4 (apply).
+* ``RecursiveSweep`` -- Algorithm 5 (setup) and Algorithm 6 (apply) of Sec. 4.2, with the
+                        group/window generalisation of the Sec. 4.2 implementation notes,
+                        and the adjoint apply.
+
+Every coupling block (A_{G_g,G_{g-1}}, the slab's tilde-A blocks, the line's off-diagonal
+blocks) is sliced out of the assembled sparse matrix, and every Schur update uses the full
+block product of Sec. 3 / Sec. 4.1 (S_m = A_mm - A_{m,m-1} T_{m-1} A_{m-1,m}); nothing here
+relies on those blocks being multiples of the identity.
+
+Adjoint.  Algorithm 6 computes M^{-1} = U^{-1} D^{-1} L^{-1} for the block factors
+L = I + (A_{g,g-1} TT_{g-1}), D = diag(TT_g^{-1}), U = I + (TT_g A_{g,g+1}).  Taking the
+conjugate transpose of that product gives M^{-H} = L^{-H} D^{-H} U^{-H}, which is the same
+forward-then-backward pass with every coupling block taken from A^H and every TT_g replaced
+by TT_g^H; the same holds one level down (Algorithm 4 with the slab matrix) and for the
+line solves (K^{-H} = L^{-H} D^{-H} U^{-H} with the block LDU factors).  Pinned by the dot
+test <M^{-1}x, y> = <x, M^{-H}y>.
+
+Pins (tests/test_oracle_sweep.py): each line's block LDU reproduces its matrix and its
+solve equals a dense solve; degenerate partitions reduce Algorithm 6 to an exact solve
+(first groups = whole axis) or to the non-recursive Algorithm 2 with exact auxiliary solves
+(along x3 or along x2); the moving PML makes the auxiliary restriction approach the exact
+Schur-complement inverse T_m of Sec. 3 as p grows; M^{-1} is linear; the dot test above.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .problem import axis_profile, assemble_box, helmholtz_matrix
+from .partition import groups, window
+
+
+def _dense_times_sparse(M, S):
+    """M @ S for a dense M and a sparse S."""
+    return np.asarray((S.T @ M.T).T)
+
+
+def _cols(v):
+    """View a vector as an (N, R) array of right-hand sides."""
+    v = np.asarray(v)
+    return v.reshape(v.shape[0], -1)
+
+
+class LineFactors:
+    """Quasi-1D auxiliary problem of (z-group zg, y-group yg) and its block LDU (Sec. 4.1).
+
+    The grid is x1 = 1..n times the y-window times the z-window.  Within the block of x1
+    index i the unknowns (jj, kk) are ordered with kk (x3) fastest, then jj (x2).
+    ``T[i]`` is the inverse of the Schur complement S_i (numpy.linalg.inv: LU with partial
+    pivoting inside the block; no pivoting across blocks).
+    """
+
+    def __init__(self, prob, Gz, zg, Gy, yg):
+        n, h = prob.n, prob.h
+        zw0, zw1, zfirst = window(Gz, zg, prob.p)
+        yw0, yw1, yfirst = window(Gy, yg, prob.p)
+        px = prob.boundary_axis()
+        py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p)
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p)
+        K = assemble_box(prob.kappa[zw0 - 1:zw1, yw0 - 1:yw1, :], px, py, pz, h)
+        self.Wy, self.Wz = yw1 - yw0 + 1, zw1 - zw0 + 1
+        self.n, self.B = n, self.Wy * self.Wz
+        self.K = K
+        idx = np.arange(K.shape[0]).reshape(self.Wz, self.Wy, n)
+        self.sel = [idx[:, :, i].T.ravel() for i in range(n)]
+        D = [K[s][:, s].toarray() for s in self.sel]
+        self.lo = [K[self.sel[i + 1]][:, self.sel[i]] for i in range(n - 1)]   # K_{i+1,i}
+        self.up = [K[self.sel[i]][:, self.sel[i + 1]] for i in range(n - 1)]   # K_{i,i+1}
+        T = []
+        for i in range(n):
+            if i == 0:
+                S = D[0]
+            else:
+                S = D[i] - _dense_times_sparse(self.lo[i - 1] @ T[i - 1], self.up[i - 1])
+            T.append(np.linalg.inv(S))
+        self.T = T
+        # line-grid unknowns of the physical rows (those of G_yg), in (kk, j, i) C-order
+        a = Gy[yg][0]
+        self.phys = idx[:, a - yw0:, :].ravel()
+
+    def solve(self, r):
+        """K^{-1} r through the factors (the solve formula of Sec. 3 / Sec. 4.1)."""
+        r = _cols(r)
+        g = [r[s].astype(np.complex128) for s in self.sel]
+        for i in range(self.n - 1):                       # L^{-1}
+            g[i + 1] = g[i + 1] - self.lo[i] @ (self.T[i] @ g[i])
+        y = [self.T[i] @ g[i] for i in range(self.n)]    # diag(T)
+        for i in range(self.n - 2, -1, -1):               # U^{-1}
+            y[i] = y[i] - self.T[i] @ (self.up[i] @ y[i + 1])
+        x = np.zeros(r.shape, np.complex128)
+        for i, s in enumerate(self.sel):
+            x[s] = y[i]
+        return x
+
+    def solve_adjoint(self, r):
+        """K^{-H} r = L^{-H} D^{-H} U^{-H} r with the same factors."""
+        r = _cols(r)
+        g = [r[s].astype(np.complex128) for s in self.sel]
+        for i in range(self.n - 1):                       # U^{-H}
+            g[i + 1] = g[i + 1] - self.up[i].conj().T @ (self.T[i].conj().T @ g[i])
+        y = [self.T[i].conj().T @ g[i] for i in range(self.n)]
+        for i in range(self.n - 2, -1, -1):               # L^{-H}
+            y[i] = y[i] - self.T[i].conj().T @ (self.lo[i].conj().T @ y[i + 1])
+        x = np.zeros(r.shape, np.complex128)
+        for i, s in enumerate(self.sel):
+            x[s] = y[i]
+        return x
+
+
+class SlabSweep:
+    """Quasi-2D auxiliary problem of z-group zg and its inner sweep (Algorithms 3 and 4).
+
+    Slab unknowns are ordered (kk, j, i) C-order, i.e. x1 fastest, over the z-window.
+    """
+
+    def __init__(self, prob, Gz, zg, Gy):
+        n = prob.n
+        zw0, zw1, zfirst = window(Gz, zg, prob.p)
+        ax = prob.boundary_axis()
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p)
+        self.H = assemble_box(prob.kappa[zw0 - 1:zw1], ax, ax, pz, prob.h)
+        self.HH = self.H.conj().T.tocsr()
+        self.Wz = zw1 - zw0 + 1
+        idx = np.arange(self.H.shape[0]).reshape(self.Wz, n, n)
+        self.rows = [idx[:, a - 1:e, :].ravel() for (a, e) in Gy]
+        a, e = Gz[zg]
+        self.phys = idx[self.Wz - (e - a + 1):, :, :].ravel()
+        self.lines = [LineFactors(prob, Gz, zg, Gy, yg) for yg in range(len(Gy))]  # Alg. 3
+
+    def _line(self, yg, alpha, adjoint):
+        """The approximate inverse of the line's block: embed, solve, restrict (Sec. 4.1)."""
+        ln = self.lines[yg]
+        r = np.zeros((ln.K.shape[0], alpha.shape[1]), np.complex128)
+        r[ln.phys] = alpha
+        x = ln.solve_adjoint(r) if adjoint else ln.solve(r)
+        return x[ln.phys]
+
+    def apply(self, gv, adjoint=False):
+        """Algorithm 4: v ~ H^{-1} g (or the adjoint with H^H couplings and line adjoints)."""
+        H = self.HH if adjoint else self.H
+        gv = _cols(gv)
+        v = np.zeros(gv.shape, np.complex128)
+        R = self.rows
+        L = len(R)
+        for yg in range(L):
+            rhs = gv[R[yg]].astype(np.complex128)
+            if yg > 0:
+                rhs = rhs - H[R[yg]][:, R[yg - 1]] @ v[R[yg - 1]]
+            v[R[yg]] = self._line(yg, rhs, adjoint)
+        for yg in range(L - 2, -1, -1):
+            v[R[yg]] = v[R[yg]] - self._line(yg, H[R[yg]][:, R[yg + 1]] @ v[R[yg + 1]], adjoint)
+        return v
+
+
+class RecursiveSweep:
+    """Algorithm 5 (setup) and Algorithm 6 (apply) of Sec. 4.2; ``apply(.., adjoint=True)``
+    gives M^{-H} (module docstring).  Vectors are ordered x1 fastest (Sec. 3)."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        n = prob.n
+        self.Gz = groups(n, prob.first_z, prob.d)
+        self.Gy = groups(n, prob.first_y, prob.d)
+        self.A = helmholtz_matrix(prob)
+        self.AH = self.A.conj().T.tocsr()
+        idx = np.arange(n ** 3).reshape(n, n, n)
+        self.layers = [idx[a - 1:e].ravel() for (a, e) in self.Gz]
+        self.slabs = [SlabSweep(prob, self.Gz, g, self.Gy) for g in range(len(self.Gz))]
+
+    def _TT(self, g, alpha, adjoint):
+        """The approximate inverse of the slab block: embed into the window, Algorithm 4, restrict."""
+        s = self.slabs[g]
+        gv = np.zeros((s.H.shape[0], alpha.shape[1]), np.complex128)
+        gv[s.phys] = alpha
+        return s.apply(gv, adjoint)[s.phys]
+
+    def apply(self, f, adjoint=False):
+        A = self.AH if adjoint else self.A
+        f = _cols(f)
+        u = np.zeros(f.shape, np.complex128)
+        Ls = self.layers
+        G = len(Ls)
+        for g in range(G):
+            rhs = f[Ls[g]].astype(np.complex128)
+            if g > 0:
+                rhs = rhs - A[Ls[g]][:, Ls[g - 1]] @ u[Ls[g - 1]]
+            u[Ls[g]] = self._TT(g, rhs, adjoint)
+        for g in range(G - 2, -1, -1):
+            u[Ls[g]] = u[Ls[g]] - self._TT(g, A[Ls[g]][:, Ls[g + 1]] @ u[Ls[g + 1]], adjoint)
+        return u
+
+    def lines(self):
+        """(zg, yg, LineFactors) in sweep order: z-group major, y-group minor."""
+        for g, s in enumerate(self.slabs):
+            for l, ln in enumerate(s.lines):
+                yield g, l, ln

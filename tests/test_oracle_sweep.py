@@ -1,0 +1,156 @@
+"""Pins of the oracle's recursive sweep (Sec. 3-4, Algorithms 3-6) against exact solves,
+the non-recursive Algorithm 2 with exact auxiliary solves, the exact block LDU of Sec. 3,
+and linear-algebra invariants."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from oracle.reference import nonrecursive_apply, exact_layer_T
+from oracle.partition import groups, window
+from oracle.problem import axis_profile, assemble_box
+from paper_1502_07266_amd import inputs
+
+
+def _prob(n=11, b=3, p=3, d=1, **kw):
+    case = inputs.small_case(n=n, b=b, p=p, d=d)
+    return O.Problem(n=n, c=case["c"], omega=case["omega"], b=b, C=case["C"], p=p, d=d, **kw)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_groups_and_windows():
+    G = groups(20, 4, 3)
+    assert G == [(1, 4), (5, 7), (8, 10), (11, 13), (14, 16), (17, 19), (20, 20)]
+    assert window(G, 0, 2) == (1, 4, None)
+    assert window(G, 1, 2) == (3, 7, 5)
+    assert window(G, 6, 4) == (16, 20, 20)
+
+
+def test_moving_profile_matches_shifted_boundary_profile():
+    """For one physical layer and p = b-1 the moving profile is the paper's s(x3 - (m-b)h) on
+    D_m = [(m-b)h, (m+1)h] (Sec. 3), i.e. the boundary profile of width b h shifted."""
+    n, b, C, om = 30, 5, 150.0, 12.0
+    h = 1 / (n + 1)
+    m = 17
+    prof = axis_profile(m - (b - 1), m, n, b, C, om, first_phys=m, p=b - 1)
+    xs_node = np.arange(m - b + 1, m + 1) * h - (m - b) * h
+    xs_half = (np.arange(m - b + 1, m + 2) - 0.5) * h - (m - b) * h
+    s = lambda x: 1 / (1 + 1j * O.sigma(x, b * h, C) / om)
+    assert np.allclose(prof.node, s(xs_node), rtol=1e-14, atol=0)
+    # the half-node above the physical layer keeps the boundary profile (undamped here)
+    assert np.allclose(prof.half[:-1], s(xs_half[:-1]), rtol=1e-14, atol=0)
+    assert prof.half[-1] == 1.0
+
+
+def test_line_ldu_reproduces_line_matrix_and_dense_solve():
+    prob = _prob(n=9, b=3, p=2)
+    M = O.RecursiveSweep(prob)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for g, l, ln in M.lines():
+        if (g, l) not in [(0, 0), (0, 2), (2, 0), (3, 4), (6, 6)]:
+            continue
+        K = ln.K.toarray()
+        Nl = K.shape[0]
+        # block-ordered K and the product of the factors: Lc has diagonal S_i = T_i^{-1} and
+        # sub-diagonal K_{i+1,i}; Uc is unit upper with T_i K_{i,i+1}
+        perm = np.concatenate(ln.sel)
+        Kb = K[np.ix_(perm, perm)]
+        B, n = ln.B, ln.n
+        Lc = np.zeros_like(Kb)
+        Uc = np.eye(Nl, dtype=complex)
+        for i in range(n):
+            Lc[i * B:(i + 1) * B, i * B:(i + 1) * B] = np.linalg.inv(ln.T[i])
+            if i + 1 < n:
+                Lc[(i + 1) * B:(i + 2) * B, i * B:(i + 1) * B] = ln.lo[i].toarray()
+                Uc[i * B:(i + 1) * B, (i + 1) * B:(i + 2) * B] = ln.T[i] @ ln.up[i].toarray()
+        assert np.linalg.norm(Lc @ Uc - Kb) <= 1e-12 * np.linalg.norm(Kb)
+        r = rng.standard_normal((Nl, 2)) + 1j * rng.standard_normal((Nl, 2))
+        assert _rel(ln.solve(r), np.linalg.solve(K, r)) < 1e-12
+        assert _rel(ln.solve_adjoint(r), np.linalg.solve(K.conj().T, r)) < 1e-12
+        checked += 1
+    assert checked == 5
+
+
+def test_degenerate_single_groups_give_exact_inverse():
+    """First group = whole axis in x2 and x3: one line problem equal to A, M^{-1} = A^{-1}."""
+    n = 9
+    prob = _prob(n=n, first_y=n, first_z=n)
+    M = O.RecursiveSweep(prob)
+    f = inputs.random_rhs(n, 2).reshape(2, -1).T
+    x = spla.spsolve(M.A.tocsc(), f)
+    assert _rel(M.apply(f), x) < 1e-12
+    assert _rel(M.apply(f, adjoint=True), spla.spsolve(M.A.conj().T.tocsc(), f)) < 1e-12
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_single_y_group_equals_nonrecursive_x3_sweep(d):
+    """First x2-group = whole axis: each slab has one line = the whole quasi-2D problem, so
+    Algorithm 6 is Algorithm 2 along x3 with exact auxiliary solves (d = 2 has a ragged
+    last group since n - b is odd)."""
+    n = 10
+    prob = _prob(n=n, d=d, first_y=n)
+    f = inputs.random_rhs(n, 2).reshape(2, -1).T
+    assert _rel(O.RecursiveSweep(prob).apply(f), nonrecursive_apply(prob, f, "z")) < 1e-12
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_single_z_group_equals_nonrecursive_x2_sweep(d):
+    """First x3-group = whole axis: one slab = A, swept along x2 with exact quasi-1D solves,
+    i.e. Algorithm 2 along x2 with exact auxiliary solves."""
+    n = 10
+    prob = _prob(n=n, d=d, first_z=n)
+    f = inputs.random_rhs(n, 2).reshape(2, -1).T
+    assert _rel(O.RecursiveSweep(prob).apply(f), nonrecursive_apply(prob, f, "y")) < 1e-12
+
+
+def test_moving_pml_approximates_exact_schur_inverse():
+    """T_m = S_m^{-1} of the exact layer LDU (Sec. 3) is the half-space Green's function on
+    layer m; the auxiliary problem with a moving PML of p cells approximates it, better as p
+    grows, and much better than the same window without damping.  (The floor of ~0.1 is the
+    scattering by the medium below layer m, which the auxiliary problem drops.)"""
+    n, b, m = 19, 5, 15
+    case = inputs.small_case(n=n, b=b, p=b)
+    prob = O.Problem(n=n, c=case["c"], omega=case["omega"], b=b, C=case["C"], p=b)
+    Tex = exact_layer_T(prob)[m - 1]
+    ax = prob.boundary_axis()
+    errs = []
+    for p, C in [(1, case["C"]), (2, case["C"]), (3, case["C"]), (4, case["C"]), (5, case["C"]), (5, 0.0)]:
+        pz = axis_profile(m - p, m, n, b, C, prob.omega, first_phys=m, p=p)
+        H = assemble_box(prob.kappa[m - p - 1:m], ax, ax, pz, prob.h).toarray()
+        Hinv = np.linalg.inv(H)
+        last = slice(p * n * n, (p + 1) * n * n)
+        errs.append(np.linalg.norm(Hinv[last, last] - Tex) / np.linalg.norm(Tex))
+    assert errs[0] > errs[1] > errs[2] > errs[3] > errs[4], errs
+    assert errs[4] < 0.2 and errs[5] > 3 * errs[4], errs
+
+
+def test_preconditioner_linear_and_adjoint_dot():
+    prob = _prob(n=11)
+    M = O.RecursiveSweep(prob)
+    x, y = inputs.random_rhs(11, 2, seed=7).reshape(2, -1)
+    a, bb = 0.3 - 1.1j, 2.0 + 0.5j
+    lhs = M.apply(a * x + bb * y)[:, 0]
+    rhs = a * M.apply(x)[:, 0] + bb * M.apply(y)[:, 0]
+    assert _rel(lhs, rhs) < 1e-13
+    d1 = np.vdot(M.apply(x)[:, 0], y)
+    d2 = np.vdot(x, M.apply(y, adjoint=True)[:, 0])
+    assert abs(d1 - d2) <= 1e-13 * abs(d1)
+    d3 = np.vdot(M.A @ x, y)
+    d4 = np.vdot(x, M.AH @ y)
+    assert abs(d3 - d4) <= 1e-13 * abs(d3)
+
+
+def test_preconditioner_is_close_to_inverse():
+    """M^{-1} approximates A^{-1} well enough that GMRES converges in a handful of iterations
+    (Sec. 5 reports 4-6 at 1e-3); here only that the preconditioned residual contracts."""
+    prob = _prob(n=11)
+    M = O.RecursiveSweep(prob)
+    f = inputs.random_rhs(11, 1, seed=3).reshape(-1)
+    x = spla.spsolve(M.A.tocsc(), f)
+    z = M.apply(f)[:, 0]
+    assert _rel(z, x) < 0.8
+    assert np.linalg.norm(f - M.A @ z) < 0.8 * np.linalg.norm(f)
