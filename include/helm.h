@@ -1,0 +1,193 @@
+/*
+ * helm.h -- C ABI of the MI355X (gfx950) recursive sweeping preconditioner for the 3D
+ * Helmholtz equation (F. Liu, L. Ying, "Recursive Sweeping Preconditioner for the 3D
+ * Helmholtz Equation", 2015).
+ *
+ * Problem (Sec. 2, eq. (2) and its discretisation eq. (3)): on the unit cube with n interior
+ * nodes per axis, h = 1/(n+1), node (i,j,k) at (ih, jh, kh),
+ *     sum_d (s_d)_p/h [ (s_d)_{p+e_d/2}/h (u_{p+e_d}-u_p) - (s_d)_{p-e_d/2}/h (u_p-u_{p-e_d}) ]
+ *     + (omega^2/c^2)_p u_p = f_p ,            u = 0 outside the grid,
+ * with s = 1/(1 + i sigma/omega), sigma(x) = (C/eta)((x-eta)/eta)^2 on [0, eta] (Sec. 2),
+ * eta = b h, mirrored on all six faces (Sec. 5 puts PMLs on every face).
+ *
+ * Conventions for every entry point:
+ *  - All *_dev pointers are device pointers on the current HIP device, owned by the caller,
+ *    contiguous.  Grids are stored with x1 fastest, then x2, then x3 (the column-major order
+ *    of Sec. 3); a batch of R vectors is R consecutive grids of n^3 values.
+ *  - Complex data is interleaved (re, im) double precision (complex128) unless stated.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is queued on it; calls that
+ *    return host outputs (helm_solve, helm_setup's error check) synchronise it.
+ *  - A handle is used by one stream at a time; calls on one handle must not overlap.
+ *  - Return value: HELM_OK (0), HELM_ENOTCONV (1, a warning: outputs are valid), or a
+ *    negative error code.  Nothing is thrown across the ABI.  helm_error_string() names a
+ *    code; helm_last_error() gives the last detailed message of the calling thread.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_OK 0
+#define HELM_ENOTCONV 1     /* GMRES hit maxit; u, iters and relres are still valid      */
+#define HELM_EINVAL (-1)    /* invalid argument (sizes, parameters, non-positive c, ...)  */
+#define HELM_ENOMEM (-2)    /* planned device bytes exceed free memory (checked first)    */
+#define HELM_ESINGULAR (-3) /* zero or non-finite pivot while inverting a block            */
+#define HELM_EHIP (-4)      /* a HIP runtime call failed                                 */
+
+#define HELM_C64 0          /* complex64 factors and sweeps, FP64 GMRES (mixed precision) */
+#define HELM_C128 1         /* complex128 everywhere                                     */
+
+typedef struct helm_handle helm_handle; /* opaque: owns kappa, factors and workspaces */
+
+typedef struct {
+  int n;                    /* interior nodes per axis, h = 1/(n+1)                       */
+} helm_grid;
+
+typedef struct {
+  int b;                    /* boundary PML cells, eta = b h (Sec. 2)                      */
+  double C;                 /* the constant C of sigma (Sec. 2), > 0                        */
+  int p;                    /* moving-PML cells of each auxiliary problem (Sec. 3, 4.2)    */
+} helm_pml;
+
+/*
+ * helm_setup -- Algorithm 5 (with Algorithm 3 per slab, Sec. 4.2): form and block-LDU factor
+ * every quasi-1D auxiliary ("line") problem.
+ *   grid, pml     : host structs.  Requires n >= 2b+1, b >= 1, 0 <= p <= b, C > 0.
+ *   c_dev         : n^3 float64 velocities at the nodes, all finite and > 0; may be freed
+ *                   after the call (the handle keeps omega^2/c^2).
+ *   omega         : angular frequency > 0.
+ *   slab_layers   : d >= 1, physical layers per auxiliary problem in x3 and in x2 (Sec. 4.2).
+ *   prec          : HELM_C64 or HELM_C128 (precision of factors and sweeps).
+ *   out           : receives the handle (NULL on error).
+ * Groups along x3 and x2: nodes 1..b, then consecutive groups of d nodes (the last may be
+ * shorter).  The auxiliary problem of every group but the first is padded with p moving-PML
+ * nodes whose zero-Dirichlet plane lies p+1 spacings below the group, with sigma(.; (p+1)h)
+ * measured from that plane; above the group's first node the boundary profile is kept.
+ * Errors: HELM_EINVAL, HELM_ENOMEM (factor bytes > free memory), HELM_ESINGULAR, HELM_EHIP.
+ * Synchronises `stream`.
+ */
+int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const helm_pml* pml,
+               int slab_layers, int prec, void* stream, helm_handle** out);
+
+/*
+ * helm_apply -- Algorithm 6 (outer sweep over x3-groups; each slab block applied by
+ * Algorithm 4, the inner sweep over x2-groups; each line block solved exactly by its block
+ * LDU): z = M^{-1} r for R right-hand sides in one persistent launch.
+ *   r_dev, z_dev : R*n^3 complex128 each (may not alias).  In HELM_C64 mode r is rounded to
+ *                  complex64 on entry and z is widened on exit.
+ */
+int helm_apply(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream);
+
+/*
+ * helm_apply_adjoint -- z = M^{-H} r: the conjugate transpose of helm_apply's operator (the
+ * same forward-then-backward passes with the couplings of A^H and conjugate-transposed block
+ * inverses).  Same arguments as helm_apply.
+ */
+int helm_apply_adjoint(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream);
+
+/*
+ * helm_matvec -- y = A u (adjoint = 0) or y = A^H u (adjoint = 1), eq. (3), in FP64.
+ *   u_dev, y_dev : R*n^3 complex128 (may not alias).
+ */
+int helm_matvec(helm_handle* h, const void* u_dev, void* y_dev, int R, int adjoint, void* stream);
+
+/*
+ * helm_solve -- right-preconditioned flexible GMRES(restart) in FP64 (Sec. 5 solves eq. (3)
+ * with GMRES preconditioned by the recursive sweep), all R right-hand sides batched.
+ *   f_dev        : R*n^3 complex128 right-hand sides.
+ *   u_dev        : R*n^3 complex128; in: initial guess (zeros for x0 = 0); out: solution.
+ *   tol          : stop when ||f - A u||_2 <= tol ||f||_2 (checked with the true residual).
+ *   restart      : Krylov basis length (>= 1); maxit: iteration cap per right-hand side.
+ *   adjoint      : 0 solves A u = f with M^{-1}; 1 solves A^H u = f with M^{-H}.
+ *   iters_host   : [R] iterations used per right-hand side (may be NULL).
+ *   relres_host  : [R] final true relative residuals (may be NULL).
+ * Returns HELM_ENOTCONV if some right-hand side did not reach tol within maxit.
+ * Synchronises `stream`.
+ */
+int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol, int restart,
+               int maxit, int adjoint, int* iters_host, double* relres_host, void* stream);
+
+/*
+ * helm_grad_c -- adjoint-state gradient of J = 1/2 sum_s ||P u_s - d_s||^2 with respect to
+ * the velocity: grad_p = (2 omega^2 / c_p^3) Re sum_s conj(lam_s,p) u_s,p, where u_s solves
+ * A u = f_s and lam_s solves A^H lam = P^T (P u_s - d_s).  (c enters eq. (3) only through
+ * omega^2/c^2 on the diagonal.)  Uses the handle's current medium.
+ *   u_dev, lam_dev : R*n^3 complex128.   grad_dev : n^3 float64, overwritten.
+ */
+int helm_grad_c(helm_handle* h, const void* u_dev, const void* lam_dev, int R, double* grad_dev,
+                void* stream);
+
+/*
+ * helm_misfit -- receiver misfit J = 1/2 sum_s ||P u_s - d_s||^2, P = restriction to all n^2
+ * nodes of the x3-layer plane_k (1-based), and the adjoint source g_s = P^T (P u_s - d_s)
+ * (the right-hand side of A^H lam_s = g_s in the adjoint-state gradient).
+ *   u_dev   : R*n^3 complex128 solutions.   d_dev : R*n^2 complex128 data (x1 fastest).
+ *   J_host  : receives J (may be NULL).     g_dev : R*n^3 complex128, overwritten (may be NULL).
+ * Synchronises `stream` when J_host is given.
+ */
+int helm_misfit(helm_handle* h, const void* u_dev, const void* d_dev, int R, int plane_k,
+                double* J_host, void* g_dev, void* stream);
+
+/*
+ * helm_set_medium -- replace omega^2/c^2 used by helm_matvec / helm_solve / helm_grad_c with
+ * a new c_dev (n^3 float64 > 0); the factors (built for the old medium) are kept.
+ */
+int helm_set_medium(helm_handle* h, const double* c_dev, void* stream);
+
+/*
+ * helm_info -- sizes of the setup: factor bytes, number of line problems, largest block.
+ * Any output pointer may be NULL.
+ */
+int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max_block);
+
+/*
+ * helm_plan_bytes -- device bytes helm_setup would allocate for these parameters (factors +
+ * coefficients), computed on the host without touching the GPU.  Returns HELM_EINVAL for
+ * invalid parameters.
+ */
+int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers, int prec,
+                    size_t* bytes, int* n_lines, int* max_block);
+
+/*
+ * helm_line_factors -- copy the block inverses T_1..T_n of line problem (zg, yg) (0-based
+ * x3-group and x2-group) into dst_dev: n blocks of B*B complex values, row-major within a
+ * block, unknowns of a block ordered (x2 window row, x3 window layer) with x3 fastest.
+ * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
+ * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
+ */
+int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* B_out,
+                      void* stream);
+
+/*
+ * helm_line_solve -- x = K^{-1} r (adjoint = 0) or K^{-H} r (adjoint = 1) for the line
+ * problem (zg, yg) with its factors, on the line grid (n x Wy x Wz, x1 fastest, then the x2
+ * window row, then the x3 window layer).  r_dev, x_dev: R consecutive line vectors of
+ * n*B complex128 values.  Exposes the building block of helm_apply for testing.
+ */
+int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_dev, int R,
+                    int adjoint, void* stream);
+
+/*
+ * helm_set_launch -- override the sweep's launch shape: lanes per block row (4, 8 or 16;
+ * 0 = automatic).  Changes summation order only, i.e. results agree to rounding.
+ */
+int helm_set_launch(helm_handle* h, int lanes_per_row);
+
+/* helm_destroy -- free the handle and everything it owns (NULL is ignored). */
+void helm_destroy(helm_handle* h);
+
+/* helm_error_string -- static name of a return code. */
+const char* helm_error_string(int code);
+
+/* helm_last_error -- last detailed error message of the calling thread ("" if none). */
+const char* helm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELM_H */

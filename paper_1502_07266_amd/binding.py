@@ -1,0 +1,237 @@
+"""ctypes binding of libhelm (include/helm.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP kernels.  torch
+provides device memory (tensors passed by data_ptr()) and the current HIP stream.  Loading
+fails loudly if libhelm.so has not been built; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelm.so")
+
+HELM_OK, HELM_ENOTCONV, HELM_EINVAL, HELM_ENOMEM, HELM_ESINGULAR, HELM_EHIP = 0, 1, -1, -2, -3, -4
+HELM_C64, HELM_C128 = 0, 1
+
+
+class helm_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int)]
+
+
+class helm_pml(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_int), ("C", ctypes.c_double), ("p", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "helm_setup": (_I, [ctypes.POINTER(helm_grid), _P, _D, ctypes.POINTER(helm_pml), _I, _I, _P,
+                        ctypes.POINTER(_P)]),
+    "helm_apply": (_I, [_P, _P, _P, _I, _P]),
+    "helm_apply_adjoint": (_I, [_P, _P, _P, _I, _P]),
+    "helm_matvec": (_I, [_P, _P, _P, _I, _I, _P]),
+    "helm_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
+    "helm_grad_c": (_I, [_P, _P, _P, _I, _P, _P]),
+    "helm_misfit": (_I, [_P, _P, _P, _I, _I, ctypes.POINTER(_D), _P, _P]),
+    "helm_set_medium": (_I, [_P, _P, _P]),
+    "helm_info": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "helm_plan_bytes": (_I, [ctypes.POINTER(helm_grid), ctypes.POINTER(helm_pml), _I, _I,
+                             ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), _P]),
+    "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
+    "helm_set_launch": (_I, [_P, _I]),
+    "helm_destroy": (None, [_P]),
+    "helm_error_string": (ctypes.c_char_p, [_I]),
+    "helm_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libhelm (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1502_07266_amd.build` (no fallback path exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code, where):
+        L = lib()
+        msg = f"{where}: {L.helm_error_string(code).decode()} ({L.helm_last_error().decode()})"
+        super().__init__(msg)
+        self.code = code
+
+
+def _check(rc, where):
+    if rc < 0:
+        raise HelmError(rc, where)
+    return rc
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def plan_bytes(n, b, C, p, slab_layers=1, prec=HELM_C64):
+    """Device bytes of a setup, computed on the host: (bytes, n_lines, max_block)."""
+    nb, nl, mb = ctypes.c_size_t(), _I(), _I()
+    _check(lib().helm_plan_bytes(ctypes.byref(helm_grid(n)), ctypes.byref(helm_pml(b, C, p)),
+                                 slab_layers, prec, ctypes.byref(nb), ctypes.byref(nl),
+                                 ctypes.byref(mb)), "helm_plan_bytes")
+    return nb.value, nl.value, mb.value
+
+
+class Helm:
+    """One setup of the recursive sweeping preconditioner on the current GPU.
+
+    c: float64 CUDA tensor of shape (n, n, n), indexed [k, j, i] (x1 fastest).  All vector
+    arguments are complex128 CUDA tensors of shape (R, n, n, n) or (n, n, n).
+    """
+
+    def __init__(self, c, omega, b, C, p, slab_layers=1, prec="c64"):
+        import torch
+        if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64):
+            raise TypeError("c must be a float64 CUDA tensor")
+        c = c.contiguous()
+        n = c.shape[0]
+        if tuple(c.shape) != (n, n, n):
+            raise ValueError("c must have shape (n, n, n)")
+        self.n, self.omega, self.b, self.C, self.p, self.d = n, float(omega), b, float(C), p, slab_layers
+        self.prec = HELM_C64 if prec in ("c64", HELM_C64) else HELM_C128
+        h = ctypes.c_void_p()
+        _check(lib().helm_setup(ctypes.byref(helm_grid(n)), _ptr(c), self.omega,
+                                ctypes.byref(helm_pml(b, self.C, p)), slab_layers, self.prec,
+                                _stream(), ctypes.byref(h)), "helm_setup")
+        self._h = h
+
+    # ------------------------------------------------------------------ helpers
+    def _batch(self, x):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128):
+            raise TypeError("vectors must be complex128 CUDA tensors")
+        x = x.contiguous()
+        if x.dim() == 3:
+            x = x.unsqueeze(0)
+        if tuple(x.shape[1:]) != (self.n,) * 3:
+            raise ValueError("vectors must have shape (R, n, n, n)")
+        return x
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("handle was destroyed")
+        return self._h
+
+    # ------------------------------------------------------------------ operations
+    def apply(self, r, adjoint=False):
+        """z = M^{-1} r (or M^{-H} r)."""
+        import torch
+        r = self._batch(r)
+        z = torch.empty_like(r)
+        fn = lib().helm_apply_adjoint if adjoint else lib().helm_apply
+        _check(fn(self.handle, _ptr(r), _ptr(z), r.shape[0], _stream()), "helm_apply")
+        return z
+
+    def matvec(self, u, adjoint=False):
+        import torch
+        u = self._batch(u)
+        y = torch.empty_like(u)
+        _check(lib().helm_matvec(self.handle, _ptr(u), _ptr(y), u.shape[0], int(adjoint), _stream()),
+               "helm_matvec")
+        return y
+
+    def solve(self, f, tol=1e-6, restart=50, maxit=500, adjoint=False, x0=None):
+        """FGMRES solve; returns (u, iters[R], relres[R], status)."""
+        import torch
+        f = self._batch(f)
+        u = torch.zeros_like(f) if x0 is None else self._batch(x0).clone()
+        R = f.shape[0]
+        its = (_I * R)()
+        rel = (_D * R)()
+        rc = _check(lib().helm_solve(self.handle, _ptr(f), _ptr(u), R, float(tol), int(restart),
+                                     int(maxit), int(adjoint), its, rel, _stream()), "helm_solve")
+        return u, np.array(its[:]), np.array(rel[:]), rc
+
+    def misfit(self, u, d, plane_k, want_source=True):
+        """(J, adjoint source g = P^T (P u - d)) for receivers on x3-layer plane_k."""
+        import torch
+        u = self._batch(u)
+        d = d.contiguous()
+        g = torch.empty_like(u) if want_source else None
+        J = _D()
+        _check(lib().helm_misfit(self.handle, _ptr(u), _ptr(d), u.shape[0], int(plane_k),
+                                 ctypes.byref(J), _ptr(g) if g is not None else None, _stream()),
+               "helm_misfit")
+        return J.value, g
+
+    def grad_c(self, u, lam):
+        import torch
+        u = self._batch(u)
+        lam = self._batch(lam)
+        g = torch.empty((self.n,) * 3, dtype=torch.float64, device=u.device)
+        _check(lib().helm_grad_c(self.handle, _ptr(u), _ptr(lam), u.shape[0], _ptr(g), _stream()),
+               "helm_grad_c")
+        return g
+
+    def set_medium(self, c):
+        c = c.contiguous()
+        _check(lib().helm_set_medium(self.handle, _ptr(c), _stream()), "helm_set_medium")
+
+    def info(self):
+        fb, nl, mb = ctypes.c_size_t(), _I(), _I()
+        _check(lib().helm_info(self.handle, ctypes.byref(fb), ctypes.byref(nl), ctypes.byref(mb)),
+               "helm_info")
+        return {"factor_bytes": fb.value, "n_lines": nl.value, "max_block": mb.value}
+
+    def line_factors(self, zg, yg):
+        """The block inverses T_1..T_n of line (zg, yg): tensor (n, B, B)."""
+        import torch
+        B = _I()
+        _check(lib().helm_line_factors(self.handle, zg, yg, None, ctypes.byref(B), _stream()),
+               "helm_line_factors")
+        dt = torch.complex64 if self.prec == HELM_C64 else torch.complex128
+        out = torch.empty((self.n, B.value, B.value), dtype=dt, device="cuda")
+        _check(lib().helm_line_factors(self.handle, zg, yg, _ptr(out), None, _stream()),
+               "helm_line_factors")
+        return out
+
+    def line_solve(self, zg, yg, r, adjoint=False):
+        """x = K^{-1} r on the line grid; r: complex128 (R, Wz, Wy, n)."""
+        import torch
+        r = r.contiguous()
+        x = torch.empty_like(r)
+        _check(lib().helm_line_solve(self.handle, zg, yg, _ptr(r), _ptr(x), r.shape[0], int(adjoint),
+                                     _stream()), "helm_line_solve")
+        return x
+
+    def set_launch(self, lanes_per_row):
+        _check(lib().helm_set_launch(self.handle, int(lanes_per_row)), "helm_set_launch")
+
+    def close(self):
+        if self._h is not None:
+            lib().helm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

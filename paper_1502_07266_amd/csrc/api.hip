@@ -1,0 +1,281 @@
+// C ABI of libhelm: argument validation, memory planning and ownership, error codes.
+// Every numerical step runs in the HIP kernels of this library; the host only plans,
+// allocates, launches and reads the scalars GMRES needs to decide.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr int kBlockLimit = 64;          // largest block B the sweep and setup kernels take
+constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+size_t csize(int prec) { return prec == HELM_C64 ? sizeof(float2) : sizeof(double2); }
+
+int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& plan) {
+  if (!grid || !pml) return fail(HELM_EINVAL, "grid and pml must not be NULL");
+  if (prec != HELM_C64 && prec != HELM_C128) return fail(HELM_EINVAL, "prec must be HELM_C64 or HELM_C128");
+  if (!(pml->C > 0.0) || !std::isfinite(pml->C)) return fail(HELM_EINVAL, "PML constant C must be finite and > 0");
+  std::string msg;
+  int rc = build_plan(grid->n, pml->b, pml->p, d, plan, msg);
+  if (rc != HELM_OK) return fail(rc, msg);
+  if (plan.maxB > kBlockLimit)
+    return fail(HELM_EINVAL, "block size (b or p+d per axis, squared) exceeds 64");
+  const size_t lds = ((size_t)plan.n * plan.maxB + 2 * (plan.n + 2)) * csize(prec);
+  if (lds > kLdsBytes) return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
+  return HELM_OK;
+}
+
+size_t planned_bytes(const Plan& p, int prec) {
+  const size_t N = (size_t)p.n * p.n * p.n;
+  return (size_t)p.total_elems * csize(prec) + N * sizeof(double) +
+         (size_t)(2 * (p.n + 1) + 1 + 2 * p.p + 2 + 5 * (p.n + 2)) * sizeof(double2) +
+         (size_t)p.G * sizeof(GroupInfo) + (size_t)p.G * p.G * sizeof(long long);
+}
+
+void release(helm_handle* h) {
+  void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
+                  h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" {
+
+const char* helm_last_error(void) { return g_last_error.c_str(); }
+
+const char* helm_error_string(int code) {
+  switch (code) {
+    case HELM_OK: return "HELM_OK";
+    case HELM_ENOTCONV: return "HELM_ENOTCONV: GMRES reached maxit before tol";
+    case HELM_EINVAL: return "HELM_EINVAL: invalid argument";
+    case HELM_ENOMEM: return "HELM_ENOMEM: not enough device memory";
+    case HELM_ESINGULAR: return "HELM_ESINGULAR: singular block in the line factorisation";
+    case HELM_EHIP: return "HELM_EHIP: HIP runtime error";
+    default: return "unknown helm status";
+  }
+}
+
+int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers, int prec,
+                    size_t* bytes, int* n_lines, int* max_block) {
+  Plan plan;
+  int rc = validate(grid, pml, slab_layers, prec, plan);
+  if (rc != HELM_OK) return rc;
+  if (bytes) *bytes = planned_bytes(plan, prec);
+  if (n_lines) *n_lines = plan.G * plan.G;
+  if (max_block) *max_block = plan.maxB;
+  return HELM_OK;
+}
+
+int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const helm_pml* pml,
+               int slab_layers, int prec, void* stream, helm_handle** out) {
+  if (!out) return fail(HELM_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!c_dev) return fail(HELM_EINVAL, "c_dev must not be NULL");
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(HELM_EINVAL, "omega must be finite and > 0");
+  Plan plan;
+  int rc = validate(grid, pml, slab_layers, prec, plan);
+  if (rc != HELM_OK) return rc;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(HELM_EHIP, "hipMemGetInfo failed");
+  const size_t need = planned_bytes(plan, prec);
+  if (need > free_b)
+    return fail(HELM_ENOMEM, "setup needs " + std::to_string(need) + " bytes, " +
+                                 std::to_string(free_b) + " free");
+  helm_handle* h = new helm_handle();
+  h->plan = plan;
+  h->n = plan.n;
+  h->prec = prec;
+  h->omega = omega;
+  h->h = 1.0 / (plan.n + 1);
+  h->C = pml->C;
+  (void)hipGetDevice(&h->device);
+  const size_t N = (size_t)plan.n * plan.n * plan.n;
+  hipStream_t s = S(stream);
+  auto bail = [&](int code, const std::string& m) {
+    release(h);
+    delete h;
+    return fail(code, m);
+  };
+#define ALLOC(ptr, bytes)                                                             \
+  if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess)                               \
+    return bail(HELM_ENOMEM, std::string("hipMalloc failed for ") + #ptr);
+  ALLOC(h->kappa, N * sizeof(double));
+  ALLOC(h->sbd, (size_t)(2 * (plan.n + 1) + 1) * sizeof(double2));
+  ALLOC(h->smv, (size_t)(2 * plan.p + 2) * sizeof(double2));
+  ALLOC(h->coef, (size_t)4 * (plan.n + 2) * sizeof(double2));
+  ALLOC(h->diag, (size_t)(plan.n + 2) * sizeof(double2));
+  ALLOC(h->d_groups, (size_t)plan.G * sizeof(GroupInfo));
+  ALLOC(h->d_line_off, (size_t)plan.G * plan.G * sizeof(long long));
+  ALLOC(h->factors, (size_t)plan.total_elems * csize(prec));
+  ALLOC(h->d_err, 2 * sizeof(int));
+#undef ALLOC
+  if (hipMemcpyAsync(h->d_groups, plan.groups.data(), plan.G * sizeof(GroupInfo),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_line_off, plan.line_off.data(), plan.line_off.size() * sizeof(long long),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return bail(HELM_EHIP, "copying the plan failed");
+  if (launch_coefficients(h, c_dev, true, s) != hipSuccess) return bail(HELM_EHIP, "coefficient kernels failed");
+  int err[2] = {0, 0};
+  if (hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(HELM_EHIP, "coefficient kernels failed");
+  if (err[0]) return bail(HELM_EINVAL, "c must be finite and > 0 at every node");
+  hipError_t e = launch_setup(h, s);
+  if (e != hipSuccess) return bail(HELM_EHIP, std::string("setup kernel: ") + hipGetErrorString(e));
+  if (hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(HELM_EHIP, "setup kernel failed");
+  if (err[0]) return bail(HELM_ESINGULAR, "singular block in line " + std::to_string(err[1]));
+  *out = h;
+  return HELM_OK;
+}
+
+static int check_batch(helm_handle* h, const void* a, const void* b, int R) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (!a || !b) return fail(HELM_EINVAL, "vector pointers must not be NULL");
+  if (a == b) return fail(HELM_EINVAL, "input and output must not alias");
+  if (R < 1) return fail(HELM_EINVAL, "R must be >= 1");
+  return HELM_OK;
+}
+
+static int apply_impl(helm_handle* h, const void* r, void* z, int R, bool adjoint, void* stream) {
+  int rc = check_batch(h, r, z, R);
+  if (rc != HELM_OK) return rc;
+  const long long N = (long long)h->n * h->n * h->n;
+  HIP_TRY(launch_apply(h, r, true, N, z, true, N, R, nullptr, adjoint, S(stream)));
+  return HELM_OK;
+}
+
+int helm_apply(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream) {
+  return apply_impl(h, r_dev, z_dev, R, false, stream);
+}
+
+int helm_apply_adjoint(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream) {
+  return apply_impl(h, r_dev, z_dev, R, true, stream);
+}
+
+int helm_matvec(helm_handle* h, const void* u_dev, void* y_dev, int R, int adjoint, void* stream) {
+  int rc = check_batch(h, u_dev, y_dev, R);
+  if (rc != HELM_OK) return rc;
+  const long long N = (long long)h->n * h->n * h->n;
+  HIP_TRY(launch_matvec(h, u_dev, true, nullptr, (double2*)y_dev, R, nullptr, N, N, adjoint != 0, 0,
+                        S(stream)));
+  return HELM_OK;
+}
+
+int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol, int restart,
+               int maxit, int adjoint, int* iters_host, double* relres_host, void* stream) {
+  int rc = check_batch(h, f_dev, u_dev, R);
+  if (rc != HELM_OK) return rc;
+  if (!(tol > 0.0)) return fail(HELM_EINVAL, "tol must be > 0");
+  if (maxit < 0) return fail(HELM_EINVAL, "maxit must be >= 0");
+  std::string msg;
+  rc = fgmres_solve(h, (const double2*)f_dev, (double2*)u_dev, R, tol, restart, maxit, adjoint != 0,
+                    iters_host, relres_host, S(stream), msg);
+  if (rc < 0) return fail(rc, msg);
+  return rc;
+}
+
+int helm_grad_c(helm_handle* h, const void* u_dev, const void* lam_dev, int R, double* grad_dev,
+                void* stream) {
+  int rc = check_batch(h, u_dev, lam_dev, R);
+  if (rc != HELM_OK) return rc;
+  if (!grad_dev) return fail(HELM_EINVAL, "grad_dev must not be NULL");
+  HIP_TRY(launch_grad(h, (const double2*)u_dev, (const double2*)lam_dev, R, grad_dev, S(stream)));
+  return HELM_OK;
+}
+
+int helm_misfit(helm_handle* h, const void* u_dev, const void* d_dev, int R, int plane_k,
+                double* J_host, void* g_dev, void* stream) {
+  int rc = check_batch(h, u_dev, d_dev, R);
+  if (rc != HELM_OK) return rc;
+  if (plane_k < 1 || plane_k > h->n) return fail(HELM_EINVAL, "plane_k must be in [1, n]");
+  hipStream_t s = S(stream);
+  double* J_dev = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&J_dev, sizeof(double), s));
+  hipError_t e = launch_misfit(h, (const double2*)u_dev, (const double2*)d_dev, R, plane_k, J_dev,
+                               (double2*)g_dev, s);
+  if (e == hipSuccess && J_host) {
+    e = hipMemcpyAsync(J_host, J_dev, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  hipError_t e2 = hipFreeAsync(J_dev, s);
+  HIP_TRY(e);
+  HIP_TRY(e2);
+  return HELM_OK;
+}
+
+int helm_set_medium(helm_handle* h, const double* c_dev, void* stream) {
+  if (!h || !c_dev) return fail(HELM_EINVAL, "handle and c_dev must not be NULL");
+  hipStream_t s = S(stream);
+  HIP_TRY(launch_coefficients(h, c_dev, false, s));
+  int err[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err[0]) return fail(HELM_EINVAL, "c must be finite and > 0 at every node");
+  return HELM_OK;
+}
+
+int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max_block) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (factor_bytes) *factor_bytes = (size_t)h->plan.total_elems * csize(h->prec);
+  if (n_lines) *n_lines = h->plan.G * h->plan.G;
+  if (max_block) *max_block = h->plan.maxB;
+  return HELM_OK;
+}
+
+int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* B_out,
+                      void* stream) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  const int G = h->plan.G;
+  if (zg < 0 || zg >= G || yg < 0 || yg >= G) return fail(HELM_EINVAL, "group index out of range");
+  const size_t line = (size_t)zg * G + yg;
+  const int B = h->plan.line_B[line];
+  if (B_out) *B_out = B;
+  if (!dst_dev) return HELM_OK;
+  const size_t cs = csize(h->prec);
+  HIP_TRY(hipMemcpyAsync(dst_dev, (const char*)h->factors + (size_t)h->plan.line_off[line] * cs,
+                         (size_t)h->n * B * B * cs, hipMemcpyDeviceToDevice, S(stream)));
+  return HELM_OK;
+}
+
+int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_dev, int R,
+                    int adjoint, void* stream) {
+  int rc = check_batch(h, r_dev, x_dev, R);
+  if (rc != HELM_OK) return rc;
+  const int G = h->plan.G;
+  if (zg < 0 || zg >= G || yg < 0 || yg >= G) return fail(HELM_EINVAL, "group index out of range");
+  HIP_TRY(launch_line_solve(h, zg, yg, (const double2*)r_dev, (double2*)x_dev, R, adjoint != 0,
+                            S(stream)));
+  return HELM_OK;
+}
+
+int helm_set_launch(helm_handle* h, int lanes_per_row) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (lanes_per_row != 0 && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
+    return fail(HELM_EINVAL, "lanes_per_row must be 0, 4, 8 or 16");
+  h->lanes_override = lanes_per_row;
+  return HELM_OK;
+}
+
+void helm_destroy(helm_handle* h) {
+  if (!h) return;
+  release(h);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP sources of libhelm (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "helm.h"
+
+// ---------------------------------------------------------------------------------------
+// complex arithmetic on float2 / double2 (interleaved re, im)
+// ---------------------------------------------------------------------------------------
+template <typename R> struct cx;
+template <> struct cx<float> { using type = float2; };
+template <> struct cx<double> { using type = double2; };
+
+__host__ __device__ inline float2 mk(float r, float i) { return make_float2(r, i); }
+__host__ __device__ inline double2 mk(double r, double i) { return make_double2(r, i); }
+
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __host__ __device__ inline C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __host__ __device__ inline C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __host__ __device__ inline C cconj(C a) { return C{a.x, -a.y}; }
+// a + b * c
+template <typename C> __host__ __device__ inline C cfma(C a, C b, C c) {
+  return C{a.x + b.x * c.x - b.y * c.y, a.y + b.x * c.y + b.y * c.x};
+}
+// a + conj(b) * c
+template <typename C> __host__ __device__ inline C cfma_conj(C a, C b, C c) {
+  return C{a.x + b.x * c.x + b.y * c.y, a.y + b.x * c.y - b.y * c.x};
+}
+template <typename C> __host__ __device__ inline auto cabs2(C a) { return a.x * a.x + a.y * a.y; }
+template <typename C> __host__ __device__ inline C cinv(C a) {
+  auto d = a.x * a.x + a.y * a.y;
+  return C{a.x / d, -a.y / d};
+}
+template <typename C> __host__ __device__ inline C cscale(C a, decltype(a.x) s) { return C{a.x * s, a.y * s}; }
+
+// conversions between storage and compute types
+template <typename D, typename S> __host__ __device__ inline D cvt(S s);
+template <> __host__ __device__ inline float2 cvt<float2, float2>(float2 s) { return s; }
+template <> __host__ __device__ inline double2 cvt<double2, double2>(double2 s) { return s; }
+template <> __host__ __device__ inline float2 cvt<float2, double2>(double2 s) {
+  return make_float2((float)s.x, (float)s.y);
+}
+template <> __host__ __device__ inline double2 cvt<double2, float2>(float2 s) {
+  return make_double2((double)s.x, (double)s.y);
+}
+
+// ---------------------------------------------------------------------------------------
+// partition of an axis into groups and their auxiliary windows
+// ---------------------------------------------------------------------------------------
+struct GroupInfo {
+  int first;  // first physical node (1-based)
+  int last;   // last physical node
+  int w0;     // first node of the auxiliary window (= first - p for moving groups)
+  int W;      // window length
+};
+
+struct Plan {
+  int n = 0, b = 0, p = 0, d = 0, G = 0;
+  std::vector<GroupInfo> groups;      // same partition along x2 and x3
+  std::vector<long long> line_off;    // [G*G] offset (complex elements) of line (g, l) = g*G + l
+  std::vector<int> line_B;            // [G*G]
+  long long total_elems = 0;          // sum over lines of n * B^2
+  int maxB = 0, maxW = 0;
+};
+
+// builds the plan; returns HELM_OK or HELM_EINVAL (with a message)
+int build_plan(int n, int b, int p, int d, Plan& plan, std::string& msg);
+
+// ---------------------------------------------------------------------------------------
+// the opaque handle
+// ---------------------------------------------------------------------------------------
+struct helm_handle {
+  Plan plan;
+  int n = 0, prec = HELM_C64, device = 0;
+  double omega = 0, h = 0, C = 0;
+  int lanes_override = 0;
+
+  // device data
+  double* kappa = nullptr;         // n^3, omega^2 / c^2
+  double2* sbd = nullptr;          // boundary profile s at half-steps t = 0 .. 2(n+1)
+  double2* smv = nullptr;          // moving profile s at half-steps u = 0 .. 2p+1 from its plane
+  double2* coef = nullptr;         // [4][n+2]: A[m,m-1], A[m,m+1], A^H[m,m-1], A^H[m,m+1]
+  double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
+  GroupInfo* d_groups = nullptr;   // [G]
+  long long* d_line_off = nullptr; // [G*G]
+  void* factors = nullptr;         // total_elems complex64 or complex128
+  int* d_err = nullptr;            // [2]: error flag, first failing line
+
+  // apply workspace (grown on demand)
+  void* slab_scratch = nullptr;
+  size_t slab_scratch_bytes = 0;
+  int* d_rhs_idx = nullptr;
+  int rhs_idx_cap = 0;
+};
+
+// ---------------------------------------------------------------------------------------
+// internal launchers (all asynchronous on `stream`)
+// ---------------------------------------------------------------------------------------
+hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables, hipStream_t s);
+hipError_t launch_setup(helm_handle* h, hipStream_t s);
+// z = M^{-1} r (or M^{-H}) for `R` right-hand sides; r in complex128 or complex64, z likewise;
+// rhs_idx (device, may be null = identity) selects which vectors to process: workgroup a
+// reads r + idx[a]*r_stride and writes z + idx[a]*z_stride (strides in complex elements).
+hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
+                        bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
+                        hipStream_t s);
+hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, double2* x, int R,
+                             bool adjoint, hipStream_t s);
+// y = A u (mode 0) or y = f - A u (mode 1); u complex128 or complex64 (u64 = false)
+hipError_t launch_matvec(helm_handle* h, const void* u, bool u64, const double2* f, double2* y,
+                         int R, const int* rhs_idx, long long u_stride, long long y_stride,
+                         bool adjoint, int mode, hipStream_t s);
+hipError_t launch_grad(helm_handle* h, const double2* u, const double2* lam, int R, double* grad,
+                       hipStream_t s);
+hipError_t launch_misfit(helm_handle* h, const double2* u, const double2* d, int R, int plane_k,
+                        double* J_dev, double2* g, hipStream_t s);
+int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol, int restart,
+                 int maxit, bool adjoint, int* iters, double* relres, hipStream_t s, std::string& msg);
+
+void set_error(const std::string& msg);
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e__ = (expr);                                                           \
+    if (e__ != hipSuccess) {                                                           \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e__));                  \
+      return HELM_EHIP;                                                                \
+    }                                                                                  \
+  } while (0)

@@ -1,0 +1,392 @@
+// Flexible GMRES(m) on the GPU, FP64, batched over right-hand sides: the outer Krylov solver
+// of Sec. 5 (GMRES around the whole 3D system, preconditioned by the recursive sweep).
+//
+// Right preconditioning with stored directions z_j = M^{-1} v_j (Saad's flexible variant), so
+// the complex64 sweep of the mixed-precision mode enters only through z_j, which is exact in
+// complex64 storage; the basis V, the Hessenberg matrix, the Givens rotations, the residual
+// and the update x += Z y are FP64.  Orthogonalisation is classical Gram-Schmidt applied twice
+// (two batched reductions per step instead of j+1 dependent ones).  x0 is the caller's u.
+// After each cycle (or when a right-hand side's residual estimate reaches tol) the true
+// residual ||f - A x|| decides convergence.
+//
+// All right-hand sides of a call advance in lockstep through one launch per kernel; a
+// right-hand side that converges leaves the active index list.  The host reads R residual
+// estimates per iteration to decide.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kDotThreads = 256;
+constexpr int kDotPerThread = 8;
+constexpr int kDotChunk = kDotThreads * kDotPerThread;
+constexpr int kMaxRestart = 200;
+
+__device__ inline double2 block_sum(double2 v, double2* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = cadd(s, red[i]);
+  return s;
+}
+
+// partial[(a*K + k)*nchunk + chunk] = sum over the chunk of conj(X_k) w, for the active vector a
+template <typename TX>
+__global__ void __launch_bounds__(kDotThreads) k_dots(const TX* __restrict__ X, long long xr,
+                                                      long long xk, int K,
+                                                      const double2* __restrict__ w, long long wr,
+                                                      const int* __restrict__ idx,
+                                                      double2* __restrict__ partial, int nchunk,
+                                                      long long N) {
+  __shared__ double2 red[kDotThreads / 64];
+  const int a = blockIdx.y, q = idx[a], chunk = blockIdx.x;
+  const long long base = (long long)chunk * kDotChunk + threadIdx.x;
+  double2 wv[kDotPerThread];
+#pragma unroll
+  for (int t = 0; t < kDotPerThread; ++t) {
+    const long long e = base + (long long)t * kDotThreads;
+    wv[t] = e < N ? w[(long long)q * wr + e] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < K; ++k) {
+    const TX* xp = X + (long long)q * xr + (long long)k * xk;
+    double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kDotPerThread; ++t) {
+      const long long e = base + (long long)t * kDotThreads;
+      if (e < N) s = cfma_conj(s, cvt<double2>(xp[e]), wv[t]);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[((long long)a * K + k) * nchunk + chunk] = s;
+  }
+}
+
+// out[q*ostride + k] = sum_chunks partial (mode 0), or sqrt(Re sum) (mode 1, norms)
+__global__ void k_dots_final(const double2* __restrict__ partial, int K, int nchunk,
+                             const int* __restrict__ idx, double2* __restrict__ out, int ostride,
+                             int mode) {
+  const int a = blockIdx.x, q = idx[a];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    const double2* p = partial + ((long long)a * K + k) * nchunk;
+    for (int c = 0; c < nchunk; ++c) s = cadd(s, p[c]);
+    if (mode == 1) s = make_double2(sqrt(fmax(s.x, 0.0)), 0.0);
+    out[(long long)q * ostride + k] = s;
+  }
+}
+
+// y_q += sign * sum_{k < K_q} coef[q][k] X_{q,k}
+template <typename TX>
+__global__ void __launch_bounds__(256) k_axpy_multi(double2* __restrict__ y, long long yr,
+                                                    const TX* __restrict__ X, long long xr,
+                                                    long long xk, const double2* __restrict__ coef,
+                                                    int cstride, int K, const int* __restrict__ kq,
+                                                    double sign, const int* __restrict__ idx,
+                                                    long long N) {
+  __shared__ double2 c[kMaxRestart + 1];
+  const int a = blockIdx.y, q = idx[a];
+  const int Kq = kq ? kq[q] : K;
+  for (int k = threadIdx.x; k < Kq; k += blockDim.x) {
+    double2 v = coef[(long long)q * cstride + k];
+    c[k] = make_double2(sign * v.x, sign * v.y);
+  }
+  __syncthreads();
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double2 acc = y[(long long)q * yr + e];
+  const TX* xp = X + (long long)q * xr + e;
+  for (int k = 0; k < Kq; ++k) acc = cfma(acc, c[k], cvt<double2>(xp[(long long)k * xk]));
+  y[(long long)q * yr + e] = acc;
+}
+
+// V_q = W_q / nrm_q (0 if the norm vanished: breakdown, the residual is then exactly zero)
+__global__ void __launch_bounds__(256) k_scale(double2* __restrict__ V, long long vr,
+                                               const double2* __restrict__ W, long long wr,
+                                               const double2* __restrict__ nrm,
+                                               const int* __restrict__ idx, long long N) {
+  const int q = idx[blockIdx.y];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const double s = nrm[q].x > 0.0 ? 1.0 / nrm[q].x : 0.0;
+  const double2 w = W[(long long)q * wr + e];
+  V[(long long)q * vr + e] = make_double2(w.x * s, w.y * s);
+}
+
+// start of a cycle: g = (beta, 0, ..., 0)
+__global__ void k_cycle_init(double2* g, int gstride, const double2* beta, const int* idx, int na) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int q = idx[a];
+  for (int i = 0; i < gstride; ++i) g[(long long)q * gstride + i] = make_double2(0.0, 0.0);
+  g[(long long)q * gstride] = beta[q];
+}
+
+// column j of the Hessenberg matrix: h = h1 + h2 (two Gram-Schmidt passes), h_{j+1,j} = ||w||;
+// apply the previous rotations, make and apply a new one, update g, residual estimate |g_{j+1}|
+__global__ void k_givens(int j, int m, const double2* h1, const double2* h2, const double2* hn,
+                         double2* H, double* cs, double2* sn, double2* g, double* resid,
+                         const int* idx, int na) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int q = idx[a];
+  double2 col[kMaxRestart + 1];
+  for (int i = 0; i <= j; ++i)
+    col[i] = cadd(h1[(long long)q * (m + 1) + i], h2[(long long)q * (m + 1) + i]);
+  col[j + 1] = make_double2(hn[q].x, 0.0);
+  double* c = cs + (long long)q * m;
+  double2* s = sn + (long long)q * m;
+  for (int i = 0; i < j; ++i) {
+    const double2 t = cadd(cscale(col[i], c[i]), cmul(s[i], col[i + 1]));
+    col[i + 1] = csub(cscale(col[i + 1], c[i]), cmul(cconj(s[i]), col[i]));
+    col[i] = t;
+  }
+  // [[c, s], [-conj(s), c]] (a, b) = (rho, 0), c real
+  const double2 av = col[j];
+  const double bv = col[j + 1].x;
+  const double aa = sqrt(cabs2(av));
+  double cj;
+  double2 sj, rho;
+  if (bv == 0.0) {
+    cj = 1.0;
+    sj = make_double2(0.0, 0.0);
+    rho = av;
+  } else if (aa == 0.0) {
+    cj = 0.0;
+    sj = make_double2(1.0, 0.0);
+    rho = make_double2(bv, 0.0);
+  } else {
+    const double r = hypot(aa, bv);
+    cj = aa / r;
+    sj = make_double2(av.x / aa * bv / r, av.y / aa * bv / r);
+    rho = make_double2(av.x / aa * r, av.y / aa * r);
+  }
+  c[j] = cj;
+  s[j] = sj;
+  col[j] = rho;
+  double2* gq = g + (long long)q * (m + 1);
+  const double2 gj = gq[j];
+  gq[j + 1] = cmul(make_double2(-sj.x, sj.y), gj);   // -conj(s) g_j
+  gq[j] = cscale(gj, cj);
+  double2* Hq = H + (long long)q * (m + 1) * m;
+  for (int i = 0; i <= j; ++i) Hq[(long long)i * m + j] = col[i];
+  resid[q] = sqrt(cabs2(gq[j + 1]));
+}
+
+// y = R^{-1} g for the leading k_q x k_q triangle
+__global__ void k_trisolve(int m, const double2* H, const double2* g, const int* kq, double2* y,
+                           const int* idx, int na) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int q = idx[a];
+  const int k = kq[q];
+  const double2* Hq = H + (long long)q * (m + 1) * m;
+  const double2* gq = g + (long long)q * (m + 1);
+  double2* yq = y + (long long)q * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 s = gq[i];
+    for (int l = i + 1; l < k; ++l) s = csub(s, cmul(Hq[(long long)i * m + l], yq[l]));
+    yq[i] = cmul(s, cinv(Hq[(long long)i * m + i]));
+  }
+}
+
+struct Workspace {
+  double2 *V = nullptr, *W = nullptr, *partial = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *ycoef = nullptr, *fnrm = nullptr;
+  void* Z = nullptr;
+  double *cs = nullptr, *resid = nullptr;
+  int *idx = nullptr, *kq = nullptr;
+  std::vector<void*> all;
+  ~Workspace() {
+    for (void* p : all) (void)hipFree(p);
+  }
+  template <typename T> hipError_t get(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+      all.push_back(q);
+      *p = (T*)q;
+    }
+    return e;
+  }
+};
+
+}  // namespace
+
+#define HIP_MSG(expr)                                                   \
+  do {                                                                  \
+    hipError_t e__ = (expr);                                            \
+    if (e__ != hipSuccess) {                                            \
+      msg = std::string(#expr) + ": " + hipGetErrorString(e__);         \
+      return HELM_EHIP;                                                 \
+    }                                                                   \
+  } while (0)
+
+int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol, int restart,
+                 int maxit, bool adjoint, int* iters, double* relres, hipStream_t s,
+                 std::string& msg) {
+  const int m = restart;
+  if (m < 1 || m > kMaxRestart) {
+    msg = "restart must be in [1, 200]";
+    return HELM_EINVAL;
+  }
+  const long long N = (long long)h->n * h->n * h->n;
+  const bool c64 = h->prec == HELM_C64;
+  const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  Workspace ws;
+  HIP_MSG(ws.get(&ws.V, (size_t)R * (m + 1) * N));
+  if (c64) {
+    float2* z = nullptr;
+    HIP_MSG(ws.get(&z, (size_t)R * m * N));
+    ws.Z = z;
+  } else {
+    double2* z = nullptr;
+    HIP_MSG(ws.get(&z, (size_t)R * m * N));
+    ws.Z = z;
+  }
+  HIP_MSG(ws.get(&ws.W, (size_t)R * N));
+  HIP_MSG(ws.get(&ws.partial, (size_t)R * (m + 1) * nchunk));
+  HIP_MSG(ws.get(&ws.H, (size_t)R * (m + 1) * m));
+  HIP_MSG(ws.get(&ws.sn, (size_t)R * m));
+  HIP_MSG(ws.get(&ws.cs, (size_t)R * m));
+  HIP_MSG(ws.get(&ws.g, (size_t)R * (m + 1)));
+  HIP_MSG(ws.get(&ws.h1, (size_t)R * (m + 1)));
+  HIP_MSG(ws.get(&ws.h2, (size_t)R * (m + 1)));
+  HIP_MSG(ws.get(&ws.nrm, (size_t)R));
+  HIP_MSG(ws.get(&ws.fnrm, (size_t)R));
+  HIP_MSG(ws.get(&ws.ycoef, (size_t)R * m));
+  HIP_MSG(ws.get(&ws.resid, (size_t)R));
+  HIP_MSG(ws.get(&ws.idx, (size_t)R));
+  HIP_MSG(ws.get(&ws.kq, (size_t)R));
+
+  std::vector<int> its(R, 0), kq(R, 0);
+  std::vector<double> fn(R), beta(R), res(R);
+  std::vector<char> done(R, 0);
+  std::vector<int> act;
+
+  auto upload = [&](const std::vector<int>& v) -> hipError_t {
+    return hipMemcpyAsync(ws.idx, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  };
+  // norms of the batch (X = w)
+  auto norms = [&](const double2* w, const std::vector<int>& a, double2* out) -> hipError_t {
+    dim3 gd(nchunk, (unsigned)a.size());
+    k_dots<double2><<<gd, kDotThreads, 0, s>>>(w, N, 0, 1, w, N, ws.idx, ws.partial, nchunk, N);
+    k_dots_final<<<(unsigned)a.size(), 64, 0, s>>>(ws.partial, 1, nchunk, ws.idx, out, 1, 1);
+    return hipGetLastError();
+  };
+
+  std::vector<int> all(R);
+  for (int q = 0; q < R; ++q) all[q] = q;
+  HIP_MSG(upload(all));
+  HIP_MSG(norms(f, all, ws.fnrm));
+  std::vector<double2> tmp(R);
+  HIP_MSG(hipMemcpyAsync(tmp.data(), ws.fnrm, R * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIP_MSG(hipStreamSynchronize(s));
+  for (int q = 0; q < R; ++q) fn[q] = tmp[q].x;
+
+  const long long Vr = (long long)(m + 1) * N, Zr = (long long)m * N;
+  int status = HELM_OK;
+  while (true) {
+    // ---- true residual of every unfinished right-hand side ----
+    std::vector<int> cyc;
+    for (int q = 0; q < R; ++q)
+      if (!done[q]) cyc.push_back(q);
+    if (cyc.empty()) break;
+    HIP_MSG(upload(cyc));
+    HIP_MSG(launch_matvec(h, u, true, f, ws.W, (int)cyc.size(), ws.idx, N, N, adjoint, 1, s));
+    HIP_MSG(norms(ws.W, cyc, ws.nrm));
+    HIP_MSG(hipMemcpyAsync(tmp.data(), ws.nrm, R * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_MSG(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int q : cyc) {
+      beta[q] = tmp[q].x;
+      res[q] = fn[q] > 0 ? beta[q] / fn[q] : 0.0;
+      if (beta[q] <= tol * fn[q]) {
+        done[q] = 1;
+      } else if (its[q] >= maxit) {
+        done[q] = 1;
+        status = HELM_ENOTCONV;
+      } else {
+        next.push_back(q);
+      }
+    }
+    if (next.empty()) break;
+    act = next;
+    HIP_MSG(upload(act));
+    const unsigned na = (unsigned)act.size();
+    // V_0 = r / beta, g = (beta, 0, ...)
+    k_scale<<<dim3(nb, na), 256, 0, s>>>(ws.V, Vr, ws.W, N, ws.nrm, ws.idx, N);
+    k_cycle_init<<<(na + 63) / 64, 64, 0, s>>>(ws.g, m + 1, ws.nrm, ws.idx, (int)na);
+    HIP_MSG(hipGetLastError());
+    std::vector<int> cycle_set = act;
+    for (int q : cycle_set) kq[q] = 0;
+    for (int j = 0; j < m && !act.empty(); ++j) {
+      const unsigned a = (unsigned)act.size();
+      // z_j = M^{-1} v_j
+      HIP_MSG(launch_apply(h, ws.V + (long long)j * N, true, Vr,
+                           c64 ? (void*)((float2*)ws.Z + (long long)j * N)
+                               : (void*)((double2*)ws.Z + (long long)j * N),
+                           !c64, Zr, (int)a, ws.idx, adjoint, s));
+      // w = A z_j
+      HIP_MSG(launch_matvec(h,
+                            c64 ? (const void*)((float2*)ws.Z + (long long)j * N)
+                                : (const void*)((double2*)ws.Z + (long long)j * N),
+                            !c64, nullptr, ws.W, (int)a, ws.idx, Zr, N, adjoint, 0, s));
+      // two classical Gram-Schmidt passes
+      for (int pass = 0; pass < 2; ++pass) {
+        double2* hp = pass == 0 ? ws.h1 : ws.h2;
+        k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, Vr, N, j + 1, ws.W, N,
+                                                                ws.idx, ws.partial, nchunk, N);
+        k_dots_final<<<a, 64, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, hp, m + 1, 0);
+        k_axpy_multi<double2><<<dim3(nb, a), 256, 0, s>>>(ws.W, N, ws.V, Vr, N, hp, m + 1, j + 1,
+                                                          nullptr, -1.0, ws.idx, N);
+      }
+      HIP_MSG(norms(ws.W, act, ws.nrm));
+      k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V + (long long)(j + 1) * N, Vr, ws.W, N, ws.nrm,
+                                          ws.idx, N);
+      k_givens<<<(a + 63) / 64, 64, 0, s>>>(j, m, ws.h1, ws.h2, ws.nrm, ws.H, ws.cs, ws.sn, ws.g,
+                                           ws.resid, ws.idx, (int)a);
+      HIP_MSG(hipGetLastError());
+      std::vector<double> rr(R);
+      HIP_MSG(hipMemcpyAsync(rr.data(), ws.resid, R * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_MSG(hipStreamSynchronize(s));
+      std::vector<int> keep;
+      for (int q : act) {
+        its[q] += 1;
+        kq[q] = j + 1;
+        res[q] = fn[q] > 0 ? rr[q] / fn[q] : 0.0;
+        if (rr[q] > tol * fn[q] && its[q] < maxit) keep.push_back(q);
+      }
+      if (keep.size() != act.size()) {
+        act = keep;
+        if (!act.empty()) HIP_MSG(upload(act));
+      }
+    }
+    // ---- x += Z y for every right-hand side of this cycle ----
+    HIP_MSG(upload(cycle_set));
+    HIP_MSG(hipMemcpyAsync(ws.kq, kq.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
+    const unsigned nc = (unsigned)cycle_set.size();
+    k_trisolve<<<(nc + 63) / 64, 64, 0, s>>>(m, ws.H, ws.g, ws.kq, ws.ycoef, ws.idx, (int)nc);
+    if (c64)
+      k_axpy_multi<float2><<<dim3(nb, nc), 256, 0, s>>>(u, N, (const float2*)ws.Z, Zr, N, ws.ycoef,
+                                                        m, m, ws.kq, 1.0, ws.idx, N);
+    else
+      k_axpy_multi<double2><<<dim3(nb, nc), 256, 0, s>>>(u, N, (const double2*)ws.Z, Zr, N,
+                                                         ws.ycoef, m, m, ws.kq, 1.0, ws.idx, N);
+    HIP_MSG(hipGetLastError());
+  }
+  for (int q = 0; q < R; ++q) {
+    if (iters) iters[q] = its[q];
+    if (relres) relres[q] = res[q];
+  }
+  HIP_MSG(hipStreamSynchronize(s));
+  return status;
+}

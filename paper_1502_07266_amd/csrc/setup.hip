@@ -1,0 +1,204 @@
+// Setup of the recursive sweep (Algorithm 5, with Algorithm 3 per slab): every quasi-1D
+// auxiliary problem is factored by the block LDU of Sec. 3 with x1 as the block index
+// (Sec. 4.1: dimensions 3 and 2 grouped first, dimension 1 last).
+//
+// For line (g, l) the window grid is x1 = 1..n times the x2-window of group l times the
+// x3-window of group g.  In eq. (3) the stretching s_d depends on x_d only, so the coupling
+// between x1-neighbour blocks is a multiple of the identity:
+//     K_{i,i-1} = l_i I,  l_i = s1_i s1_{i-1/2} / h^2,   K_{i,i+1} = u_i I,  u_i = s1_i s1_{i+1/2} / h^2,
+// and the block recursion S_1 = D_1, S_i = D_i - K_{i,i-1} S_{i-1}^{-1} K_{i-1,i} becomes the
+// scaled update S_i = D_i - (l_i u_{i-1}) T_{i-1}: the only dense work is inverting S_i.
+// D_i is the 5-point (x2, x3) operator of the window plus the x1 diagonal and kappa.
+//
+// One workgroup owns one line: it forms S_i in LDS, inverts it by Gauss-Jordan elimination
+// with partial pivoting (row interchanges inside the block only), stores T_i = S_i^{-1} and
+// reuses it for the next Schur update.  All ~G^2 lines are independent (Sec. 6 notes that
+// the setup is O(n^2) independent quasi-1D problems), so one launch covers them all.
+#include "common.h"
+
+namespace {
+
+constexpr int kMaxW = 64;
+constexpr int kMaxB = 64;
+constexpr int kSetupThreads = 256;
+
+struct SetupArgs {
+  int n, G, p;
+  double h;
+  const GroupInfo* groups;
+  const long long* line_off;
+  const double2* sbd;
+  const double2* smv;
+  const double* kappa;
+  void* factors;
+  int* err;
+};
+
+// s at half-step t of the window of group gi (the moving profile replaces the boundary one
+// strictly below the group's first node, groups other than the first)
+__device__ inline double2 window_s(const SetupArgs& a, const GroupInfo& gi, bool moving, int t) {
+  return (moving && t < 2 * gi.first) ? a.smv[t - 2 * (gi.first - a.p - 1)] : a.sbd[t];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
+  using C = typename cx<R>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double2 syn[kMaxW], syh[kMaxW + 1], szn[kMaxW], szh[kMaxW + 1];
+  __shared__ int perm[kMaxB], rho[kMaxB];
+  __shared__ C fcol[kMaxB];
+  __shared__ C pinv_s;
+  __shared__ int piv_s, bad_s;
+
+  const int line = blockIdx.x;
+  const int g = line / a.G, l = line % a.G;
+  const GroupInfo gz = a.groups[g], gy = a.groups[l];
+  const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
+  const int n = a.n;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  C* S = reinterpret_cast<C*>(smem_raw);
+  C* Tb = S + B * B;
+  C* out = reinterpret_cast<C*>(a.factors) + a.line_off[line];
+  const double ih2 = 1.0 / (a.h * a.h);
+
+  if (tid < Wy) syn[tid] = window_s(a, gy, l > 0, 2 * (gy.w0 + tid));
+  if (tid <= Wy) syh[tid] = window_s(a, gy, l > 0, 2 * (gy.w0 + tid) - 1);
+  if (tid < Wz) szn[tid] = window_s(a, gz, g > 0, 2 * (gz.w0 + tid));
+  if (tid <= Wz) szh[tid] = window_s(a, gz, g > 0, 2 * (gz.w0 + tid) - 1);
+  if (tid == 0) bad_s = 0;
+  __syncthreads();
+
+  for (int i = 0; i < n; ++i) {
+    const int m = i + 1;  // global x1 node of block i
+    const double2 sxn = a.sbd[2 * m], sxd = a.sbd[2 * m - 1], sxu = a.sbd[2 * m + 1];
+    const double2 dx = cscale(cmul(sxn, cadd(sxu, sxd)), -ih2);
+    // l_i * u_{i-1}: (s_m s_{m-1/2} / h^2) * (s_{m-1} s_{m-1/2} / h^2)
+    const double2 sc = (i > 0) ? cmul(cscale(cmul(sxn, sxd), ih2),
+                                      cscale(cmul(a.sbd[2 * m - 2], sxd), ih2))
+                               : make_double2(0.0, 0.0);
+    const C scR = cvt<C>(sc);
+    for (int e = tid; e < B * B; e += NT) {
+      const int r = e / B, c = e - r * B;
+      const int jr = r / Wz, kr = r - jr * Wz, jc = c / Wz, kc = c - jc * Wz;
+      double2 val = make_double2(0.0, 0.0);
+      if (r == c) {
+        const int k = gz.w0 + kr, j = gy.w0 + jr;
+        const double kap = a.kappa[((long long)(k - 1) * n + (j - 1)) * n + i];
+        double2 dy = cscale(cmul(syn[jr], cadd(syh[jr + 1], syh[jr])), -ih2);
+        double2 dz = cscale(cmul(szn[kr], cadd(szh[kr + 1], szh[kr])), -ih2);
+        val = cadd(cadd(dx, dy), dz);
+        val.x += kap;
+      } else if (jr == jc) {
+        if (kc == kr + 1) val = cscale(cmul(szn[kr], szh[kr + 1]), ih2);
+        else if (kc == kr - 1) val = cscale(cmul(szn[kr], szh[kr]), ih2);
+      } else if (kr == kc) {
+        if (jc == jr + 1) val = cscale(cmul(syn[jr], syh[jr + 1]), ih2);
+        else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
+      }
+      C v = cvt<C>(val);
+      if (i > 0) v = csub(v, cmul(scR, Tb[e]));
+      S[e] = v;
+    }
+    __syncthreads();
+
+    // ---- in-place Gauss-Jordan inversion with partial pivoting ----
+    for (int k = 0; k < B; ++k) {
+      if (tid < 64) {
+        R best = (R)-1;
+        int bi = B;
+        for (int r = k + tid; r < B; r += 64) {
+          R mg = cabs2(S[r * B + k]);
+          if (mg > best) { best = mg; bi = r; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          R ob = __shfl_xor(best, off);
+          int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (tid == 0) {
+          C pv = S[bi * B + k];
+          if (!(best > (R)0) || !isfinite(best)) { bad_s = 1; pv = mk((R)1, (R)0); }
+          piv_s = bi;
+          perm[k] = bi;
+          pinv_s = cinv(pv);
+        }
+      }
+      __syncthreads();
+      const int pr = piv_s;
+      if (pr != k) {
+        for (int c = tid; c < B; c += NT) {
+          C t = S[k * B + c];
+          S[k * B + c] = S[pr * B + c];
+          S[pr * B + c] = t;
+        }
+      }
+      __syncthreads();
+      const C pinv = pinv_s;
+      for (int c = tid; c < B; c += NT) S[k * B + c] = (c == k) ? pinv : cmul(S[k * B + c], pinv);
+      for (int r = tid; r < B; r += NT)
+        if (r != k) fcol[r] = S[r * B + k];
+      __syncthreads();
+      for (int e = tid; e < B * B; e += NT) {
+        const int r = e / B, c = e - r * B;
+        if (r == k) continue;
+        C old = (c == k) ? mk((R)0, (R)0) : S[e];
+        S[e] = csub(old, cmul(fcol[r], S[k * B + c]));
+      }
+      __syncthreads();
+    }
+    // column order of the inverse: (PS)^{-1} P = S^{-1}, i.e. T[r][rho(m)] = X[r][m]
+    if (tid == 0) {
+      for (int q = 0; q < B; ++q) rho[q] = q;
+      for (int k = 0; k < B; ++k) {
+        int t = rho[k];
+        rho[k] = rho[perm[k]];
+        rho[perm[k]] = t;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < B * B; e += NT) {
+      const int r = e / B, q = e - r * B;
+      Tb[r * B + rho[q]] = S[e];
+    }
+    __syncthreads();
+    C* dst = out + (long long)i * B * B;
+    for (int e = tid; e < B * B; e += NT) dst[e] = Tb[e];
+  }
+  if (tid == 0 && bad_s) {
+    atomicOr(&a.err[0], 1);
+    atomicExch(&a.err[1], line);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_setup(helm_handle* h, hipStream_t s) {
+  const Plan& P = h->plan;
+  SetupArgs a;
+  a.n = h->n;
+  a.G = P.G;
+  a.p = P.p;
+  a.h = h->h;
+  a.groups = h->d_groups;
+  a.line_off = h->d_line_off;
+  a.sbd = h->sbd;
+  a.smv = h->smv;
+  a.kappa = h->kappa;
+  a.factors = h->factors;
+  a.err = h->d_err;
+  const unsigned lines = (unsigned)(P.G * P.G);
+  if (h->prec == HELM_C64) {
+    size_t sm = 2 * (size_t)P.maxB * P.maxB * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    k_line_setup<float><<<lines, kSetupThreads, sm, s>>>(a);
+  } else {
+    size_t sm = 2 * (size_t)P.maxB * P.maxB * sizeof(double2);
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    k_line_setup<double><<<lines, kSetupThreads, sm, s>>>(a);
+  }
+  return hipGetLastError();
+}
