@@ -177,6 +177,28 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
  */
 int helm_set_launch(helm_handle* h, int lanes_per_row);
 
+/*
+ * Device-time statistics of one handle, from HIP events recorded on the launch stream around
+ * every sweep (helm_apply / helm_apply_adjoint / inside helm_solve) and every matvec launch.
+ */
+typedef struct {
+  double setup_ms;             /* device time of the last setup (coefficients + factors)      */
+  long long apply_launches;    /* sweep launches since the last reset                          */
+  long long apply_rhs;         /* right-hand sides those launches processed                    */
+  double apply_ms;             /* summed device time of those launches                         */
+  double apply_bytes_per_rhs;  /* algorithmic bytes of one sweep of one right-hand side:      */
+                               /* every block visit reads B*B factor entries, plus the input  */
+                               /* vector read and the output vector written once              */
+  long long matvec_launches;   /* 7-point operator launches since the last reset             */
+  long long matvec_rhs;
+  double matvec_ms;
+  double matvec_bytes_per_rhs; /* 40 bytes per grid point (u, kappa read; y written)          */
+} helm_stats;
+
+/* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */
+int helm_get_stats(helm_handle* h, helm_stats* out);
+int helm_reset_stats(helm_handle* h);
+
 /* helm_destroy -- free the handle and everything it owns (NULL is ignored). */
 void helm_destroy(helm_handle* h);
 

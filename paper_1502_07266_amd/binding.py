@@ -24,6 +24,14 @@ class helm_pml(ctypes.Structure):
     _fields_ = [("b", ctypes.c_int), ("C", ctypes.c_double), ("p", ctypes.c_int)]
 
 
+class helm_stats(ctypes.Structure):
+    _fields_ = [("setup_ms", ctypes.c_double), ("apply_launches", ctypes.c_longlong),
+                ("apply_rhs", ctypes.c_longlong), ("apply_ms", ctypes.c_double),
+                ("apply_bytes_per_rhs", ctypes.c_double), ("matvec_launches", ctypes.c_longlong),
+                ("matvec_rhs", ctypes.c_longlong), ("matvec_ms", ctypes.c_double),
+                ("matvec_bytes_per_rhs", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -43,6 +51,8 @@ _SIGS = {
     "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), _P]),
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
+    "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
+    "helm_reset_stats": (_I, [_P]),
     "helm_destroy": (None, [_P]),
     "helm_error_string": (ctypes.c_char_p, [_I]),
     "helm_last_error": (ctypes.c_char_p, []),
@@ -221,6 +231,14 @@ class Helm:
         _check(lib().helm_line_solve(self.handle, zg, yg, _ptr(r), _ptr(x), r.shape[0], int(adjoint),
                                      _stream()), "helm_line_solve")
         return x
+
+    def stats(self):
+        st = helm_stats()
+        _check(lib().helm_get_stats(self.handle, ctypes.byref(st)), "helm_get_stats")
+        return {f: getattr(st, f) for f, _ in helm_stats._fields_}
+
+    def reset_stats(self):
+        _check(lib().helm_reset_stats(self.handle), "helm_reset_stats")
 
     def set_launch(self, lanes_per_row):
         _check(lib().helm_set_launch(self.handle, int(lanes_per_row)), "helm_set_launch")

@@ -12,6 +12,7 @@ thread_local std::string g_last_error;
 
 constexpr int kBlockLimit = 64;          // largest block B the sweep and setup kernels take
 constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
+constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -29,19 +30,38 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   if (rc != HELM_OK) return fail(rc, msg);
   if (plan.maxB > kBlockLimit)
     return fail(HELM_EINVAL, "block size (b or p+d per axis, squared) exceeds 64");
-  const size_t lds = ((size_t)plan.n * plan.maxB + 2 * (plan.n + 2)) * csize(prec);
+  const size_t lds = ((size_t)plan.n * plan.maxB + 128 + 2 * (plan.n + 2)) * csize(prec);
   if (lds > kLdsBytes) return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
   return HELM_OK;
 }
 
 size_t planned_bytes(const Plan& p, int prec) {
   const size_t N = (size_t)p.n * p.n * p.n;
-  return (size_t)p.total_elems * csize(prec) + N * sizeof(double) +
+  return ((size_t)p.total_elems + kFactorPad) * csize(prec) + N * sizeof(double) +
          (size_t)(2 * (p.n + 1) + 1 + 2 * p.p + 2 + 5 * (p.n + 2)) * sizeof(double2) +
          (size_t)p.G * sizeof(GroupInfo) + (size_t)p.G * p.G * sizeof(long long);
 }
 
+// algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
+// inner pass it takes part in (twice unless l is the last x2-group) and once per outer pass
+// (twice unless g is the last x3-group); each solve visits its n blocks twice (forward and
+// backward substitution) and reads B*B entries per visit; plus the input (complex128) read
+// and the output written once.
+double sweep_bytes_per_rhs(const Plan& p, int prec) {
+  double acc = 0.0;
+  for (int g = 0; g < p.G; ++g)
+    for (int l = 0; l < p.G; ++l) {
+      const double mult = (g < p.G - 1 ? 2.0 : 1.0) * (l < p.G - 1 ? 2.0 : 1.0);
+      const double B = p.line_B[(size_t)g * p.G + l];
+      acc += mult * 2.0 * p.n * B * B;
+    }
+  const double N = (double)p.n * p.n * p.n;
+  return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
+}
+
 void release(helm_handle* h) {
+  h->t_apply.reset();
+  h->t_matvec.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
                   h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
   for (void* p : ptrs)
@@ -120,14 +140,21 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   ALLOC(h->diag, (size_t)(plan.n + 2) * sizeof(double2));
   ALLOC(h->d_groups, (size_t)plan.G * sizeof(GroupInfo));
   ALLOC(h->d_line_off, (size_t)plan.G * plan.G * sizeof(long long));
-  ALLOC(h->factors, (size_t)plan.total_elems * csize(prec));
+  // the sweep's row-major block walk may read up to 64 entries past the last block
+  ALLOC(h->factors, ((size_t)plan.total_elems + kFactorPad) * csize(prec));
   ALLOC(h->d_err, 2 * sizeof(int));
 #undef ALLOC
+  if (hipMemsetAsync((char*)h->factors + (size_t)plan.total_elems * csize(prec), 0,
+                     kFactorPad * csize(prec), s) != hipSuccess)
+    return bail(HELM_EHIP, "clearing the factor padding failed");
   if (hipMemcpyAsync(h->d_groups, plan.groups.data(), plan.G * sizeof(GroupInfo),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(h->d_line_off, plan.line_off.data(), plan.line_off.size() * sizeof(long long),
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return bail(HELM_EHIP, "copying the plan failed");
+  h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
+  LaunchTimer t_setup;
+  hipEvent_t ev = t_setup.begin(s);
   if (launch_coefficients(h, c_dev, true, s) != hipSuccess) return bail(HELM_EHIP, "coefficient kernels failed");
   int err[2] = {0, 0};
   if (hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -136,9 +163,12 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   if (err[0]) return bail(HELM_EINVAL, "c must be finite and > 0 at every node");
   hipError_t e = launch_setup(h, s);
   if (e != hipSuccess) return bail(HELM_EHIP, std::string("setup kernel: ") + hipGetErrorString(e));
+  t_setup.end(ev, s, 1);
   if (hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return bail(HELM_EHIP, "setup kernel failed");
+  t_setup.flush();
+  h->setup_ms = t_setup.ms;
   if (err[0]) return bail(HELM_ESINGULAR, "singular block in line " + std::to_string(err[1]));
   *out = h;
   return HELM_OK;
@@ -269,6 +299,29 @@ int helm_set_launch(helm_handle* h, int lanes_per_row) {
   if (lanes_per_row != 0 && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
     return fail(HELM_EINVAL, "lanes_per_row must be 0, 4, 8 or 16");
   h->lanes_override = lanes_per_row;
+  return HELM_OK;
+}
+
+int helm_get_stats(helm_handle* h, helm_stats* out) {
+  if (!h || !out) return fail(HELM_EINVAL, "handle and out must not be NULL");
+  h->t_apply.flush();
+  h->t_matvec.flush();
+  out->setup_ms = h->setup_ms;
+  out->apply_launches = h->t_apply.launches;
+  out->apply_rhs = h->t_apply.rhs;
+  out->apply_ms = h->t_apply.ms;
+  out->apply_bytes_per_rhs = h->apply_bytes_per_rhs;
+  out->matvec_launches = h->t_matvec.launches;
+  out->matvec_rhs = h->t_matvec.rhs;
+  out->matvec_ms = h->t_matvec.ms;
+  out->matvec_bytes_per_rhs = 40.0 * h->n * h->n * h->n;
+  return HELM_OK;
+}
+
+int helm_reset_stats(helm_handle* h) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  h->t_apply.reset();
+  h->t_matvec.reset();
   return HELM_OK;
 }
 

@@ -75,6 +75,57 @@ struct Plan {
 int build_plan(int n, int b, int p, int d, Plan& plan, std::string& msg);
 
 // ---------------------------------------------------------------------------------------
+// device-time accounting: event pairs recorded around launches, resolved lazily
+// ---------------------------------------------------------------------------------------
+struct LaunchTimer {
+  struct Pending {
+    hipEvent_t a, b;
+    long long rhs;
+  };
+  std::vector<Pending> pending;
+  long long launches = 0, rhs = 0;
+  double ms = 0.0;
+  // records the start event; returns it for end()
+  hipEvent_t begin(hipStream_t s) {
+    hipEvent_t a = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return nullptr;
+    if (hipEventRecord(a, s) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return nullptr;
+    }
+    return a;
+  }
+  void end(hipEvent_t a, hipStream_t s, long long nrhs) {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+      return;
+    }
+    pending.push_back({a, b, nrhs});
+  }
+  void flush() {
+    for (auto& p : pending) {
+      float t = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        ms += t;
+        launches += 1;
+        rhs += p.rhs;
+      }
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    flush();
+    launches = rhs = 0;
+    ms = 0.0;
+  }
+};
+
+// ---------------------------------------------------------------------------------------
 // the opaque handle
 // ---------------------------------------------------------------------------------------
 struct helm_handle {
@@ -93,6 +144,11 @@ struct helm_handle {
   long long* d_line_off = nullptr; // [G*G]
   void* factors = nullptr;         // total_elems complex64 or complex128
   int* d_err = nullptr;            // [2]: error flag, first failing line
+
+  // timing
+  LaunchTimer t_apply, t_matvec;
+  double setup_ms = 0.0;
+  double apply_bytes_per_rhs = 0.0;
 
   // apply workspace (grown on demand)
   void* slab_scratch = nullptr;

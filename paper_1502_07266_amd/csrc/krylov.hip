@@ -14,6 +14,8 @@
 // estimates per iteration to decide.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -294,6 +296,7 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
 
   const long long Vr = (long long)(m + 1) * N, Zr = (long long)m * N;
   int status = HELM_OK;
+  const bool verbose = std::getenv("HELM_VERBOSE") != nullptr;
   while (true) {
     // ---- true residual of every unfinished right-hand side ----
     std::vector<int> cyc;
@@ -359,12 +362,17 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
       HIP_MSG(hipMemcpyAsync(rr.data(), ws.resid, R * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_MSG(hipStreamSynchronize(s));
       std::vector<int> keep;
+      double worst = 0.0;
       for (int q : act) {
         its[q] += 1;
         kq[q] = j + 1;
         res[q] = fn[q] > 0 ? rr[q] / fn[q] : 0.0;
+        worst = std::max(worst, res[q]);
         if (rr[q] > tol * fn[q] && its[q] < maxit) keep.push_back(q);
       }
+      if (verbose)
+        std::fprintf(stderr, "[helm fgmres] iteration %d: %zu active, worst estimate %.3e\n",
+                     j + 1, act.size(), worst);
       if (keep.size() != act.size()) {
         act = keep;
         if (!act.empty()) HIP_MSG(upload(act));

@@ -120,6 +120,7 @@ hipError_t launch_matvec(helm_handle* h, const void* u, bool u64, const double2*
   const int n = h->n;
   const long long N = (long long)n * n * n;
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)R);
+  hipEvent_t ev = h->t_matvec.begin(s);
   if (u64) {
     if (adjoint)
       k_matvec<double2, true><<<grid, 256, 0, s>>>((const double2*)u, u_stride, f, y, y_stride,
@@ -135,7 +136,9 @@ hipError_t launch_matvec(helm_handle* h, const void* u, bool u64, const double2*
       k_matvec<float2, false><<<grid, 256, 0, s>>>((const float2*)u, u_stride, f, y, y_stride,
                                                    h->kappa, h->coef, h->diag, n, rhs_idx, mode);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  h->t_matvec.end(ev, s, R);
+  return e;
 }
 
 hipError_t launch_grad(helm_handle* h, const double2* u, const double2* lam, int R, double* grad,

@@ -15,16 +15,20 @@
 //       line solve: y_i = T_i (q_i - l_i y_{i-1}),  x_i = y_i - u_i T_i x_{i+1}
 // where v is the slab iterate (n x n x window layers, in global scratch), the line vector
 // (n blocks of B = Wy*Wz) lives in LDS, and the T_i stream from HBM.  The adjoint uses the
-// couplings of A^H and T_i^H (see the oracle's derivation: the same pass order).
+// couplings of A^H and T_i^H (the same pass order).
 //
-// Block step mapping: thread t owns output row t / NC of the B x B block and a chunk of
-// ceil(B/NC) columns; the NC partial sums of a row sit in adjacent lanes of one wavefront
-// and are combined with cross-lane exchanges.  One barrier per block step.
+// Block step: thread t owns output row t / NC of the B x B block and CW consecutive columns;
+// the NC partial sums of a row are adjacent lanes of one wavefront and are combined with DPP
+// row operations.  The vector a step multiplies (z_i = q_i - l_i y_{i-1} forward, x_{i+1}
+// backward) is formed once per row by the row's owner lane and published through a
+// double-buffered LDS slot, so one barrier separates consecutive steps.  The factor blocks do
+// not depend on the data: each thread keeps its slice of the next D blocks in registers
+// (a ring refilled D steps ahead), which hides the HBM latency behind D dependent steps.
 #include "common.h"
 
 namespace {
 
-constexpr int kBMax = 64;
+constexpr int kZMax = 64;   // largest NC * CW of the instantiated shapes
 
 struct SweepArgs {
   int n, G, maxW, maxB;
@@ -39,111 +43,206 @@ struct SweepArgs {
   void* scratch;
 };
 
-template <int NC, typename C> __device__ inline C reduce_lanes(C a) {
-#pragma unroll
-  for (int off = NC / 2; off > 0; off >>= 1) {
-    a.x += __shfl_xor(a.x, off);
-    a.y += __shfl_xor(a.y, off);
-  }
-  return a;
+// sum over groups of NC adjacent lanes (NC in {4, 8, 16}), result in every lane of the group
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int NC, typename T> __device__ __forceinline__ T lane_sum(T v) {
+  static_assert(NC == 4 || NC == 8 || NC == 16, "lanes per row must be 4, 8 or 16");
+  v += dpp_mov<0xB1>(v);                             // quad_perm [1,0,3,2]: pairs
+  v += dpp_mov<0x4E>(v);                             // quad_perm [2,3,0,1]: quads
+  if constexpr (NC >= 8) v += dpp_mov<0x141>(v);     // row_half_mirror: the other quad of 8
+  if constexpr (NC == 16) v += dpp_mov<0x140>(v);    // row_mirror: the other 8 of each 16
+  return v;
 }
 
-// Exact solve of one line problem through its block LDU factors.  On entry ybuf[i*B + q]
-// holds the right-hand side block i; on exit it holds the solution.  `emit(i, q, x)` is
-// called once per solution entry (by the thread owning row q) as soon as x is final.
-// cf[m], cb[m] are the x1 couplings of row m (m = i+1) towards m-1 and m+1.
-template <typename R, int NC, bool ADJ, typename Emit>
-__device__ inline void line_solve(const typename cx<R>::type* __restrict__ T, const int B,
-                                  const int n, typename cx<R>::type* ybuf,
-                                  const typename cx<R>::type* cf, const typename cx<R>::type* cb,
-                                  Emit emit) {
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, then
+// s_barrier.  Unlike __syncthreads() it does not wait for outstanding global loads, so the
+// factor ring stays in flight across block steps.  Global scratch written around a line
+// solve is published with full __syncthreads() by the caller.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename R, int NC, int CW, int D, bool ADJ>
+struct LineSolver {
   using C = typename cx<R>::type;
-  constexpr int CWMAX = kBMax / NC;
-  const int tid = threadIdx.x;
-  const int row = tid / NC, lc = tid - row * NC;
-  const int CW = (B + NC - 1) / NC;
-  const int c0 = lc * CW;
-  const bool act = row < B;
-  const long long BB = (long long)B * B;
-  C tcur[CWMAX], tnxt[CWMAX], qcur[CWMAX], qnxt[CWMAX];
-  const C zero = mk((R)0, (R)0);
+  static constexpr int ZS = NC * CW;   // stride of one published vector (>= B, zero-padded)
+  static constexpr int NA = CW < 3 ? CW : 3;   // independent accumulators in a block row
+  C ring[D][CW];
+  unsigned off[CW];                    // this thread's byte offsets inside a B x B block
+  int row, c0;
+  bool owner_lane;
 
-  // ---- forward: y_i = T_i (q_i - cf_i y_{i-1}) ----
-#define HELM_LOAD_T(blk, dst)                                                        \
-  _Pragma("unroll") for (int cc = 0; cc < CWMAX; ++cc) {                             \
-    const int col = c0 + cc;                                                         \
-    dst[cc] = (act && cc < CW && col < B) ? (ADJ ? (blk)[col * B + row] : (blk)[row * B + col]) \
-                                          : zero;                                    \
+  __device__ __forceinline__ LineSolver() {
+    row = threadIdx.x / NC;
+    const int lc = threadIdx.x - row * NC;
+    c0 = lc * CW;
+    owner_lane = lc == 0;
   }
-#define HELM_LOAD_Q(i, dst)                                                          \
-  _Pragma("unroll") for (int cc = 0; cc < CWMAX; ++cc) {                             \
-    const int col = c0 + cc;                                                         \
-    dst[cc] = (cc < CW && col < B) ? ybuf[(i) * B + col] : zero;                     \
-  }
-  HELM_LOAD_T(T, tcur);
-  HELM_LOAD_Q(0, qcur);
-  for (int i = 0; i < n; ++i) {
-    if (i + 1 < n) {
-      HELM_LOAD_T(T + (i + 1) * BB, tnxt);
-      HELM_LOAD_Q(i + 1, qnxt);
-    }
-    const C cfi = cf[i + 1];
-    C acc = zero;
+
+  // per-line offsets; rows past B are clamped to a valid row (their sums are never
+  // published).  Columns past B meet zero padding of the published vector: in the row-major
+  // (non-adjoint) walk they run into the next row, or past the last block into the padding
+  // that follows the factor array, so they read finite values; the adjoint walk clamps them.
+  __device__ __forceinline__ void begin_line(int B) {
+    const int r = row < B ? row : B - 1;
 #pragma unroll
-    for (int cc = 0; cc < CWMAX; ++cc) {
-      const int col = c0 + cc;
-      if (cc < CW && col < B) {
-        C z = qcur[cc];
-        if (i > 0) z = csub(z, cmul(cfi, ybuf[(i - 1) * B + col]));
-        acc = ADJ ? cfma_conj(acc, tcur[cc], z) : cfma(acc, tcur[cc], z);
-      }
-    }
-    acc = reduce_lanes<NC>(acc);
-    if (lc == 0 && act) ybuf[i * B + row] = acc;
-    __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < CWMAX; ++cc) {
-      tcur[cc] = tnxt[cc];
-      qcur[cc] = qnxt[cc];
+    for (int cc = 0; cc < CW; ++cc) {
+      const int col = (ADJ && c0 + cc >= B) ? B - 1 : c0 + cc;
+      off[cc] = (unsigned)(ADJ ? col * B + r : r * B + col) * (unsigned)sizeof(C);
     }
   }
-  // ---- backward: x_{n-1} = y_{n-1};  x_i = y_i - cb_i T_i x_{i+1} ----
-  if (lc == 0 && act) emit(n - 1, row, ybuf[(n - 1) * B + row]);
-  if (n >= 2) { HELM_LOAD_T(T + (n - 2) * BB, tcur); }
-  for (int i = n - 2; i >= 0; --i) {
-    if (i > 0) { HELM_LOAD_T(T + (i - 1) * BB, tnxt); }
-    const C cbi = cb[i + 1];
-    C acc = zero;
+
+  // slot S <- this thread's slice of the block at element offset blk_off of the line T.  The
+  // byte offset is formed in 32 bits (a line's factors are far below 4 GiB) on a uniform base,
+  // which maps to scalar-base + 32-bit vector-offset addressing.
+  template <int S> __device__ __forceinline__ void load(const C* __restrict__ T, unsigned blk_off) {
+    const char* base = reinterpret_cast<const char*>(T);
+    const unsigned b0 = blk_off * (unsigned)sizeof(C);
+    if constexpr (ADJ) {
 #pragma unroll
-    for (int cc = 0; cc < CWMAX; ++cc) {
-      const int col = c0 + cc;
-      if (cc < CW && col < B) {
-        const C xv = ybuf[(i + 1) * B + col];
-        acc = ADJ ? cfma_conj(acc, tcur[cc], xv) : cfma(acc, tcur[cc], xv);
-      }
+      for (int cc = 0; cc < CW; ++cc)
+        ring[S][cc] = *reinterpret_cast<const C*>(base + (b0 + off[cc]));
+    } else {
+      const C* p = reinterpret_cast<const C*>(base + (b0 + off[0]));   // contiguous columns
+#pragma unroll
+      for (int cc = 0; cc < CW; ++cc) ring[S][cc] = p[cc];
     }
-    acc = reduce_lanes<NC>(acc);
-    if (lc == 0 && act) {
-      const C x = csub(ybuf[i * B + row], cmul(cbi, acc));
+  }
+
+  // Ring refills are unconditional: past either end of the line the block index is clamped
+  // (a re-read of a block of the same line, never used), which keeps the load stream free of
+  // branches so the wait counts before each use stay exact.
+  template <int S = 0> __device__ __forceinline__ void fill_forward(const C* T, int B, int n) {
+    if constexpr (S < D) {
+      load<S>(T, (unsigned)((S < n ? S : n - 1) * B * B));
+      fill_forward<S + 1>(T, B, n);
+    }
+  }
+  template <int S = 0> __device__ __forceinline__ void fill_backward(const C* T, int B, int n) {
+    if constexpr (S < D) {
+      load<S>(T, (unsigned)((n - 2 - S >= 0 ? n - 2 - S : 0) * B * B));
+      fill_backward<S + 1>(T, B, n);
+    }
+  }
+
+  // row sum of ring[S] . z over this thread's columns, reduced over the row's NC lanes
+  template <int S> __device__ __forceinline__ C dot(const C* z) const {
+    C zr[CW];
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc) zr[cc] = z[c0 + cc];
+    C acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = mk((R)0, (R)0);
+#pragma unroll
+    for (int cc = 0; cc < CW; ++cc)
+      acc[cc % NA] = ADJ ? cfma_conj(acc[cc % NA], ring[S][cc], zr[cc])
+                         : cfma(acc[cc % NA], ring[S][cc], zr[cc]);
+#pragma unroll
+    for (int a = 1; a < NA; ++a) acc[0] = cadd(acc[0], acc[a]);
+    acc[0].x = lane_sum<NC>(acc[0].x);
+    acc[0].y = lane_sum<NC>(acc[0].y);
+    return acc[0];
+  }
+
+  // Forward step i with ring slot S: y_i = T_i z_i, z_{i+1} = q_{i+1} - l_{i+1} y_i; refills
+  // the slot with block i + D.  The owner's operands are read before the reduction.
+  template <int S> __device__ __forceinline__ void fwd_step(int i, const C* T, int B, int BB, int n,
+                                                            C* ybuf, C* zb, const C* cf) {
+    const bool own = owner_lane && row < B;
+    const int inext = i + 1 < n ? i + 1 : i;
+    C qn = mk((R)0, (R)0), cn = mk((R)0, (R)0);
+    if (own) {
+      qn = ybuf[inext * B + row];
+      cn = cf[inext + 1];
+    }
+    const C acc = dot<S>(zb + (i & 1) * ZS);
+    load<S>(T, (unsigned)((i + D < n ? i + D : n - 1) * BB));
+    if (own) {
+      ybuf[i * B + row] = acc;
+      zb[((i + 1) & 1) * ZS + row] = csub(qn, cmul(cn, acc));
+    }
+    lds_barrier();
+  }
+
+  // Backward step i: x_i = y_i - u_i T_i x_{i+1}; refills the slot with block i - D.
+  template <int S>
+  __device__ __forceinline__ void bwd_step(int i, const C* T, int B, int BB, C* ybuf, C* zb,
+                                           const C* cb) {
+    const bool own = owner_lane && row < B;
+    C yi = mk((R)0, (R)0), ci = mk((R)0, (R)0);
+    if (own) {
+      yi = ybuf[i * B + row];
+      ci = cb[i + 1];
+    }
+    const C acc = dot<S>(zb + ((i + 1) & 1) * ZS);
+    load<S>(T, (unsigned)((i - D >= 0 ? i - D : 0) * BB));
+    if (own) {
+      const C x = csub(yi, cmul(ci, acc));
       ybuf[i * B + row] = x;
-      emit(i, row, x);
+      zb[(i & 1) * ZS + row] = x;
     }
-    __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < CWMAX; ++cc) tcur[cc] = tnxt[cc];
+    lds_barrier();
   }
-#undef HELM_LOAD_T
-#undef HELM_LOAD_Q
-}
 
-template <typename R, typename TI, typename TO, int NC, bool ADJ>
-__global__ void __launch_bounds__(kBMax * NC) k_sweep(SweepArgs a) {
+  template <int S = 0> __device__ __forceinline__ void fwd_group(int i0, const C* T, int B, int BB,
+                                                                 int n, C* ybuf, C* zb, const C* cf) {
+    if constexpr (S < D) {
+      if (i0 + S < n) {
+        fwd_step<S>(i0 + S, T, B, BB, n, ybuf, zb, cf);
+        fwd_group<S + 1>(i0, T, B, BB, n, ybuf, zb, cf);
+      }
+    }
+  }
+  template <int S = 0>
+  __device__ __forceinline__ void bwd_group(int i0, const C* T, int B, int BB, C* ybuf, C* zb,
+                                            const C* cb) {
+    if constexpr (S < D) {
+      if (i0 - S >= 0) {
+        bwd_step<S>(i0 - S, T, B, BB, ybuf, zb, cb);
+        bwd_group<S + 1>(i0, T, B, BB, ybuf, zb, cb);
+      }
+    }
+  }
+
+  // Solve with the factors T (n blocks) on the right-hand side in ybuf[i*B + q]; begin_line(B)
+  // and fill_forward must have run, and ybuf must be complete (barrier).  zb holds 2 * ZS
+  // values.  On return ybuf holds the solution (visible to the whole workgroup).  No global
+  // memory is touched besides the factor stream, so the wait before each ring slot is exact.
+  __device__ __forceinline__ void run(const C* T, int B, int n, C* ybuf, C* zb, const C* cf,
+                                      const C* cb) {
+    const int BB = B * B;
+    for (int e = threadIdx.x; e < 2 * ZS; e += blockDim.x) {
+      const int q = e < ZS ? e : e - ZS;
+      if (q >= B) zb[e] = mk((R)0, (R)0);
+    }
+    if (owner_lane && row < B) zb[row] = ybuf[row];             // z_0 = q_0
+    lds_barrier();
+    for (int i0 = 0; i0 < n; i0 += D)
+      fwd_group(__builtin_amdgcn_readfirstlane(i0), T, B, BB, n, ybuf, zb, cf);
+    fill_backward(T, B, n);
+    if (owner_lane && row < B) zb[((n - 1) & 1) * ZS + row] = ybuf[(n - 1) * B + row];  // x_{n-1} = y_{n-1}
+    lds_barrier();
+    for (int i0 = n - 2; i0 >= 0; i0 -= D)
+      bwd_group(__builtin_amdgcn_readfirstlane(i0), T, B, BB, ybuf, zb, cb);
+  }
+};
+
+template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ>
+__global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepArgs a) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, G = a.G;
   C* ybuf = reinterpret_cast<C*>(smem_raw);
-  C* cf = ybuf + (size_t)n * a.maxB;  // A'[m, m-1], m = 0..n+1
-  C* cb = cf + (n + 2);               // A'[m, m+1]
+  C* zb = ybuf + (size_t)n * a.maxB;    // [2][NC*CW], zero-padded past B
+  C* cf = zb + 2 * kZMax;               // A'[m, m-1], m = 0..n+1
+  C* cb = cf + (n + 2);                 // A'[m, m+1]
   const int tid = threadIdx.x, NT = blockDim.x;
   const int q = a.rhs_idx ? a.rhs_idx[blockIdx.x] : (int)blockIdx.x;
   const TI* __restrict__ f = reinterpret_cast<const TI*>(a.in) + (long long)q * a.in_stride;
@@ -158,6 +257,7 @@ __global__ void __launch_bounds__(kBMax * NC) k_sweep(SweepArgs a) {
   auto gidx = [&](int i, int j, int k) -> long long {  // i 0-based, j, k 1-based
     return ((long long)(k - 1) * n + (j - 1)) * n + i;
   };
+  LineSolver<R, NC, CW, D, ADJ> ls;
 
   for (int pass = 0; pass < 2; ++pass) {
     const bool ofwd = pass == 0;
@@ -170,7 +270,9 @@ __global__ void __launch_bounds__(kBMax * NC) k_sweep(SweepArgs a) {
         const int l = ifwd ? lp : 2 * G - 2 - lp;
         const GroupInfo gy = a.groups[l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
-        // ---- line input ----
+        const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
+        ls.begin_line(B);
+        ls.fill_forward(T, B, n);   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
           const int jj = qq / Wz, kk = qq - jj * Wz;
@@ -194,15 +296,16 @@ __global__ void __launch_bounds__(kBMax * NC) k_sweep(SweepArgs a) {
           ybuf[i * B + qq] = val;
         }
         __syncthreads();
-        const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-        line_solve<R, NC, ADJ>(T, B, n, ybuf, cf, cb, [&](int i, int qq, C x) {
-          const int jj = qq / Wz, kk = qq - jj * Wz;
-          const int j = yw0 + jj;
-          if (j >= j0) {
-            C* p = v + ((long long)kk * n + (j - 1)) * n + i;
-            *p = ifwd ? x : csub(*p, x);
-          }
-        });
+        ls.run(T, B, n, ybuf, zb, cf, cb);
+        // ---- line output on the group's rows: v = x (inner forward) or v -= x (backward) ----
+        const int npy = j1 - j0 + 1;
+        for (int e = tid; e < n * Wz * npy; e += NT) {
+          const int i = e % n, kk = (e / n) % Wz, jp = e / (n * Wz);
+          const int qq = (Wy - npy + jp) * Wz + kk;
+          C* p = v + ((long long)kk * n + (j0 + jp - 1)) * n + i;
+          *p = ifwd ? ybuf[i * B + qq] : csub(*p, ybuf[i * B + qq]);
+        }
+        __syncthreads();
       }
       // ---- slab output on the group's layers ----
       const int nph = k1 - k0 + 1;
@@ -218,14 +321,15 @@ __global__ void __launch_bounds__(kBMax * NC) k_sweep(SweepArgs a) {
   }
 }
 
-// Exact solve of a single line problem on its own grid (for testing the building block).
-template <typename R, int NC, bool ADJ>
-__global__ void __launch_bounds__(kBMax * NC) k_line_solve(SweepArgs a, int g, int l) {
+// Exact solve of a single line problem on its own grid (exposes the building block).
+template <typename R, int NC, int CW, int D, bool ADJ>
+__global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_line_solve(SweepArgs a, int g, int l) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, G = a.G;
   C* ybuf = reinterpret_cast<C*>(smem_raw);
-  C* cf = ybuf + (size_t)n * a.maxB;
+  C* zb = ybuf + (size_t)n * a.maxB;
+  C* cf = zb + 2 * kZMax;
   C* cb = cf + (n + 2);
   const int tid = threadIdx.x, NT = blockDim.x;
   for (int m = tid; m < n + 2; m += NT) {
@@ -235,43 +339,83 @@ __global__ void __launch_bounds__(kBMax * NC) k_line_solve(SweepArgs a, int g, i
   const int Wz = a.groups[g].W, Wy = a.groups[l].W, B = Wy * Wz;
   const double2* r = reinterpret_cast<const double2*>(a.in) + (long long)blockIdx.x * n * B;
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
+  const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
+  LineSolver<R, NC, CW, D, ADJ> ls;
+  ls.begin_line(B);
+  ls.fill_forward(T, B, n);
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
     ybuf[i * B + jj * Wz + kk] = cvt<C>(r[e]);
   }
   __syncthreads();
-  const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-  line_solve<R, NC, ADJ>(T, B, n, ybuf, cf, cb, [&](int i, int qq, C val) {
-    const int jj = qq / Wz, kk = qq - jj * Wz;
-    x[i + (long long)n * (jj + (long long)Wy * kk)] = cvt<double2>(val);
-  });
-}
-
-// threads per workgroup: NC lanes for each of the maxB block rows, whole wavefronts
-inline int block_threads(int maxB, int nc) { return ((maxB * nc + 63) / 64) * 64; }
-
-template <typename K>
-hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, SweepArgs a) {
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)sm);
-  if (e != hipSuccess) return e;
-  kern<<<grid, threads, sm, s>>>(a);
-  return hipGetLastError();
-}
-
-template <typename R, typename TI, typename TO, bool ADJ>
-hipError_t dispatch_nc(int nc, int maxB, int grid, size_t sm, hipStream_t s, SweepArgs a) {
-  const int t = block_threads(maxB, nc);
-  switch (nc) {
-    case 4: return launch_k(k_sweep<R, TI, TO, 4, ADJ>, grid, t, sm, s, a);
-    case 16: return launch_k(k_sweep<R, TI, TO, 16, ADJ>, grid, t, sm, s, a);
-    default: return launch_k(k_sweep<R, TI, TO, 8, ADJ>, grid, t, sm, s, a);
+  ls.run(T, B, n, ybuf, zb, cf, cb);
+  for (int e = tid; e < n * B; e += NT) {
+    const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
+    x[e] = cvt<double2>(ybuf[i * B + jj * Wz + kk]);
   }
 }
 
-int auto_lanes(const helm_handle* h) {
-  if (h->lanes_override) return h->lanes_override;
-  return h->prec == HELM_C64 ? 8 : 8;
+// ------------------------------------------------------------------------------------------
+// launch shapes: NC lanes per block row, CW columns per lane (NC * CW >= B), ring depth D
+// (registers: D * CW complex values per thread)
+// ------------------------------------------------------------------------------------------
+struct Shape {
+  int nc, cw;
+};
+
+Shape choose_shape(int maxB, int lanes) {
+  // default: 16 lanes per block row up to B = 48 (measured fastest at B = 36 in both
+  // precisions), 4 lanes beyond (16 x 4 columns would not fit the register budget); CW is
+  // the smallest instantiated column count covering B
+  const int nc = lanes ? lanes : (maxB <= 48 ? 16 : 4);
+  const int need = (maxB + nc - 1) / nc;
+  static const int cw4[] = {4, 7, 9, 13, 16}, cw8[] = {4, 8}, cw16[] = {1, 2, 3, 4};
+  const int* t = nc == 4 ? cw4 : (nc == 8 ? cw8 : cw16);
+  const int cnt = nc == 4 ? 5 : (nc == 8 ? 2 : 4);
+  for (int k = 0; k < cnt; ++k)
+    if (t[k] >= need) return {nc, t[k]};
+  return {nc, -1};
+}
+
+inline int block_threads(int maxB, int nc) { return ((maxB * nc + 63) / 64) * 64; }
+
+template <typename K, typename... Args>
+hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Args... args) {
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sm);
+  if (e != hipSuccess) return e;
+  kern<<<grid, threads, sm, s>>>(args...);
+  return hipGetLastError();
+}
+
+// the instantiated shapes: (NC, CW, ring depth for complex64, ring depth for complex128)
+#define HELM_SHAPES(X)                                                             \
+  X(4, 4, 16, 12) X(4, 7, 10, 6) X(4, 9, 8, 4) X(4, 13, 5, 3) X(4, 16, 4, 2)       \
+  X(8, 4, 12, 6) X(8, 8, 6, 4) X(16, 1, 16, 16) X(16, 2, 16, 12) X(16, 3, 12, 6)
+
+template <typename R, typename TI, typename TO, bool ADJ>
+hipError_t dispatch_sweep(Shape sh, int maxB, int grid, size_t sm, hipStream_t s, SweepArgs a) {
+  const int t = block_threads(maxB, sh.nc);
+  constexpr bool c64 = sizeof(R) == 4;
+#define X(NC, CW, D64, D128)                                                              \
+  if (sh.nc == NC && sh.cw == CW)                                                         \
+    return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a);
+  HELM_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R, bool ADJ>
+hipError_t dispatch_line(Shape sh, int maxB, int grid, size_t sm, hipStream_t s, SweepArgs a, int g,
+                         int l) {
+  const int t = block_threads(maxB, sh.nc);
+  constexpr bool c64 = sizeof(R) == 4;
+#define X(NC, CW, D64, D128)                                                              \
+  if (sh.nc == NC && sh.cw == CW)                                                         \
+    return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a, g, l);
+  HELM_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 SweepArgs base_args(helm_handle* h) {
@@ -291,6 +435,10 @@ SweepArgs base_args(helm_handle* h) {
   a.rhs_idx = nullptr;
   a.scratch = nullptr;
   return a;
+}
+
+size_t sweep_lds(const helm_handle* h, size_t csz) {
+  return ((size_t)h->n * h->plan.maxB + 2 * (size_t)kZMax + 2 * (size_t)(h->n + 2)) * csz;
 }
 
 }  // namespace
@@ -321,45 +469,41 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   a.out_stride = z_stride;
   a.rhs_idx = rhs_idx;
   a.scratch = h->slab_scratch;
-  const size_t sm = ((size_t)n * h->plan.maxB + 2 * (n + 2)) * csz;
-  const int nc = auto_lanes(h);
+  const size_t sm = sweep_lds(h, csz);
   const int mb = h->plan.maxB;
+  const Shape sh = choose_shape(mb, h->lanes_override);
+  if (sh.cw < 0) return hipErrorInvalidValue;
   if (!r64) return hipErrorInvalidValue;  // inputs are always complex128
-  if (!c64) {
-    if (!z64) return hipErrorInvalidValue;
-    return adjoint ? dispatch_nc<double, double2, double2, true>(nc, mb, R, sm, s, a)
-                   : dispatch_nc<double, double2, double2, false>(nc, mb, R, sm, s, a);
-  }
-  if (z64)
-    return adjoint ? dispatch_nc<float, double2, double2, true>(nc, mb, R, sm, s, a)
-                   : dispatch_nc<float, double2, double2, false>(nc, mb, R, sm, s, a);
-  return adjoint ? dispatch_nc<float, double2, float2, true>(nc, mb, R, sm, s, a)
-                 : dispatch_nc<float, double2, float2, false>(nc, mb, R, sm, s, a);
+  if (!c64 && !z64) return hipErrorInvalidValue;
+  hipEvent_t ev = h->t_apply.begin(s);
+  hipError_t e;
+  if (!c64)
+    e = adjoint ? dispatch_sweep<double, double2, double2, true>(sh, mb, R, sm, s, a)
+                : dispatch_sweep<double, double2, double2, false>(sh, mb, R, sm, s, a);
+  else if (z64)
+    e = adjoint ? dispatch_sweep<float, double2, double2, true>(sh, mb, R, sm, s, a)
+                : dispatch_sweep<float, double2, double2, false>(sh, mb, R, sm, s, a);
+  else
+    e = adjoint ? dispatch_sweep<float, double2, float2, true>(sh, mb, R, sm, s, a)
+                : dispatch_sweep<float, double2, float2, false>(sh, mb, R, sm, s, a);
+  h->t_apply.end(ev, s, R);
+  return e;
 }
 
 hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, double2* x, int R,
                              bool adjoint, hipStream_t s) {
-  const int n = h->n;
   const bool c64 = h->prec == HELM_C64;
   const size_t csz = c64 ? sizeof(float2) : sizeof(double2);
   SweepArgs a = base_args(h);
   a.in = r;
   a.out = x;
-  const size_t sm = ((size_t)n * h->plan.maxB + 2 * (n + 2)) * csz;
-  const int nc = auto_lanes(h);
-  auto go = [&](auto kern) -> hipError_t {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    kern<<<R, block_threads(h->plan.maxB, nc), sm, s>>>(a, zg, yg);
-    return hipGetLastError();
-  };
-  if (c64) {
-    if (nc == 4) return adjoint ? go(k_line_solve<float, 4, true>) : go(k_line_solve<float, 4, false>);
-    if (nc == 16) return adjoint ? go(k_line_solve<float, 16, true>) : go(k_line_solve<float, 16, false>);
-    return adjoint ? go(k_line_solve<float, 8, true>) : go(k_line_solve<float, 8, false>);
-  }
-  if (nc == 4) return adjoint ? go(k_line_solve<double, 4, true>) : go(k_line_solve<double, 4, false>);
-  if (nc == 16) return adjoint ? go(k_line_solve<double, 16, true>) : go(k_line_solve<double, 16, false>);
-  return adjoint ? go(k_line_solve<double, 8, true>) : go(k_line_solve<double, 8, false>);
+  const size_t sm = sweep_lds(h, csz);
+  const int mb = h->plan.maxB;
+  const Shape sh = choose_shape(mb, h->lanes_override);
+  if (sh.cw < 0) return hipErrorInvalidValue;
+  if (c64)
+    return adjoint ? dispatch_line<float, true>(sh, mb, R, sm, s, a, zg, yg)
+                   : dispatch_line<float, false>(sh, mb, R, sm, s, a, zg, yg);
+  return adjoint ? dispatch_line<double, true>(sh, mb, R, sm, s, a, zg, yg)
+                 : dispatch_line<double, false>(sh, mb, R, sm, s, a, zg, yg);
 }
