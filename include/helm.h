@@ -178,6 +178,19 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
 int helm_set_launch(helm_handle* h, int lanes_per_row);
 
 /*
+ * helm_autotune -- pick the sweep's launch shape for this handle: time every valid
+ * lanes-per-row candidate on an interior line problem of the handle (the sweep's inner loop)
+ * and keep the fastest via helm_set_launch.  If cache_path is not NULL the choice is looked up
+ * in / appended to that file (one JSON object per line, keyed by n, largest block and
+ * precision), so the timing runs once per configuration.  *lanes_out (may be NULL) receives
+ * the choice and *ns_per_step (may be NULL) its measured time per block step (0 when taken
+ * from the cache).  Results of later sweeps change only by rounding (summation order).
+ * Synchronises `stream`.
+ */
+int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,
+                  void* stream);
+
+/*
  * Device-time statistics of one handle, from HIP events recorded on the launch stream around
  * every sweep (helm_apply / helm_apply_adjoint / inside helm_solve) and every matvec launch.
  */

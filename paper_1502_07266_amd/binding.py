@@ -52,6 +52,7 @@ _SIGS = {
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
     "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
+    "helm_autotune": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "helm_reset_stats": (_I, [_P]),
     "helm_destroy": (None, [_P]),
     "helm_error_string": (ctypes.c_char_p, [_I]),
@@ -239,6 +240,14 @@ class Helm:
 
     def reset_stats(self):
         _check(lib().helm_reset_stats(self.handle), "helm_reset_stats")
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest launch shape (cached in cache_path); returns (lanes, ns_per_step)."""
+        lanes, ns = _I(), _D()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().helm_autotune(self.handle, path, ctypes.byref(lanes), ctypes.byref(ns), _stream()),
+               "helm_autotune")
+        return lanes.value, ns.value
 
     def set_launch(self, lanes_per_row):
         _check(lib().helm_set_launch(self.handle, int(lanes_per_row)), "helm_set_launch")

@@ -2,6 +2,7 @@
 // Every numerical step runs in the HIP kernels of this library; the host only plans,
 // allocates, launches and reads the scalars GMRES needs to decide.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -299,6 +300,102 @@ int helm_set_launch(helm_handle* h, int lanes_per_row) {
   if (lanes_per_row != 0 && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
     return fail(HELM_EINVAL, "lanes_per_row must be 0, 4, 8 or 16");
   h->lanes_override = lanes_per_row;
+  return HELM_OK;
+}
+
+// ---- launch-shape autotuner -------------------------------------------------------------
+static std::string tune_key(const helm_handle* h) {
+  return "n=" + std::to_string(h->n) + ",maxB=" + std::to_string(h->plan.maxB) +
+         ",prec=" + (h->prec == HELM_C64 ? "c64" : "c128");
+}
+
+static int tune_lookup(const char* path, const std::string& key) {
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return 0;
+  char line[512];
+  int found = 0;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (std::fgets(line, sizeof line, fp)) {
+    if (std::strstr(line, pat.c_str())) {
+      const char* q = std::strstr(line, "\"lanes\":");
+      int v = 0;
+      if (q && std::sscanf(q + 8, "%d", &v) == 1 && (v == 4 || v == 8 || v == 16)) found = v;
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,
+                  void* stream) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  const std::string key = tune_key(h);
+  if (cache_path) {
+    int v = tune_lookup(cache_path, key);
+    if (v) {
+      h->lanes_override = v;
+      if (lanes_out) *lanes_out = v;
+      if (ns_per_step) *ns_per_step = 0.0;
+      return HELM_OK;
+    }
+  }
+  hipStream_t s = S(stream);
+  // an interior line with the largest block: group (G/2, G/2)
+  const int G = h->plan.G, g = G / 2;
+  const int B = h->plan.line_B[(size_t)g * G + g];
+  const size_t elems = (size_t)h->n * B;
+  double2 *r = nullptr, *x = nullptr;
+  HIP_TRY(hipMalloc((void**)&r, elems * sizeof(double2)));
+  if (hipMalloc((void**)&x, elems * sizeof(double2)) != hipSuccess) {
+    (void)hipFree(r);
+    return fail(HELM_EHIP, "autotune buffer allocation failed");
+  }
+  (void)hipMemsetAsync(r, 0, elems * sizeof(double2), s);
+  const int saved = h->lanes_override;
+  int best = 0;
+  double best_ns = 0.0;
+  const int reps = 8;
+  for (int lanes : {16, 8, 4}) {
+    h->lanes_override = lanes;
+    if (launch_line_solve(h, g, g, r, x, 1, false, s) != hipSuccess) {   // warm-up / validity
+      (void)hipGetLastError();
+      continue;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
+    bool ok = true;
+    for (int k = 0; k < reps && ok; ++k) ok = launch_line_solve(h, g, g, r, x, 1, false, s) == hipSuccess;
+    (void)hipEventRecord(b, s);
+    float ms = 0.f;
+    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+      const double ns = ms * 1e6 / (reps * 2.0 * h->n);
+      if (!best || ns < best_ns) {
+        best = lanes;
+        best_ns = ns;
+      }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  (void)hipFree(r);
+  (void)hipFree(x);
+  if (!best) {
+    h->lanes_override = saved;
+    return fail(HELM_EHIP, "no launch shape could be timed");
+  }
+  h->lanes_override = best;
+  if (lanes_out) *lanes_out = best;
+  if (ns_per_step) *ns_per_step = best_ns;
+  if (cache_path) {
+    FILE* fp = std::fopen(cache_path, "a");
+    if (fp) {
+      std::fprintf(fp, "{\"key\": \"%s\", \"lanes\": %d, \"ns_per_step\": %.1f}\n", key.c_str(),
+                   best, best_ns);
+      std::fclose(fp);
+    }
+  }
   return HELM_OK;
 }
 

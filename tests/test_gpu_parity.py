@@ -147,3 +147,18 @@ def test_solve(name, prec):
     for q in range(2):
         r = f[q].ravel() - M.A @ u[q].ravel()
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f[q])
+
+
+def test_autotune_cache_and_invariance(tmp_path):
+    """The tuner picks a valid shape, caches it, and the tuned sweep still matches the oracle."""
+    sc, prob, M = case("b4p4")
+    H = helm("b4p4", "c64")
+    path = str(tmp_path / "tune.jsonl")
+    lanes, ns = H.autotune(path)
+    assert lanes in (4, 8, 16) and ns > 0
+    lanes2, ns2 = H.autotune(path)
+    assert lanes2 == lanes and ns2 == 0.0
+    x = rhs(prob.n, 2, seed=12)
+    z = H.apply(to_gpu(x)).cpu().numpy()
+    ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
+    assert rel(z, ref) <= 2e-4
