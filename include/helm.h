@@ -153,9 +153,12 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
                     size_t* bytes, int* n_lines, int* max_block);
 
 /*
- * helm_line_factors -- copy the block inverses T_1..T_n of line problem (zg, yg) (0-based
- * x3-group and x2-group) into dst_dev: n blocks of B*B complex values, row-major within a
- * block, unknowns of a block ordered (x2 window row, x3 window layer) with x3 fastest.
+ * helm_line_factors -- copy the block inverses of line problem (zg, yg) (0-based x3-group
+ * and x2-group) into dst_dev: n blocks of B*B complex values, block i (0-based x1 index)
+ * holding the factor of x1-block i, row-major within a block, unknowns of a block ordered
+ * (x2 window row, x3 window layer) with x3 fastest.  Lines with zg + yg even are eliminated
+ * upwards in x1 (block i holds the inverse Schur complement after blocks 0..i-1, Sec. 3),
+ * lines with zg + yg odd downwards (after blocks i+1..n-1); both solve the line exactly.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
  * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
  */

@@ -53,11 +53,14 @@ class LineFactors:
 
     The grid is x1 = 1..n times the y-window times the z-window.  Within the block of x1
     index i the unknowns (jj, kk) are ordered with kk (x3) fastest, then jj (x2).
-    ``T[i]`` is the inverse of the Schur complement S_i (numpy.linalg.inv: LU with partial
-    pivoting inside the block; no pivoting across blocks).
+    ``T[t]`` is the inverse of the Schur complement S_t of the t-th block eliminated
+    (numpy.linalg.inv: LU with partial pivoting inside the block; no pivoting across blocks).
+    With ``reverse=True`` the same block LDU is applied to the blocks taken in reverse x1
+    order (the last block eliminated first); the solve is exact either way.
+    ``block_T[i]`` is the factor belonging to x1-block i.
     """
 
-    def __init__(self, prob, Gz, zg, Gy, yg):
+    def __init__(self, prob, Gz, zg, Gy, yg, reverse=False):
         n, h = prob.n, prob.h
         zw0, zw1, zfirst = window(Gz, zg, prob.p)
         yw0, yw1, yfirst = window(Gy, yg, prob.p)
@@ -69,7 +72,8 @@ class LineFactors:
         self.n, self.B = n, self.Wy * self.Wz
         self.K = K
         idx = np.arange(K.shape[0]).reshape(self.Wz, self.Wy, n)
-        self.sel = [idx[:, :, i].T.ravel() for i in range(n)]
+        self.order = list(range(n))[::-1] if reverse else list(range(n))
+        self.sel = [idx[:, :, i].T.ravel() for i in self.order]
         D = [K[s][:, s].toarray() for s in self.sel]
         self.lo = [K[self.sel[i + 1]][:, self.sel[i]] for i in range(n - 1)]   # K_{i+1,i}
         self.up = [K[self.sel[i]][:, self.sel[i + 1]] for i in range(n - 1)]   # K_{i,i+1}
@@ -81,6 +85,9 @@ class LineFactors:
                 S = D[i] - _dense_times_sparse(self.lo[i - 1] @ T[i - 1], self.up[i - 1])
             T.append(np.linalg.inv(S))
         self.T = T
+        self.block_T = [None] * n
+        for t, i in enumerate(self.order):
+            self.block_T[i] = T[t]
         # line-grid unknowns of the physical rows (those of G_yg), in (kk, j, i) C-order
         a = Gy[yg][0]
         self.phys = idx[:, a - yw0:, :].ravel()

@@ -68,14 +68,22 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   if (tid == 0) bad_s = 0;
   __syncthreads();
 
-  for (int i = 0; i < n; ++i) {
+  // Elimination order: lines with g + l even eliminate x1-blocks upwards (i = 0..n-1), lines
+  // with g + l odd downwards (i = n-1..0).  Both are the block LDU of Sec. 3, the second on
+  // the blocks taken in reverse order; the sweep alternates them so that one line's
+  // back-substitution yields its values in the order the next line's elimination needs them.
+  const int dir = (g + l) & 1;
+  for (int t = 0; t < n; ++t) {
+    const int i = dir ? n - 1 - t : t;
     const int m = i + 1;  // global x1 node of block i
     const double2 sxn = a.sbd[2 * m], sxd = a.sbd[2 * m - 1], sxu = a.sbd[2 * m + 1];
     const double2 dx = cscale(cmul(sxn, cadd(sxu, sxd)), -ih2);
-    // l_i * u_{i-1}: (s_m s_{m-1/2} / h^2) * (s_{m-1} s_{m-1/2} / h^2)
-    const double2 sc = (i > 0) ? cmul(cscale(cmul(sxn, sxd), ih2),
-                                      cscale(cmul(a.sbd[2 * m - 2], sxd), ih2))
-                               : make_double2(0.0, 0.0);
+    // upwards:   l_i u_{i-1} = (s_m s_{m-1/2} / h^2) (s_{m-1} s_{m-1/2} / h^2)
+    // downwards: u_i l_{i+1} = (s_m s_{m+1/2} / h^2) (s_{m+1} s_{m+1/2} / h^2)
+    double2 sc = make_double2(0.0, 0.0);
+    if (t > 0)
+      sc = dir ? cmul(cscale(cmul(sxn, sxu), ih2), cscale(cmul(a.sbd[2 * m + 2], sxu), ih2))
+               : cmul(cscale(cmul(sxn, sxd), ih2), cscale(cmul(a.sbd[2 * m - 2], sxd), ih2));
     const C scR = cvt<C>(sc);
     for (int e = tid; e < B * B; e += NT) {
       const int r = e / B, c = e - r * B;
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
         else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
       }
       C v = cvt<C>(val);
-      if (i > 0) v = csub(v, cmul(scR, Tb[e]));
+      if (t > 0) v = csub(v, cmul(scR, Tb[e]));
       S[e] = v;
     }
     __syncthreads();
@@ -127,9 +135,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
       const int pr = piv_s;
       if (pr != k) {
         for (int c = tid; c < B; c += NT) {
-          C t = S[k * B + c];
+          C tmp = S[k * B + c];
           S[k * B + c] = S[pr * B + c];
-          S[pr * B + c] = t;
+          S[pr * B + c] = tmp;
         }
       }
       __syncthreads();
@@ -150,9 +158,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
     if (tid == 0) {
       for (int q = 0; q < B; ++q) rho[q] = q;
       for (int k = 0; k < B; ++k) {
-        int t = rho[k];
+        int tmp = rho[k];
         rho[k] = rho[perm[k]];
-        rho[perm[k]] = t;
+        rho[perm[k]] = tmp;
       }
     }
     __syncthreads();

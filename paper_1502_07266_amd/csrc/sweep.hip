@@ -12,7 +12,8 @@
 //     inner forward  l = 0..G-1 : line input  slab input on the group's rows, minus
 //                                              Ht[j0,j0-1] v[j0-1]   (all window layers)
 //     inner backward l = G-2..0 : line input  Ht[j1,j1+1] v[j1+1]
-//       line solve: y_i = T_i (q_i - l_i y_{i-1}),  x_i = y_i - u_i T_i x_{i+1}
+//       line solve: y_i = T_i (q_i - l_i y_{i-1}),  x_i = y_i - u_i T_i x_{i+1}  (lines with
+//       g + l odd eliminate downwards: y_i = T_i (q_i - u_i y_{i+1}), x_i = y_i - l_i T_i x_{i-1})
 // where v is the slab iterate (n x n x window layers, in global scratch), the line vector
 // (n blocks of B = Wy*Wz) lives in LDS, and the T_i stream from HBM.  The adjoint uses the
 // couplings of A^H and T_i^H (the same pass order).
@@ -78,6 +79,10 @@ struct LineSolver {
   unsigned off[CW];                    // this thread's byte offsets inside a B x B block
   int row, c0;
   bool owner_lane;
+  // Elimination order of the current line: block f0 + fs * t is eliminated at step t
+  // (f0 = 0, fs = 1 upwards; f0 = n - 1, fs = -1 downwards).  The back-substitution visits
+  // the blocks in the opposite order, starting from the second to last one eliminated.
+  int n_, f0, fs;
 
   __device__ __forceinline__ LineSolver() {
     row = threadIdx.x / NC;
@@ -86,17 +91,26 @@ struct LineSolver {
     owner_lane = lc == 0;
   }
 
-  // per-line offsets; rows past B are clamped to a valid row (their sums are never
+  // per-line set-up: offsets and elimination order (dir 0 upwards, 1 downwards, as the
+  // factors were computed).  Rows past B are clamped to a valid row (their sums are never
   // published).  Columns past B meet zero padding of the published vector: in the row-major
   // (non-adjoint) walk they run into the next row, or past the last block into the padding
   // that follows the factor array, so they read finite values; the adjoint walk clamps them.
-  __device__ __forceinline__ void begin_line(int B) {
+  __device__ __forceinline__ void begin_line(int B, int n, int dir) {
+    n_ = n;
+    f0 = dir ? n - 1 : 0;
+    fs = dir ? -1 : 1;
     const int r = row < B ? row : B - 1;
 #pragma unroll
     for (int cc = 0; cc < CW; ++cc) {
       const int col = (ADJ && c0 + cc >= B) ? B - 1 : c0 + cc;
       off[cc] = (unsigned)(ADJ ? col * B + r : r * B + col) * (unsigned)sizeof(C);
     }
+  }
+  // block of forward step t and of backward step t (t clamped to the last step)
+  __device__ __forceinline__ int fblk(int t) const { return f0 + fs * (t < n_ ? t : n_ - 1); }
+  __device__ __forceinline__ int bblk(int t) const {
+    return f0 + fs * (n_ - 2 - (t < n_ - 1 ? t : n_ - 2));
   }
 
   // slot S <- this thread's slice of the block at element offset blk_off of the line T.  The
@@ -116,19 +130,19 @@ struct LineSolver {
     }
   }
 
-  // Ring refills are unconditional: past either end of the line the block index is clamped
-  // (a re-read of a block of the same line, never used), which keeps the load stream free of
+  // Ring refills are unconditional: past either end of the line the step is clamped (a
+  // re-read of a block of the same line, never used), which keeps the load stream free of
   // branches so the wait counts before each use stay exact.
-  template <int S = 0> __device__ __forceinline__ void fill_forward(const C* T, int B, int n) {
+  template <int S = 0> __device__ __forceinline__ void fill_forward(const C* T, int BB) {
     if constexpr (S < D) {
-      load<S>(T, (unsigned)((S < n ? S : n - 1) * B * B));
-      fill_forward<S + 1>(T, B, n);
+      load<S>(T, (unsigned)(fblk(S) * BB));
+      fill_forward<S + 1>(T, BB);
     }
   }
-  template <int S = 0> __device__ __forceinline__ void fill_backward(const C* T, int B, int n) {
+  template <int S = 0> __device__ __forceinline__ void fill_backward(const C* T, int BB) {
     if constexpr (S < D) {
-      load<S>(T, (unsigned)((n - 2 - S >= 0 ? n - 2 - S : 0) * B * B));
-      fill_backward<S + 1>(T, B, n);
+      load<S>(T, (unsigned)(bblk(S) * BB));
+      fill_backward<S + 1>(T, BB);
     }
   }
 
@@ -151,86 +165,93 @@ struct LineSolver {
     return acc[0];
   }
 
-  // Forward step i with ring slot S: y_i = T_i z_i, z_{i+1} = q_{i+1} - l_{i+1} y_i; refills
-  // the slot with block i + D.  The owner's operands are read before the reduction.
-  template <int S> __device__ __forceinline__ void fwd_step(int i, const C* T, int B, int BB, int n,
-                                                            C* ybuf, C* zb, const C* cf) {
+  // Forward step t with ring slot S on block i = fblk(t): y_i = T_i z_i, then the next
+  // block's z = q - (coupling to block i) y_i; refills the slot with the block of step t + D.
+  // cfw[m] is the coupling of node m to its predecessor in elimination order.  The owner's
+  // operands are read before the reduction.
+  template <int S> __device__ __forceinline__ void fwd_step(int t, const C* T, int B, int BB,
+                                                            C* ybuf, C* zb, const C* cfw) {
     const bool own = owner_lane && row < B;
-    const int inext = i + 1 < n ? i + 1 : i;
+    const int i = fblk(t), inext = fblk(t + 1);
     C qn = mk((R)0, (R)0), cn = mk((R)0, (R)0);
     if (own) {
       qn = ybuf[inext * B + row];
-      cn = cf[inext + 1];
+      cn = cfw[inext + 1];
     }
-    const C acc = dot<S>(zb + (i & 1) * ZS);
-    load<S>(T, (unsigned)((i + D < n ? i + D : n - 1) * BB));
+    const C acc = dot<S>(zb + (t & 1) * ZS);
+    load<S>(T, (unsigned)(fblk(t + D) * BB));
     if (own) {
       ybuf[i * B + row] = acc;
-      zb[((i + 1) & 1) * ZS + row] = csub(qn, cmul(cn, acc));
+      zb[((t + 1) & 1) * ZS + row] = csub(qn, cmul(cn, acc));
     }
     lds_barrier();
   }
 
-  // Backward step i: x_i = y_i - u_i T_i x_{i+1}; refills the slot with block i - D.
+  // Backward step t on block i = bblk(t): x_i = y_i - c_i T_i x_prev, with cbw[m] the coupling
+  // of node m to its successor in elimination order; refills the slot with step t + D.
   template <int S>
-  __device__ __forceinline__ void bwd_step(int i, const C* T, int B, int BB, C* ybuf, C* zb,
-                                           const C* cb) {
+  __device__ __forceinline__ void bwd_step(int t, const C* T, int B, int BB, C* ybuf, C* zb,
+                                           const C* cbw) {
     const bool own = owner_lane && row < B;
+    const int i = bblk(t);
     C yi = mk((R)0, (R)0), ci = mk((R)0, (R)0);
     if (own) {
       yi = ybuf[i * B + row];
-      ci = cb[i + 1];
+      ci = cbw[i + 1];
     }
-    const C acc = dot<S>(zb + ((i + 1) & 1) * ZS);
-    load<S>(T, (unsigned)((i - D >= 0 ? i - D : 0) * BB));
+    const C acc = dot<S>(zb + (t & 1) * ZS);
+    load<S>(T, (unsigned)(bblk(t + D) * BB));
     if (own) {
       const C x = csub(yi, cmul(ci, acc));
       ybuf[i * B + row] = x;
-      zb[(i & 1) * ZS + row] = x;
+      zb[((t + 1) & 1) * ZS + row] = x;
     }
     lds_barrier();
   }
 
-  template <int S = 0> __device__ __forceinline__ void fwd_group(int i0, const C* T, int B, int BB,
-                                                                 int n, C* ybuf, C* zb, const C* cf) {
+  template <int S = 0> __device__ __forceinline__ void fwd_group(int t0, const C* T, int B, int BB,
+                                                                 C* ybuf, C* zb, const C* cfw) {
     if constexpr (S < D) {
-      if (i0 + S < n) {
-        fwd_step<S>(i0 + S, T, B, BB, n, ybuf, zb, cf);
-        fwd_group<S + 1>(i0, T, B, BB, n, ybuf, zb, cf);
+      if (t0 + S < n_) {
+        fwd_step<S>(t0 + S, T, B, BB, ybuf, zb, cfw);
+        fwd_group<S + 1>(t0, T, B, BB, ybuf, zb, cfw);
       }
     }
   }
   template <int S = 0>
-  __device__ __forceinline__ void bwd_group(int i0, const C* T, int B, int BB, C* ybuf, C* zb,
-                                            const C* cb) {
+  __device__ __forceinline__ void bwd_group(int t0, const C* T, int B, int BB, C* ybuf, C* zb,
+                                            const C* cbw) {
     if constexpr (S < D) {
-      if (i0 - S >= 0) {
-        bwd_step<S>(i0 - S, T, B, BB, ybuf, zb, cb);
-        bwd_group<S + 1>(i0, T, B, BB, ybuf, zb, cb);
+      if (t0 + S < n_ - 1) {
+        bwd_step<S>(t0 + S, T, B, BB, ybuf, zb, cbw);
+        bwd_group<S + 1>(t0, T, B, BB, ybuf, zb, cbw);
       }
     }
   }
 
-  // Solve with the factors T (n blocks) on the right-hand side in ybuf[i*B + q]; begin_line(B)
-  // and fill_forward must have run, and ybuf must be complete (barrier).  zb holds 2 * ZS
-  // values.  On return ybuf holds the solution (visible to the whole workgroup).  No global
-  // memory is touched besides the factor stream, so the wait before each ring slot is exact.
-  __device__ __forceinline__ void run(const C* T, int B, int n, C* ybuf, C* zb, const C* cf,
-                                      const C* cb) {
+  // Solve with the factors T (n blocks) on the right-hand side in ybuf[i*B + q]; begin_line
+  // and fill_forward must have run, and ybuf must be complete (barrier).  cf[m] / cb[m] are
+  // the couplings of x1-node m to m-1 / m+1.  zb holds 2 * ZS values.  On return ybuf holds
+  // the solution (visible to the whole workgroup).  No global memory is touched besides the
+  // factor stream, so the wait before each ring slot is exact.
+  __device__ __forceinline__ void run(const C* T, int B, C* ybuf, C* zb, const C* cf, const C* cb) {
     const int BB = B * B;
+    const C* cfw = fs > 0 ? cf : cb;
+    const C* cbw = fs > 0 ? cb : cf;
     for (int e = threadIdx.x; e < 2 * ZS; e += blockDim.x) {
       const int q = e < ZS ? e : e - ZS;
       if (q >= B) zb[e] = mk((R)0, (R)0);
     }
-    if (owner_lane && row < B) zb[row] = ybuf[row];             // z_0 = q_0
+    if (owner_lane && row < B) zb[row] = ybuf[fblk(0) * B + row];   // first z = its q
     lds_barrier();
-    for (int i0 = 0; i0 < n; i0 += D)
-      fwd_group(__builtin_amdgcn_readfirstlane(i0), T, B, BB, n, ybuf, zb, cf);
-    fill_backward(T, B, n);
-    if (owner_lane && row < B) zb[((n - 1) & 1) * ZS + row] = ybuf[(n - 1) * B + row];  // x_{n-1} = y_{n-1}
+    for (int t0 = 0; t0 < n_; t0 += D)
+      fwd_group(__builtin_amdgcn_readfirstlane(t0), T, B, BB, ybuf, zb, cfw);
+    fill_backward(T, BB);
+    // the last block eliminated: x = y
+    if (owner_lane && row < B) zb[row] = ybuf[fblk(n_ - 1) * B + row];
     lds_barrier();
-    for (int i0 = n - 2; i0 >= 0; i0 -= D)
-      bwd_group(__builtin_amdgcn_readfirstlane(i0), T, B, BB, ybuf, zb, cb);
+    for (int t0 = 0; t0 < n_ - 1; t0 += D)
+      bwd_group(__builtin_amdgcn_readfirstlane(t0), T, B, BB, ybuf, zb, cbw);
   }
 };
 
@@ -271,8 +292,8 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
         const GroupInfo gy = a.groups[l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
         const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-        ls.begin_line(B);
-        ls.fill_forward(T, B, n);   // in flight while the line input is gathered
+        ls.begin_line(B, n, (g + l) & 1);
+        ls.fill_forward(T, B * B);   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
           const int jj = qq / Wz, kk = qq - jj * Wz;
@@ -296,7 +317,7 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
           ybuf[i * B + qq] = val;
         }
         __syncthreads();
-        ls.run(T, B, n, ybuf, zb, cf, cb);
+        ls.run(T, B, ybuf, zb, cf, cb);
         // ---- line output on the group's rows: v = x (inner forward) or v -= x (backward) ----
         const int npy = j1 - j0 + 1;
         for (int e = tid; e < n * Wz * npy; e += NT) {
@@ -341,14 +362,14 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_line_solve(Sw
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
   LineSolver<R, NC, CW, D, ADJ> ls;
-  ls.begin_line(B);
-  ls.fill_forward(T, B, n);
+  ls.begin_line(B, n, (g + l) & 1);
+  ls.fill_forward(T, B * B);
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
     ybuf[i * B + jj * Wz + kk] = cvt<C>(r[e]);
   }
   __syncthreads();
-  ls.run(T, B, n, ybuf, zb, cf, cb);
+  ls.run(T, B, ybuf, zb, cf, cb);
   for (int e = tid; e < n * B; e += NT) {
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
     x[e] = cvt<double2>(ybuf[i * B + jj * Wz + kk]);

@@ -75,6 +75,24 @@ def test_line_ldu_reproduces_line_matrix_and_dense_solve():
     assert checked == 5
 
 
+def test_reverse_order_ldu_solves_the_same_line():
+    """The block LDU with the x1-blocks taken in reverse order solves the same line problem."""
+    prob = _prob(n=9, b=3, p=2)
+    from oracle.partition import groups
+    Gz = groups(prob.n, prob.b, prob.d)
+    rng = np.random.default_rng(8)
+    for (g, l) in [(0, 1), (2, 3), (5, 2)]:
+        fwd = O.LineFactors(prob, Gz, g, Gz, l)
+        rev = O.LineFactors(prob, Gz, g, Gz, l, reverse=True)
+        Nl = fwd.K.shape[0]
+        r = rng.standard_normal((Nl, 2)) + 1j * rng.standard_normal((Nl, 2))
+        assert _rel(rev.solve(r), fwd.solve(r)) < 1e-12
+        assert _rel(rev.solve_adjoint(r), fwd.solve_adjoint(r)) < 1e-12
+        # the first block eliminated upwards is the last one eliminated downwards: both are D^{-1}
+        assert np.allclose(rev.block_T[prob.n - 1], np.linalg.inv(rev.K[rev.sel[0]][:, rev.sel[0]].toarray()))
+        assert np.allclose(fwd.block_T[0], np.linalg.inv(fwd.K[fwd.sel[0]][:, fwd.sel[0]].toarray()))
+
+
 def test_degenerate_single_groups_give_exact_inverse():
     """First group = whole axis in x2 and x3: one line problem equal to A, M^{-1} = A^{-1}."""
     n = 9
