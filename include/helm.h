@@ -156,9 +156,11 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
  * helm_line_factors -- copy the block inverses of line problem (zg, yg) (0-based x3-group
  * and x2-group) into dst_dev: n blocks of B*B complex values, block i (0-based x1 index)
  * holding the factor of x1-block i, row-major within a block, unknowns of a block ordered
- * (x2 window row, x3 window layer) with x3 fastest.  Lines with zg + yg even are eliminated
- * upwards in x1 (block i holds the inverse Schur complement after blocks 0..i-1, Sec. 3),
- * lines with zg + yg odd downwards (after blocks i+1..n-1); both solve the line exactly.
+ * (x2 window row, x3 window layer) with x3 fastest.  The blocks are eliminated from both
+ * ends towards the middle block m = n/2 (0-based, integer division): block i < m holds the inverse Schur
+ * complement after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks
+ * i+1..n-1, and block m the one after all others, which equals the (m, m) block of the line
+ * matrix's inverse.  The solve is exact for any such order.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
  * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
  */
@@ -186,8 +188,8 @@ int helm_set_launch(helm_handle* h, int lanes_per_row);
  * and keep the fastest via helm_set_launch.  If cache_path is not NULL the choice is looked up
  * in / appended to that file (one JSON object per line, keyed by n, largest block and
  * precision), so the timing runs once per configuration.  *lanes_out (may be NULL) receives
- * the choice and *ns_per_step (may be NULL) its measured time per block step (0 when taken
- * from the cache).  Results of later sweeps change only by rounding (summation order).
+ * the choice and *ns_per_step (may be NULL) its measured time per x1-block of a line solve,
+ * i.e. the time of one line solve divided by n (0 when taken from the cache).  Results of later sweeps change only by rounding (summation order).
  * Synchronises `stream`.
  */
 int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,

@@ -30,12 +30,12 @@ Parity status of each function is recorded in its module docstring.
 from .problem import (Problem, sigma, stretch, boundary_profile, axis_profile,
                       assemble_box, helmholtz_matrix)
 from .partition import groups, window
-from .sweep import LineFactors, SlabSweep, RecursiveSweep
+from .sweep import LineFactors, SlabSweep, RecursiveSweep, elimination_order
 from .krylov import fgmres
 from .gradient import misfit_and_gradient
 
 __all__ = [
     "Problem", "sigma", "stretch", "boundary_profile", "axis_profile", "assemble_box",
-    "helmholtz_matrix", "groups", "window", "LineFactors", "SlabSweep", "RecursiveSweep",
+    "helmholtz_matrix", "groups", "window", "LineFactors", "SlabSweep", "RecursiveSweep", "elimination_order",
     "fgmres", "misfit_and_gradient",
 ]

@@ -4,7 +4,8 @@ Test infrastructure only (see ``oracle/__init__.py``).
 
 * ``LineFactors``    -- one quasi-1D auxiliary problem (Sec. 4.1, moving PML next to the
                         y-group, Fig. 3), factored by the block LDU of Sec. 3 with the x1
-                        index as block index ("dimension 3 and 2 first and dimension 1 last").
+                        index as block index (x3 and x2 grouped first, x1 last), the blocks
+                        eliminated upwards, downwards or from both ends towards the middle.
 * ``SlabSweep``      -- one quasi-2D auxiliary problem (H_b or H_m of Sec. 3) and its inner
                         sweep: Algorithm 3 (setup) and Algorithm 4 (apply).
 * ``RecursiveSweep`` -- Algorithm 5 (setup) and Algorithm 6 (apply) of Sec. 4.2, with the
@@ -25,7 +26,8 @@ line solves (K^{-H} = L^{-H} D^{-H} U^{-H} with the block LDU factors).  Pinned 
 test <M^{-1}x, y> = <x, M^{-H}y>.
 
 Pins (tests/test_oracle_sweep.py): each line's block LDU reproduces its matrix and its
-solve equals a dense solve; degenerate partitions reduce Algorithm 6 to an exact solve
+solve equals a dense solve, in every elimination order; the first block eliminated has
+T = K_ii^{-1} and the last one T = (K^{-1})_ii; degenerate partitions reduce Algorithm 6 to an exact solve
 (first groups = whole axis) or to the non-recursive Algorithm 2 with exact auxiliary solves
 (along x3 or along x2); the moving PML makes the auxiliary restriction approach the exact
 Schur-complement inverse T_m of Sec. 3 as p grows; M^{-1} is linear; the dot test above.
@@ -48,19 +50,36 @@ def _cols(v):
     return v.reshape(v.shape[0], -1)
 
 
+def elimination_order(n, kind="up"):
+    """Order in which the x1-blocks 0..n-1 of a line are eliminated by its block LDU.
+
+    "up": 0, 1, ..., n-1 (the order of Sec. 3).  "down": n-1, ..., 0.  "two-sided": blocks
+    0..m-1 upwards and n-1..m+1 downwards, the middle block m = n//2 last.  Every order
+    eliminates an end block of the remaining chain, so no fill is created and the block LDU
+    stays exact; only the factors differ.
+    """
+    if kind == "up":
+        return list(range(n))
+    if kind == "down":
+        return list(range(n - 1, -1, -1))
+    if kind == "two-sided":
+        m = n // 2
+        return list(range(m)) + list(range(n - 1, m, -1)) + [m]
+    raise ValueError(kind)
+
+
 class LineFactors:
     """Quasi-1D auxiliary problem of (z-group zg, y-group yg) and its block LDU (Sec. 4.1).
 
     The grid is x1 = 1..n times the y-window times the z-window.  Within the block of x1
-    index i the unknowns (jj, kk) are ordered with kk (x3) fastest, then jj (x2).
-    ``T[t]`` is the inverse of the Schur complement S_t of the t-th block eliminated
-    (numpy.linalg.inv: LU with partial pivoting inside the block; no pivoting across blocks).
-    With ``reverse=True`` the same block LDU is applied to the blocks taken in reverse x1
-    order (the last block eliminated first); the solve is exact either way.
-    ``block_T[i]`` is the factor belonging to x1-block i.
+    index i the unknowns (jj, kk) are ordered with kk (x3) fastest, then jj (x2).  The
+    blocks are eliminated in ``order`` (``elimination_order``); when block i is eliminated,
+    its Schur complement is S_i = K_ii - sum_j K_ij T_j K_ji over its already eliminated
+    neighbours j, and ``block_T[i]`` = S_i^{-1} (numpy.linalg.inv: LU with partial pivoting
+    inside the block; no pivoting across blocks).
     """
 
-    def __init__(self, prob, Gz, zg, Gy, yg, reverse=False):
+    def __init__(self, prob, Gz, zg, Gy, yg, order="up"):
         n, h = prob.n, prob.h
         zw0, zw1, zfirst = window(Gz, zg, prob.p)
         yw0, yw1, yfirst = window(Gy, yg, prob.p)
@@ -72,53 +91,61 @@ class LineFactors:
         self.n, self.B = n, self.Wy * self.Wz
         self.K = K
         idx = np.arange(K.shape[0]).reshape(self.Wz, self.Wy, n)
-        self.order = list(range(n))[::-1] if reverse else list(range(n))
-        self.sel = [idx[:, :, i].T.ravel() for i in self.order]
-        D = [K[s][:, s].toarray() for s in self.sel]
-        self.lo = [K[self.sel[i + 1]][:, self.sel[i]] for i in range(n - 1)]   # K_{i+1,i}
-        self.up = [K[self.sel[i]][:, self.sel[i + 1]] for i in range(n - 1)]   # K_{i,i+1}
-        T = []
-        for i in range(n):
-            if i == 0:
-                S = D[0]
-            else:
-                S = D[i] - _dense_times_sparse(self.lo[i - 1] @ T[i - 1], self.up[i - 1])
-            T.append(np.linalg.inv(S))
-        self.T = T
+        self.sel = [idx[:, :, i].T.ravel() for i in range(n)]   # unknowns of x1-block i
+        self.order = elimination_order(n, order)
+        # K_ij for neighbouring blocks (sparse)
+        self.Kc = {}
+        for i in range(n - 1):
+            self.Kc[(i + 1, i)] = K[self.sel[i + 1]][:, self.sel[i]]
+            self.Kc[(i, i + 1)] = K[self.sel[i]][:, self.sel[i + 1]]
+        done = set()
         self.block_T = [None] * n
-        for t, i in enumerate(self.order):
-            self.block_T[i] = T[t]
+        for i in self.order:
+            assert not (i - 1 in done and i + 1 in done and len(done) < n - 1), "not an end block"
+            S = K[self.sel[i]][:, self.sel[i]].toarray()
+            for j in (i - 1, i + 1):
+                if j in done:
+                    S = S - _dense_times_sparse(self.Kc[(i, j)] @ self.block_T[j], self.Kc[(j, i)])
+            self.block_T[i] = np.linalg.inv(S)
+            done.add(i)
+        self.rank = {i: t for t, i in enumerate(self.order)}
         # line-grid unknowns of the physical rows (those of G_yg), in (kk, j, i) C-order
         a = Gy[yg][0]
         self.phys = idx[:, a - yw0:, :].ravel()
 
+    def _nbrs(self, i, before):
+        """Neighbours of block i eliminated before (or after) it."""
+        return [j for j in (i - 1, i + 1)
+                if 0 <= j < self.n and (self.rank[j] < self.rank[i]) == before]
+
+    def _solve(self, r, Kij, Ti):
+        r = _cols(r)
+        w = [r[s].astype(np.complex128) for s in self.sel]
+        y = [None] * self.n
+        for i in self.order:                              # L^{-1}, then diag(T)
+            z = w[i]
+            for j in self._nbrs(i, True):
+                z = z - Kij(i, j) @ y[j]
+            y[i] = Ti(i) @ z
+        x = [None] * self.n
+        for i in reversed(self.order):                    # U^{-1}
+            c = 0
+            for j in self._nbrs(i, False):
+                c = c + Kij(i, j) @ x[j]
+            x[i] = y[i] - Ti(i) @ c if not np.isscalar(c) else y[i]
+        out = np.zeros(r.shape, np.complex128)
+        for i, s in enumerate(self.sel):
+            out[s] = x[i]
+        return out
+
     def solve(self, r):
         """K^{-1} r through the factors (the solve formula of Sec. 3 / Sec. 4.1)."""
-        r = _cols(r)
-        g = [r[s].astype(np.complex128) for s in self.sel]
-        for i in range(self.n - 1):                       # L^{-1}
-            g[i + 1] = g[i + 1] - self.lo[i] @ (self.T[i] @ g[i])
-        y = [self.T[i] @ g[i] for i in range(self.n)]    # diag(T)
-        for i in range(self.n - 2, -1, -1):               # U^{-1}
-            y[i] = y[i] - self.T[i] @ (self.up[i] @ y[i + 1])
-        x = np.zeros(r.shape, np.complex128)
-        for i, s in enumerate(self.sel):
-            x[s] = y[i]
-        return x
+        return self._solve(r, lambda i, j: self.Kc[(i, j)], lambda i: self.block_T[i])
 
     def solve_adjoint(self, r):
-        """K^{-H} r = L^{-H} D^{-H} U^{-H} r with the same factors."""
-        r = _cols(r)
-        g = [r[s].astype(np.complex128) for s in self.sel]
-        for i in range(self.n - 1):                       # U^{-H}
-            g[i + 1] = g[i + 1] - self.up[i].conj().T @ (self.T[i].conj().T @ g[i])
-        y = [self.T[i].conj().T @ g[i] for i in range(self.n)]
-        for i in range(self.n - 2, -1, -1):               # L^{-H}
-            y[i] = y[i] - self.T[i].conj().T @ (self.lo[i].conj().T @ y[i + 1])
-        x = np.zeros(r.shape, np.complex128)
-        for i, s in enumerate(self.sel):
-            x[s] = y[i]
-        return x
+        """K^{-H} r = L^{-H} D^{-H} U^{-H} r: the same passes with K^H and the T^H."""
+        return self._solve(r, lambda i, j: self.Kc[(j, i)].conj().T,
+                           lambda i: self.block_T[i].conj().T)
 
 
 class SlabSweep:

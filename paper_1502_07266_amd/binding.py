@@ -242,7 +242,8 @@ class Helm:
         _check(lib().helm_reset_stats(self.handle), "helm_reset_stats")
 
     def autotune(self, cache_path=None):
-        """Pick the fastest launch shape (cached in cache_path); returns (lanes, ns_per_step)."""
+        """Pick the fastest launch shape (cached in cache_path); returns (lanes, ns per x1-block
+        of a line solve)."""
         lanes, ns = _I(), _D()
         path = cache_path.encode() if cache_path else None
         _check(lib().helm_autotune(self.handle, path, ctypes.byref(lanes), ctypes.byref(ns), _stream()),

@@ -31,7 +31,7 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   if (rc != HELM_OK) return fail(rc, msg);
   if (plan.maxB > kBlockLimit)
     return fail(HELM_EINVAL, "block size (b or p+d per axis, squared) exceeds 64");
-  const size_t lds = ((size_t)plan.n * plan.maxB + 128 + 2 * (plan.n + 2)) * csize(prec);
+  const size_t lds = LdsLayout(plan.n, plan.maxB, (int)csize(prec)).bytes;
   if (lds > kLdsBytes) return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
   return HELM_OK;
 }
@@ -370,7 +370,7 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
     (void)hipEventRecord(b, s);
     float ms = 0.f;
     if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
-      const double ns = ms * 1e6 / (reps * 2.0 * h->n);
+      const double ns = ms * 1e6 / (reps * (double)h->n);   // per x1-block of a line solve
       if (!best || ns < best_ns) {
         best = lanes;
         best_ns = ns;

@@ -53,6 +53,30 @@ template <> __host__ __device__ inline double2 cvt<double2, float2>(float2 s) {
 }
 
 // ---------------------------------------------------------------------------------------
+// LDS of the sweep kernels
+// ---------------------------------------------------------------------------------------
+constexpr int kZMax = 64;   // largest NC * CW of the sweep's launch shapes
+
+// LDS layout of the sweep kernels, in complex elements from the base (the step table follows
+// at a 16-byte boundary): line vector, published vectors, zero and junk rows, couplings, the
+// per-step couplings and the per-step table of the two chains.
+struct LdsLayout {
+  int ybuf, zb, zeros, junk, cf, cb, ctab;
+  size_t tab_byte, bytes;
+  __host__ __device__ LdsLayout(int n, int maxB, int csz) {
+    ybuf = 0;
+    zb = n * maxB;
+    zeros = zb + 4 * kZMax;
+    junk = zeros + kZMax;
+    cf = junk + kZMax;
+    cb = cf + (n + 2);
+    ctab = cb + (n + 2);
+    tab_byte = ((size_t)(ctab + 2 * (n + 3)) * csz + 15) / 16 * 16;
+    bytes = tab_byte + 2 * (size_t)(n + 3) * 16;
+  }
+};
+
+// ---------------------------------------------------------------------------------------
 // partition of an axis into groups and their auxiliary windows
 // ---------------------------------------------------------------------------------------
 struct GroupInfo {

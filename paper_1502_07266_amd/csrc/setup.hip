@@ -7,12 +7,14 @@
 // between x1-neighbour blocks is a multiple of the identity:
 //     K_{i,i-1} = l_i I,  l_i = s1_i s1_{i-1/2} / h^2,   K_{i,i+1} = u_i I,  u_i = s1_i s1_{i+1/2} / h^2,
 // and the block recursion S_1 = D_1, S_i = D_i - K_{i,i-1} S_{i-1}^{-1} K_{i-1,i} becomes the
-// scaled update S_i = D_i - (l_i u_{i-1}) T_{i-1}: the only dense work is inverting S_i.
+// scaled update S_i = D_i - (l_i u_{i-1}) T_{i-1} (and its mirror image from the other end):
+// the only dense work is inverting S_i.
 // D_i is the 5-point (x2, x3) operator of the window plus the x1 diagonal and kappa.
 //
 // One workgroup owns one line: it forms S_i in LDS, inverts it by Gauss-Jordan elimination
 // with partial pivoting (row interchanges inside the block only), stores T_i = S_i^{-1} and
-// reuses it for the next Schur update.  All ~G^2 lines are independent (Sec. 6 notes that
+// reuses it for the next Schur update.  The blocks are eliminated from both ends towards the
+// middle (see the order below), which halves the dependent chain of the line solve.  All ~G^2 lines are independent (Sec. 6 notes that
 // the setup is O(n^2) independent quasi-1D problems), so one launch covers them all.
 #include "common.h"
 
@@ -68,23 +70,29 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   if (tid == 0) bad_s = 0;
   __syncthreads();
 
-  // Elimination order: lines with g + l even eliminate x1-blocks upwards (i = 0..n-1), lines
-  // with g + l odd downwards (i = n-1..0).  Both are the block LDU of Sec. 3, the second on
-  // the blocks taken in reverse order; the sweep alternates them so that one line's
-  // back-substitution yields its values in the order the next line's elimination needs them.
-  const int dir = (g + l) & 1;
+  // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
+  // middle block m = n/2 (integer division) last, whose Schur complement takes the update from both sides.
+  // It is the block LDU of Sec. 3 with the blocks in that order (every block eliminated is an
+  // end of the remaining chain, so there is no fill); the sweep runs the two halves of each
+  // line solve as two concurrent chains.
+  const int mid = n / 2;
+  const bool has_lower = mid + 1 <= n - 1;
+  const C* T_mid_minus1 = out + (long long)(mid - 1) * B * B;   // T_{m-1}, stored at t = m - 1
   for (int t = 0; t < n; ++t) {
-    const int i = dir ? n - 1 - t : t;
+    const int i = t < mid ? t : (t < n - 1 ? n - 1 - (t - mid) : mid);
     const int m = i + 1;  // global x1 node of block i
     const double2 sxn = a.sbd[2 * m], sxd = a.sbd[2 * m - 1], sxu = a.sbd[2 * m + 1];
     const double2 dx = cscale(cmul(sxn, cadd(sxu, sxd)), -ih2);
-    // upwards:   l_i u_{i-1} = (s_m s_{m-1/2} / h^2) (s_{m-1} s_{m-1/2} / h^2)
-    // downwards: u_i l_{i+1} = (s_m s_{m+1/2} / h^2) (s_{m+1} s_{m+1/2} / h^2)
-    double2 sc = make_double2(0.0, 0.0);
-    if (t > 0)
-      sc = dir ? cmul(cscale(cmul(sxn, sxu), ih2), cscale(cmul(a.sbd[2 * m + 2], sxu), ih2))
-               : cmul(cscale(cmul(sxn, sxd), ih2), cscale(cmul(a.sbd[2 * m - 2], sxd), ih2));
-    const C scR = cvt<C>(sc);
+    // update from the block below: l_i u_{i-1} = (s_m s_{m-1/2} / h^2)(s_{m-1} s_{m-1/2} / h^2)
+    // update from the block above: u_i l_{i+1} = (s_m s_{m+1/2} / h^2)(s_{m+1} s_{m+1/2} / h^2)
+    const C sc_below = cvt<C>(cmul(cscale(cmul(sxn, sxd), ih2), cscale(cmul(a.sbd[2 * m - 2], sxd), ih2)));
+    const C sc_above = cvt<C>(cmul(cscale(cmul(sxn, sxu), ih2), cscale(cmul(a.sbd[2 * m + 2], sxu), ih2)));
+    // (scale, factor) pairs of the Schur update; Tb holds the factor computed last
+    const bool is_mid = t == n - 1;
+    const bool use_a = (t > 0 && t < mid) || (t > mid && t < n - 1) || is_mid;
+    const C scA = (t < mid || is_mid) ? sc_below : sc_above;
+    const C* TA = (is_mid && has_lower) ? T_mid_minus1 : Tb;
+    const bool use_b = is_mid && has_lower;
     for (int e = tid; e < B * B; e += NT) {
       const int r = e / B, c = e - r * B;
       const int jr = r / Wz, kr = r - jr * Wz, jc = c / Wz, kc = c - jc * Wz;
@@ -104,7 +112,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
         else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
       }
       C v = cvt<C>(val);
-      if (t > 0) v = csub(v, cmul(scR, Tb[e]));
+      if (use_a) v = csub(v, cmul(scA, TA[e]));
+      if (use_b) v = csub(v, cmul(sc_above, Tb[e]));
       S[e] = v;
     }
     __syncthreads();

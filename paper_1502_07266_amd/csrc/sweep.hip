@@ -12,13 +12,15 @@
 //     inner forward  l = 0..G-1 : line input  slab input on the group's rows, minus
 //                                              Ht[j0,j0-1] v[j0-1]   (all window layers)
 //     inner backward l = G-2..0 : line input  Ht[j1,j1+1] v[j1+1]
-//       line solve: y_i = T_i (q_i - l_i y_{i-1}),  x_i = y_i - u_i T_i x_{i+1}  (lines with
-//       g + l odd eliminate downwards: y_i = T_i (q_i - u_i y_{i+1}), x_i = y_i - l_i T_i x_{i-1})
+//       line solve: two-sided block LDU, y_i = T_i (q_i - l_i y_{i-1}) for the blocks below the
+//       middle, y_i = T_i (q_i - u_i y_{i+1}) above it, the middle block last, then
+//       x_i = y_i - u_i T_i x_{i+1} below and x_i = y_i - l_i T_i x_{i-1} above
 // where v is the slab iterate (n x n x window layers, in global scratch), the line vector
 // (n blocks of B = Wy*Wz) lives in LDS, and the T_i stream from HBM.  The adjoint uses the
 // couplings of A^H and T_i^H (the same pass order).
 //
-// Block step: thread t owns output row t / NC of the B x B block and CW consecutive columns;
+// Block step: in each of the line's two chains, thread t owns output row t / NC of the B x B
+// block and CW consecutive columns;
 // the NC partial sums of a row are adjacent lanes of one wavefront and are combined with DPP
 // row operations.  The vector a step multiplies (z_i = q_i - l_i y_{i-1} forward, x_{i+1}
 // backward) is formed once per row by the row's owner lane and published through a
@@ -29,10 +31,10 @@
 
 namespace {
 
-constexpr int kZMax = 64;   // largest NC * CW of the instantiated shapes
 
 struct SweepArgs {
   int n, G, maxW, maxB;
+  int tpc;               // threads per line chain (the launch has two chains)
   long long N, in_stride, out_stride;
   const GroupInfo* groups;
   const long long* line_off;
@@ -62,6 +64,18 @@ template <int NC, typename T> __device__ __forceinline__ T lane_sum(T v) {
   return v;
 }
 
+// Loads from the factor array through an explicitly global pointer (global_load, counted by
+// vmcnt only; a generic pointer would give flat loads, which also count against lgkmcnt and
+// would make every LDS wait drain the factor ring).
+#define HELM_GLOBAL __attribute__((address_space(1)))
+template <typename R> struct vec2 { using type = R __attribute__((ext_vector_type(2))); };
+template <typename R>
+__device__ __forceinline__ typename cx<R>::type load_global(const HELM_GLOBAL char* base, unsigned off) {
+  using V = typename vec2<R>::type;
+  const V v = *reinterpret_cast<const HELM_GLOBAL V*>(base + off);
+  return mk(v.x, v.y);
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS operations, then
 // s_barrier.  Unlike __syncthreads() it does not wait for outstanding global loads, so the
 // factor ring stays in flight across block steps.  Global scratch written around a line
@@ -70,200 +84,246 @@ __device__ __forceinline__ void lds_barrier() {
   __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Two-sided line solve.  The factors eliminate the blocks of a line from both ends towards the
+// middle block mid = n/2 (integer division).  Step t (t = 0..2 mid) of a chain handles block
+//     upper chain (threads [0, tpc))      : i = mid - |mid - t|
+//     lower chain (threads [tpc, 2 tpc))  : i = mid + |mid - t|
+// forward elimination for t < mid, the middle block at t = mid (both chains compute it, from
+// the sum of their two partial right-hand sides), back-substitution for t > mid.  The lower
+// chain has no block when i > n - 1 (t = 0 and t = 2 mid for even n).  One barrier per step:
+// a line takes 2 mid + 1 steps (n for odd n) instead of the 2n - 1 of a one-sided sweep.
+//
+// A wave issues one instruction every few cycles and the scalar unit is shared by all waves of
+// the compute unit, so the step is kept free of per-step bookkeeping: a per-line table gives,
+// for each chain and step, the LDS rows to read and write and the factor block to prefetch,
+// and every lane of a block row writes the row's (identical) result, so no lane masking is
+// needed.  Steps without a destination write to a junk row.
 template <typename R, int NC, int CW, int D, bool ADJ>
 struct LineSolver {
   using C = typename cx<R>::type;
   static constexpr int ZS = NC * CW;   // stride of one published vector (>= B, zero-padded)
-  static constexpr int NA = CW < 3 ? CW : 3;   // independent accumulators in a block row
+  static_assert(D % 2 == 0, "the ring depth must be even (published-vector parity per slot)");
   C ring[D][CW];
-  unsigned off[CW];                    // this thread's byte offsets inside a B x B block
-  int row, c0;
-  bool owner_lane;
-  // Elimination order of the current line: block f0 + fs * t is eliminated at step t
-  // (f0 = 0, fs = 1 upwards; f0 = n - 1, fs = -1 downwards).  The back-substitution visits
-  // the blocks in the opposite order, starting from the second to last one eliminated.
-  int n_, f0, fs;
+  unsigned off0;                       // this thread's byte offset inside a B x B block
+  unsigned offa[ADJ ? CW : 1];         // adjoint walk: one offset per column
+  int row, rowc, c0;
+  int lower;                           // 0 upper chain, 1 lower chain (uniform in a wave)
+  // per line (uniform)
+  int n_, mid, B_, steps;
+  unsigned BBb;                        // bytes of one factor block
+  const HELM_GLOBAL char* Tb;          // factors of the line
+  // per step, carried one step ahead: table entry of this and the next step, the owner
+  // operand and the coupling of this step
+  int4 ecur, enext;
+  C Acur, ccur;
 
-  __device__ __forceinline__ LineSolver() {
-    row = threadIdx.x / NC;
-    const int lc = threadIdx.x - row * NC;
-    c0 = lc * CW;
-    owner_lane = lc == 0;
+  // tpc: threads per chain, a multiple of the wavefront size
+  __device__ __forceinline__ explicit LineSolver(int tpc) {
+    lower = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= tpc ? 1 : 0);
+    const int lt = (int)threadIdx.x - lower * tpc;
+    row = lt / NC;
+    c0 = (lt - row * NC) * CW;
   }
 
-  // per-line set-up: offsets and elimination order (dir 0 upwards, 1 downwards, as the
-  // factors were computed).  Rows past B are clamped to a valid row (their sums are never
-  // published).  Columns past B meet zero padding of the published vector: in the row-major
-  // (non-adjoint) walk they run into the next row, or past the last block into the padding
-  // that follows the factor array, so they read finite values; the adjoint walk clamps them.
-  __device__ __forceinline__ void begin_line(int B, int n, int dir) {
+  // per-line set-up.  Rows past B are clamped to row B - 1 (they compute and write that row's
+  // values again).  Columns past B meet zero padding of the published vector: in the
+  // row-major (non-adjoint) walk they run into the next row, or past the last block into the
+  // padding that follows the factor array, so they read finite values; the adjoint walk
+  // clamps them.
+  __device__ __forceinline__ void begin_line(const C* T, int B, int n) {
     n_ = n;
-    f0 = dir ? n - 1 : 0;
-    fs = dir ? -1 : 1;
-    const int r = row < B ? row : B - 1;
-#pragma unroll
-    for (int cc = 0; cc < CW; ++cc) {
-      const int col = (ADJ && c0 + cc >= B) ? B - 1 : c0 + cc;
-      off[cc] = (unsigned)(ADJ ? col * B + r : r * B + col) * (unsigned)sizeof(C);
-    }
-  }
-  // block of forward step t and of backward step t (t clamped to the last step)
-  __device__ __forceinline__ int fblk(int t) const { return f0 + fs * (t < n_ ? t : n_ - 1); }
-  __device__ __forceinline__ int bblk(int t) const {
-    return f0 + fs * (n_ - 2 - (t < n_ - 1 ? t : n_ - 2));
-  }
-
-  // slot S <- this thread's slice of the block at element offset blk_off of the line T.  The
-  // byte offset is formed in 32 bits (a line's factors are far below 4 GiB) on a uniform base,
-  // which maps to scalar-base + 32-bit vector-offset addressing.
-  template <int S> __device__ __forceinline__ void load(const C* __restrict__ T, unsigned blk_off) {
-    const char* base = reinterpret_cast<const char*>(T);
-    const unsigned b0 = blk_off * (unsigned)sizeof(C);
+    B_ = B;
+    mid = n / 2;
+    steps = 2 * mid + 1;
+    BBb = (unsigned)(B * B) * (unsigned)sizeof(C);
+    const unsigned long long tp = reinterpret_cast<unsigned long long>(T);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)tp);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(tp >> 32));
+    Tb = (const HELM_GLOBAL char*)(((unsigned long long)hi << 32) | lo);
+    rowc = row < B ? row : B - 1;
+    off0 = (unsigned)(rowc * B + c0) * (unsigned)sizeof(C);
     if constexpr (ADJ) {
 #pragma unroll
-      for (int cc = 0; cc < CW; ++cc)
-        ring[S][cc] = *reinterpret_cast<const C*>(base + (b0 + off[cc]));
-    } else {
-      const C* p = reinterpret_cast<const C*>(base + (b0 + off[0]));   // contiguous columns
+      for (int cc = 0; cc < CW; ++cc) {
+        const int col = c0 + cc >= B ? B - 1 : c0 + cc;
+        offa[cc] = (unsigned)(col * B + rowc) * (unsigned)sizeof(C);
+      }
+    }
+  }
+
+  // block of step t of chain ch, clamped to the line
+  __device__ __forceinline__ int blk(int ch, int t) const {
+    const int d = mid > t ? mid - t : t - mid;
+    const int i = ch ? mid + d : mid - d;
+    return i < 0 ? 0 : (i > n_ - 1 ? n_ - 1 : i);
+  }
+
+  // slot S <- this thread's slice of the factor block at byte offset b0 of the line: a uniform
+  // base plus 32-bit vector offsets (a line's factors are far below 4 GiB); the non-adjoint
+  // columns are contiguous and share one offset register.
+  template <int S> __device__ __forceinline__ void load(unsigned b0) {
+    if constexpr (ADJ) {
 #pragma unroll
-      for (int cc = 0; cc < CW; ++cc) ring[S][cc] = p[cc];
+      for (int cc = 0; cc < CW; ++cc) ring[S][cc] = load_global<R>(Tb, b0 + offa[cc]);
+    } else {
+      using V = typename vec2<R>::type;
+      const HELM_GLOBAL V* p = reinterpret_cast<const HELM_GLOBAL V*>(Tb + (b0 + off0));
+#pragma unroll
+      for (int cc = 0; cc < CW; ++cc) {
+        const V w = p[cc];
+        ring[S][cc] = mk(w.x, w.y);
+      }
     }
   }
 
-  // Ring refills are unconditional: past either end of the line the step is clamped (a
-  // re-read of a block of the same line, never used), which keeps the load stream free of
-  // branches so the wait counts before each use stay exact.
-  template <int S = 0> __device__ __forceinline__ void fill_forward(const C* T, int BB) {
+  template <int S = 0> __device__ __forceinline__ void fill() {
     if constexpr (S < D) {
-      load<S>(T, (unsigned)(fblk(S) * BB));
-      fill_forward<S + 1>(T, BB);
-    }
-  }
-  template <int S = 0> __device__ __forceinline__ void fill_backward(const C* T, int BB) {
-    if constexpr (S < D) {
-      load<S>(T, (unsigned)(bblk(S) * BB));
-      fill_backward<S + 1>(T, BB);
+      load<S>((unsigned)blk(lower, S) * BBb);
+      fill<S + 1>();
     }
   }
 
-  // row sum of ring[S] . z over this thread's columns, reduced over the row's NC lanes
-  template <int S> __device__ __forceinline__ C dot(const C* z) const {
+  // row sum of ring[S] . z over this thread's columns, reduced over the row's NC lanes (one
+  // accumulator: a wave issues an instruction only every few cycles, which already covers the
+  // FMA latency)
+  template <int S> __device__ __forceinline__ C dot(const C (&zr)[CW]) const {
+    C acc = ADJ ? mk(ring[S][0].x * zr[0].x + ring[S][0].y * zr[0].y,
+                     ring[S][0].x * zr[0].y - ring[S][0].y * zr[0].x)
+                : cmul(ring[S][0], zr[0]);
+#pragma unroll
+    for (int cc = 1; cc < CW; ++cc)
+      acc = ADJ ? cfma_conj(acc, ring[S][cc], zr[cc]) : cfma(acc, ring[S][cc], zr[cc]);
+    acc.x = lane_sum<NC>(acc.x);
+    acc.y = lane_sum<NC>(acc.y);
+    return acc;
+  }
+
+  // Step t with ring slot S (parity of t = parity of S):
+  //   forward  y_i = T_i z_i; the next published vector is q_next - c y_i (the lower chain
+  //            leaves q_mid out: the upper chain's partial right-hand side of the middle block
+  //            has it)
+  //   middle   x_mid = T_mid (z_upper + z_lower), published by both chains
+  //   backward x_i = y_i - c T_i x_prev, published
+  // i.e. P = A - c acc with the table's operand row A and coupling c (A = 0, c = -1 in the
+  // middle); the block row gets acc (forward) or P.  sb is the LDS base the table indexes.
+  template <int S>
+  __device__ __forceinline__ void step(int t, C* sb, const C* zme, const C* zot, const int4* tab,
+                                       const C* ctab) {
+    constexpr int par = (S & 1) * ZS;
     C zr[CW];
 #pragma unroll
-    for (int cc = 0; cc < CW; ++cc) zr[cc] = z[c0 + cc];
-    C acc[NA];
+    for (int cc = 0; cc < CW; ++cc) zr[cc] = zme[par + c0 + cc];
+    if (t == mid) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = mk((R)0, (R)0);
-#pragma unroll
-    for (int cc = 0; cc < CW; ++cc)
-      acc[cc % NA] = ADJ ? cfma_conj(acc[cc % NA], ring[S][cc], zr[cc])
-                         : cfma(acc[cc % NA], ring[S][cc], zr[cc]);
-#pragma unroll
-    for (int a = 1; a < NA; ++a) acc[0] = cadd(acc[0], acc[a]);
-    acc[0].x = lane_sum<NC>(acc[0].x);
-    acc[0].y = lane_sum<NC>(acc[0].y);
-    return acc[0];
-  }
-
-  // Forward step t with ring slot S on block i = fblk(t): y_i = T_i z_i, then the next
-  // block's z = q - (coupling to block i) y_i; refills the slot with the block of step t + D.
-  // cfw[m] is the coupling of node m to its predecessor in elimination order.  The owner's
-  // operands are read before the reduction.
-  template <int S> __device__ __forceinline__ void fwd_step(int t, const C* T, int B, int BB,
-                                                            C* ybuf, C* zb, const C* cfw) {
-    const bool own = owner_lane && row < B;
-    const int i = fblk(t), inext = fblk(t + 1);
-    C qn = mk((R)0, (R)0), cn = mk((R)0, (R)0);
-    if (own) {
-      qn = ybuf[inext * B + row];
-      cn = cfw[inext + 1];
+      for (int cc = 0; cc < CW; ++cc) zr[cc] = cadd(zr[cc], zot[par + c0 + cc]);
     }
-    const C acc = dot<S>(zb + (t & 1) * ZS);
-    load<S>(T, (unsigned)(fblk(t + D) * BB));
-    if (own) {
-      ybuf[i * B + row] = acc;
-      zb[((t + 1) & 1) * ZS + row] = csub(qn, cmul(cn, acc));
-    }
+    const int4 e2 = tab[t + 2];
+    const C cn = ctab[t + 1];
+    const C acc = dot<S>(zr);
+    load<S>((unsigned)ecur.w);
+    const C P = csub(Acur, cmul(ccur, acc));
+    // component-wise select (a select of whole complex128 values is lowered through scratch)
+    const bool fwd = t < mid;
+    C out;
+    out.x = fwd ? acc.x : P.x;
+    out.y = fwd ? acc.y : P.y;
+    sb[ecur.y + rowc] = out;
+    sb[ecur.z + rowc] = P;
+    Acur = sb[enext.x + rowc];   // operand of step t + 1 (never written by step t)
+    ccur = cn;
+    ecur = enext;
+    enext = e2;
     lds_barrier();
   }
 
-  // Backward step t on block i = bblk(t): x_i = y_i - c_i T_i x_prev, with cbw[m] the coupling
-  // of node m to its successor in elimination order; refills the slot with step t + D.
-  template <int S>
-  __device__ __forceinline__ void bwd_step(int t, const C* T, int B, int BB, C* ybuf, C* zb,
-                                           const C* cbw) {
-    const bool own = owner_lane && row < B;
-    const int i = bblk(t);
-    C yi = mk((R)0, (R)0), ci = mk((R)0, (R)0);
-    if (own) {
-      yi = ybuf[i * B + row];
-      ci = cbw[i + 1];
-    }
-    const C acc = dot<S>(zb + (t & 1) * ZS);
-    load<S>(T, (unsigned)(bblk(t + D) * BB));
-    if (own) {
-      const C x = csub(yi, cmul(ci, acc));
-      ybuf[i * B + row] = x;
-      zb[((t + 1) & 1) * ZS + row] = x;
-    }
-    lds_barrier();
-  }
-
-  template <int S = 0> __device__ __forceinline__ void fwd_group(int t0, const C* T, int B, int BB,
-                                                                 C* ybuf, C* zb, const C* cfw) {
-    if constexpr (S < D) {
-      if (t0 + S < n_) {
-        fwd_step<S>(t0 + S, T, B, BB, ybuf, zb, cfw);
-        fwd_group<S + 1>(t0, T, B, BB, ybuf, zb, cfw);
-      }
-    }
-  }
   template <int S = 0>
-  __device__ __forceinline__ void bwd_group(int t0, const C* T, int B, int BB, C* ybuf, C* zb,
-                                            const C* cbw) {
+  __device__ __forceinline__ void group(int t0, C* sb, const C* zme, const C* zot, const int4* tab,
+                                        const C* ctab) {
     if constexpr (S < D) {
-      if (t0 + S < n_ - 1) {
-        bwd_step<S>(t0 + S, T, B, BB, ybuf, zb, cbw);
-        bwd_group<S + 1>(t0, T, B, BB, ybuf, zb, cbw);
+      if (t0 + S < steps) {
+        step<S>(t0 + S, sb, zme, zot, tab, ctab);
+        group<S + 1>(t0, sb, zme, zot, tab, ctab);
       }
     }
   }
 
-  // Solve with the factors T (n blocks) on the right-hand side in ybuf[i*B + q]; begin_line
-  // and fill_forward must have run, and ybuf must be complete (barrier).  cf[m] / cb[m] are
-  // the couplings of x1-node m to m-1 / m+1.  zb holds 2 * ZS values.  On return ybuf holds
-  // the solution (visible to the whole workgroup).  No global memory is touched besides the
-  // factor stream, so the wait before each ring slot is exact.
-  __device__ __forceinline__ void run(const C* T, int B, C* ybuf, C* zb, const C* cf, const C* cb) {
-    const int BB = B * B;
-    const C* cfw = fs > 0 ? cf : cb;
-    const C* cbw = fs > 0 ? cb : cf;
-    for (int e = threadIdx.x; e < 2 * ZS; e += blockDim.x) {
-      const int q = e < ZS ? e : e - ZS;
-      if (q >= B) zb[e] = mk((R)0, (R)0);
+  // Solve on the right-hand side in ybuf[i*B + q]; begin_line and fill must have run, and
+  // ybuf must be complete (barrier).  All LDS regions are given as element offsets from sb:
+  // zb (4 ZS values: two double-buffered published vectors per chain), zeros and junk (kZMax
+  // values each), ctab (2 (n + 2) couplings), tab (2 (n + 3) entries, 16 bytes each).  On
+  // return ybuf holds the solution (visible to the whole workgroup).  No global memory is
+  // touched besides the factor stream, so the wait before each ring slot is exact.
+  __device__ __forceinline__ void run(C* sb, int ybuf, int zb, int zeros, int junk, C* ctab,
+                                      int4* tab, const C* cf, const C* cb) {
+    const C zero = mk((R)0, (R)0);
+    const int B = B_, ts = steps + 2;   // table entries per chain
+    for (int e = threadIdx.x; e < 4 * ZS; e += blockDim.x)
+      if (e % ZS >= B) sb[zb + e] = zero;
+    // per chain and step: couplings (forward upper l_{i+1}, lower u_{i-1}; backward upper u_i,
+    // lower l_i; middle -1; block i is x1-node i + 1: l_i = cf[i + 1], u_i = cb[i + 1]) and
+    // the table {operand row, result row, published-vector row, prefetch offset}
+    for (int e = threadIdx.x; e < 2 * ts; e += blockDim.x) {
+      const int ch = e >= ts, t = e - ch * ts;
+      const int d = mid > t ? mid - t : t - mid;
+      const int i = ch ? mid + d : mid - d;
+      const bool valid = t < steps && i >= 0 && i < n_;
+      const int znext = zb + (2 * ch + ((t + 1) & 1)) * ZS;
+      C c = mk((R)-1, (R)0);
+      int4 en = make_int4(zeros, junk, junk, (int)((unsigned)blk(ch, t + D) * BBb));
+      if (t < mid) {
+        c = ch ? cb[i] : cf[i + 2];
+        const bool last_lower = ch && t == mid - 1;
+        en.x = last_lower ? zeros : ybuf + (ch ? i - 1 : i + 1) * B;
+        if (valid) {
+          en.y = ybuf + i * B;
+          en.z = znext;
+        }
+      } else if (t == mid) {
+        en.y = ch ? junk : ybuf + mid * B;
+        en.z = znext;
+      } else if (valid) {
+        c = ch ? cf[i + 1] : cb[i + 1];
+        en.x = ybuf + i * B;
+        en.y = ybuf + i * B;
+        en.z = znext;
+      }
+      ctab[e] = c;
+      tab[e] = en;
     }
-    if (owner_lane && row < B) zb[row] = ybuf[fblk(0) * B + row];   // first z = its q
+    if (row < B) {   // each chain starts from the q of its first block
+      if (!lower) sb[zb + row] = sb[ybuf + row];
+      else sb[zb + (2 + ((2 * mid - n_ + 1) & 1)) * ZS + row] = sb[ybuf + (n_ - 1) * B + row];
+    }
     lds_barrier();
-    for (int t0 = 0; t0 < n_; t0 += D)
-      fwd_group(__builtin_amdgcn_readfirstlane(t0), T, B, BB, ybuf, zb, cfw);
-    fill_backward(T, BB);
-    // the last block eliminated: x = y
-    if (owner_lane && row < B) zb[row] = ybuf[fblk(n_ - 1) * B + row];
-    lds_barrier();
-    for (int t0 = 0; t0 < n_ - 1; t0 += D)
-      bwd_group(__builtin_amdgcn_readfirstlane(t0), T, B, BB, ybuf, zb, cbw);
+    const int4* tb = tab + lower * ts;
+    const C* ct = ctab + lower * ts;
+    ecur = tb[0];
+    enext = tb[1];
+    ccur = ct[0];
+    Acur = sb[ecur.x + rowc];
+    const C* zme = sb + zb + lower * 2 * ZS;
+    const C* zot = sb + zb + (1 - lower) * 2 * ZS;
+    for (int t0 = 0; t0 < steps; t0 += D)
+      group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
   }
 };
 
+// threads of a launch: two chains of round-up-to-64(B * NC) threads each
+template <int NC, int CW> constexpr int max_threads() { return 2 * ((NC * NC * CW + 63) / 64 * 64); }
+
 template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ>
-__global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepArgs a) {
+__global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, G = a.G;
-  C* ybuf = reinterpret_cast<C*>(smem_raw);
-  C* zb = ybuf + (size_t)n * a.maxB;    // [2][NC*CW], zero-padded past B
-  C* cf = zb + 2 * kZMax;               // A'[m, m-1], m = 0..n+1
-  C* cb = cf + (n + 2);                 // A'[m, m+1]
+  const LdsLayout L(n, a.maxB, (int)sizeof(C));
+  C* sb = reinterpret_cast<C*>(smem_raw);
+  C* ybuf = sb + L.ybuf;
+  C* zeros = sb + L.zeros;
+  C* cf = sb + L.cf;                    // A'[m, m-1], m = 0..n+1
+  C* cb = sb + L.cb;                    // A'[m, m+1]
+  C* ctab = sb + L.ctab;
+  int4* tab = reinterpret_cast<int4*>(smem_raw + L.tab_byte);
   const int tid = threadIdx.x, NT = blockDim.x;
   const int q = a.rhs_idx ? a.rhs_idx[blockIdx.x] : (int)blockIdx.x;
   const TI* __restrict__ f = reinterpret_cast<const TI*>(a.in) + (long long)q * a.in_stride;
@@ -274,11 +334,12 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
     cf[m] = cvt<C>(a.coef[(ADJ ? 2 : 0) * (n + 2) + m]);
     cb[m] = cvt<C>(a.coef[(ADJ ? 3 : 1) * (n + 2) + m]);
   }
+  for (int m = tid; m < kZMax; m += NT) zeros[m] = mk((R)0, (R)0);
   __syncthreads();
   auto gidx = [&](int i, int j, int k) -> long long {  // i 0-based, j, k 1-based
     return ((long long)(k - 1) * n + (j - 1)) * n + i;
   };
-  LineSolver<R, NC, CW, D, ADJ> ls;
+  LineSolver<R, NC, CW, D, ADJ> ls(a.tpc);
 
   for (int pass = 0; pass < 2; ++pass) {
     const bool ofwd = pass == 0;
@@ -292,8 +353,8 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
         const GroupInfo gy = a.groups[l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
         const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-        ls.begin_line(B, n, (g + l) & 1);
-        ls.fill_forward(T, B * B);   // in flight while the line input is gathered
+        ls.begin_line(T, B, n);
+        ls.fill();   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
           const int jj = qq / Wz, kk = qq - jj * Wz;
@@ -317,7 +378,7 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
           ybuf[i * B + qq] = val;
         }
         __syncthreads();
-        ls.run(T, B, ybuf, zb, cf, cb);
+        ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb);
         // ---- line output on the group's rows: v = x (inner forward) or v -= x (backward) ----
         const int npy = j1 - j0 + 1;
         for (int e = tid; e < n * Wz * npy; e += NT) {
@@ -344,32 +405,37 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_sweep(SweepAr
 
 // Exact solve of a single line problem on its own grid (exposes the building block).
 template <typename R, int NC, int CW, int D, bool ADJ>
-__global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_line_solve(SweepArgs a, int g, int l) {
+__global__ void __launch_bounds__((max_threads<NC, CW>())) k_line_solve(SweepArgs a, int g, int l) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, G = a.G;
-  C* ybuf = reinterpret_cast<C*>(smem_raw);
-  C* zb = ybuf + (size_t)n * a.maxB;
-  C* cf = zb + 2 * kZMax;
-  C* cb = cf + (n + 2);
+  const LdsLayout L(n, a.maxB, (int)sizeof(C));
+  C* sb = reinterpret_cast<C*>(smem_raw);
+  C* ybuf = sb + L.ybuf;
+  C* zeros = sb + L.zeros;
+  C* cf = sb + L.cf;                    // A'[m, m-1], m = 0..n+1
+  C* cb = sb + L.cb;                    // A'[m, m+1]
+  C* ctab = sb + L.ctab;
+  int4* tab = reinterpret_cast<int4*>(smem_raw + L.tab_byte);
   const int tid = threadIdx.x, NT = blockDim.x;
   for (int m = tid; m < n + 2; m += NT) {
     cf[m] = cvt<C>(a.coef[(ADJ ? 2 : 0) * (n + 2) + m]);
     cb[m] = cvt<C>(a.coef[(ADJ ? 3 : 1) * (n + 2) + m]);
   }
+  for (int m = tid; m < kZMax; m += NT) zeros[m] = mk((R)0, (R)0);
   const int Wz = a.groups[g].W, Wy = a.groups[l].W, B = Wy * Wz;
   const double2* r = reinterpret_cast<const double2*>(a.in) + (long long)blockIdx.x * n * B;
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-  LineSolver<R, NC, CW, D, ADJ> ls;
-  ls.begin_line(B, n, (g + l) & 1);
-  ls.fill_forward(T, B * B);
+  LineSolver<R, NC, CW, D, ADJ> ls(a.tpc);
+  ls.begin_line(T, B, n);
+  ls.fill();
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
     ybuf[i * B + jj * Wz + kk] = cvt<C>(r[e]);
   }
   __syncthreads();
-  ls.run(T, B, ybuf, zb, cf, cb);
+  ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb);
   for (int e = tid; e < n * B; e += NT) {
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
     x[e] = cvt<double2>(ybuf[i * B + jj * Wz + kk]);
@@ -378,27 +444,28 @@ __global__ void __launch_bounds__((NC * NC * CW + 63) / 64 * 64) k_line_solve(Sw
 
 // ------------------------------------------------------------------------------------------
 // launch shapes: NC lanes per block row, CW columns per lane (NC * CW >= B), ring depth D
-// (registers: D * CW complex values per thread)
+// (registers: D * CW complex values per thread); two chains of round-up-to-64(B * NC) threads
 // ------------------------------------------------------------------------------------------
 struct Shape {
   int nc, cw;
 };
 
 Shape choose_shape(int maxB, int lanes) {
-  // default: 16 lanes per block row up to B = 48 (measured fastest at B = 36 in both
-  // precisions), 4 lanes beyond (16 x 4 columns would not fit the register budget); CW is
-  // the smallest instantiated column count covering B
-  const int nc = lanes ? lanes : (maxB <= 48 ? 16 : 4);
+  // default: 8 lanes per block row up to B = 40 (measured fastest for two chains at B = 36),
+  // 4 lanes beyond (8 x 7 columns leaves too few registers for the factor ring); 16 lanes
+  // only fit two chains in one workgroup up to B = 32.  CW is the smallest instantiated
+  // column count covering B.
+  const int nc = lanes ? lanes : (maxB <= 40 ? 8 : 4);
   const int need = (maxB + nc - 1) / nc;
-  static const int cw4[] = {4, 7, 9, 13, 16}, cw8[] = {4, 8}, cw16[] = {1, 2, 3, 4};
+  static const int cw4[] = {5, 7, 9, 13, 16}, cw8[] = {3, 4, 5, 7, 8}, cw16[] = {1, 2};
   const int* t = nc == 4 ? cw4 : (nc == 8 ? cw8 : cw16);
-  const int cnt = nc == 4 ? 5 : (nc == 8 ? 2 : 4);
+  const int cnt = nc == 16 ? 2 : 5;
   for (int k = 0; k < cnt; ++k)
     if (t[k] >= need) return {nc, t[k]};
   return {nc, -1};
 }
 
-inline int block_threads(int maxB, int nc) { return ((maxB * nc + 63) / 64) * 64; }
+inline int chain_threads(int maxB, int nc) { return ((maxB * nc + 63) / 64) * 64; }
 
 template <typename K, typename... Args>
 hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Args... args) {
@@ -409,31 +476,39 @@ hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Arg
   return hipGetLastError();
 }
 
-// the instantiated shapes: (NC, CW, ring depth for complex64, ring depth for complex128)
-#define HELM_SHAPES(X)                                                             \
-  X(4, 4, 16, 12) X(4, 7, 10, 6) X(4, 9, 8, 4) X(4, 13, 5, 3) X(4, 16, 4, 2)       \
-  X(8, 4, 12, 6) X(8, 8, 6, 4) X(16, 1, 16, 16) X(16, 2, 16, 12) X(16, 3, 12, 6)
+// the instantiated shapes: (NC, CW, ring depth for complex64, ring depth for complex128),
+// depths sized so that the ring fits the register budget of the shape's largest launch; depth
+// 0: not built (complex128 with 8 x 7 or 8 x 8 columns leaves no registers for a ring)
+#define HELM_SHAPES(X)                                                                  \
+  X(4, 5, 16, 12) X(4, 7, 16, 12) X(4, 9, 8, 4) X(4, 13, 6, 2) X(4, 16, 4, 2)          \
+  X(8, 3, 16, 12) X(8, 4, 16, 10) X(8, 5, 8, 4) X(8, 7, 4, 0) X(8, 8, 2, 0)            \
+  X(16, 1, 16, 16) X(16, 2, 16, 8)
 
 template <typename R, typename TI, typename TO, bool ADJ>
-hipError_t dispatch_sweep(Shape sh, int maxB, int grid, size_t sm, hipStream_t s, SweepArgs a) {
-  const int t = block_threads(maxB, sh.nc);
+hipError_t dispatch_sweep(Shape sh, int grid, size_t sm, hipStream_t s, SweepArgs a) {
+  const int t = 2 * a.tpc;
   constexpr bool c64 = sizeof(R) == 4;
 #define X(NC, CW, D64, D128)                                                              \
-  if (sh.nc == NC && sh.cw == CW)                                                         \
-    return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a);
+  if (sh.nc == NC && sh.cw == CW) {                                                       \
+    if constexpr ((c64 ? D64 : D128) > 0)                                                 \
+      return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a); \
+    return hipErrorInvalidValue;                                                          \
+  }
   HELM_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 template <typename R, bool ADJ>
-hipError_t dispatch_line(Shape sh, int maxB, int grid, size_t sm, hipStream_t s, SweepArgs a, int g,
-                         int l) {
-  const int t = block_threads(maxB, sh.nc);
+hipError_t dispatch_line(Shape sh, int grid, size_t sm, hipStream_t s, SweepArgs a, int g, int l) {
+  const int t = 2 * a.tpc;
   constexpr bool c64 = sizeof(R) == 4;
 #define X(NC, CW, D64, D128)                                                              \
-  if (sh.nc == NC && sh.cw == CW)                                                         \
-    return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a, g, l);
+  if (sh.nc == NC && sh.cw == CW) {                                                       \
+    if constexpr ((c64 ? D64 : D128) > 0)                                                 \
+      return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a, g, l); \
+    return hipErrorInvalidValue;                                                          \
+  }
   HELM_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
@@ -445,6 +520,7 @@ SweepArgs base_args(helm_handle* h) {
   a.G = h->plan.G;
   a.maxW = h->plan.maxW;
   a.maxB = h->plan.maxB;
+  a.tpc = 0;
   a.N = (long long)h->n * h->n * h->n;
   a.in_stride = a.out_stride = a.N;
   a.groups = h->d_groups;
@@ -459,7 +535,7 @@ SweepArgs base_args(helm_handle* h) {
 }
 
 size_t sweep_lds(const helm_handle* h, size_t csz) {
-  return ((size_t)h->n * h->plan.maxB + 2 * (size_t)kZMax + 2 * (size_t)(h->n + 2)) * csz;
+  return LdsLayout(h->n, h->plan.maxB, (int)csz).bytes;
 }
 
 }  // namespace
@@ -494,19 +570,20 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   const int mb = h->plan.maxB;
   const Shape sh = choose_shape(mb, h->lanes_override);
   if (sh.cw < 0) return hipErrorInvalidValue;
+  a.tpc = chain_threads(mb, sh.nc);
   if (!r64) return hipErrorInvalidValue;  // inputs are always complex128
   if (!c64 && !z64) return hipErrorInvalidValue;
   hipEvent_t ev = h->t_apply.begin(s);
   hipError_t e;
   if (!c64)
-    e = adjoint ? dispatch_sweep<double, double2, double2, true>(sh, mb, R, sm, s, a)
-                : dispatch_sweep<double, double2, double2, false>(sh, mb, R, sm, s, a);
+    e = adjoint ? dispatch_sweep<double, double2, double2, true>(sh, R, sm, s, a)
+                : dispatch_sweep<double, double2, double2, false>(sh, R, sm, s, a);
   else if (z64)
-    e = adjoint ? dispatch_sweep<float, double2, double2, true>(sh, mb, R, sm, s, a)
-                : dispatch_sweep<float, double2, double2, false>(sh, mb, R, sm, s, a);
+    e = adjoint ? dispatch_sweep<float, double2, double2, true>(sh, R, sm, s, a)
+                : dispatch_sweep<float, double2, double2, false>(sh, R, sm, s, a);
   else
-    e = adjoint ? dispatch_sweep<float, double2, float2, true>(sh, mb, R, sm, s, a)
-                : dispatch_sweep<float, double2, float2, false>(sh, mb, R, sm, s, a);
+    e = adjoint ? dispatch_sweep<float, double2, float2, true>(sh, R, sm, s, a)
+                : dispatch_sweep<float, double2, float2, false>(sh, R, sm, s, a);
   h->t_apply.end(ev, s, R);
   return e;
 }
@@ -522,9 +599,10 @@ hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, d
   const int mb = h->plan.maxB;
   const Shape sh = choose_shape(mb, h->lanes_override);
   if (sh.cw < 0) return hipErrorInvalidValue;
+  a.tpc = chain_threads(mb, sh.nc);
   if (c64)
-    return adjoint ? dispatch_line<float, true>(sh, mb, R, sm, s, a, zg, yg)
-                   : dispatch_line<float, false>(sh, mb, R, sm, s, a, zg, yg);
-  return adjoint ? dispatch_line<double, true>(sh, mb, R, sm, s, a, zg, yg)
-                 : dispatch_line<double, false>(sh, mb, R, sm, s, a, zg, yg);
+    return adjoint ? dispatch_line<float, true>(sh, R, sm, s, a, zg, yg)
+                   : dispatch_line<float, false>(sh, R, sm, s, a, zg, yg);
+  return adjoint ? dispatch_line<double, true>(sh, R, sm, s, a, zg, yg)
+                 : dispatch_line<double, false>(sh, R, sm, s, a, zg, yg);
 }

@@ -1,8 +1,8 @@
 """GPU parity of the HIP path against the oracle, element by element, on seeded inputs.
 
 Sizes are small enough for the oracle to finish in seconds but span several groups, block
-sizes B that are not multiples of the lanes per row, and (case "ragged") a last group shorter
-than d.  Tolerances:
+sizes B that are not multiples of the lanes per row, (case "ragged") a last group shorter
+than d, odd and even line lengths n, and the shortest lines the method allows (n = 3, 4).  Tolerances:
   complex128 path: rounding only -> relative error <= 1e-10 for every operator;
   complex64 path : the factors and sweeps run in complex64 (unit roundoff 6e-8); each line
                    solve amplifies rounding by at most the conditioning of its blocks, and the
@@ -22,6 +22,9 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "b4p4": dict(n=15, b=4, p=4, d=1),
     "ragged": dict(n=16, b=3, p=2, d=2),
+    # the shortest lines: n = 3 has no lower chain in the two-sided line solve, n = 4 one block
+    "tiny3": dict(n=3, b=1, p=1, d=1),
+    "tiny4": dict(n=4, b=1, p=1, d=1),
 }
 _cache = {}
 
@@ -77,9 +80,8 @@ def test_line_factors(name, prec, tol):
     worst = 0.0
     for g, l, ln in M.lines():
         T = H.line_factors(g, l).cpu().numpy()
-        # lines with g + l odd are eliminated in reverse x1 order
-        if (g + l) % 2:
-            ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, reverse=True)
+        # the library eliminates the x1-blocks from both ends towards the middle
+        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order="two-sided")
         ref = np.stack(ln.block_T)
         assert T.shape == ref.shape
         e = max(rel(T[i], ref[i]) for i in range(prob.n))
@@ -94,7 +96,9 @@ def test_line_solve(name, adjoint):
     sc, prob, M = case(name)
     H = helm(name, "c128")
     rng = np.random.default_rng(3)
-    for (g, l) in [(0, 0), (1, 0), (0, 2), (3, 5), (len(M.Gz) - 1, len(M.Gy) - 1)]:
+    Gz, Gy = len(M.Gz), len(M.Gy)
+    picks = [(0, 0), (1, 0), (0, 2), (3, 5), (Gz - 1, Gy - 1)]
+    for (g, l) in [(g, l) for (g, l) in picks if g < Gz and l < Gy]:
         ln = M.slabs[g].lines[l]
         Nl = ln.K.shape[0]
         r = rng.standard_normal((2, Nl)) + 1j * rng.standard_normal((2, Nl))

@@ -45,28 +45,33 @@ def test_moving_profile_matches_shifted_boundary_profile():
     assert prof.half[-1] == 1.0
 
 
-def test_line_ldu_reproduces_line_matrix_and_dense_solve():
+@pytest.mark.parametrize("order", ["up", "down", "two-sided"])
+def test_line_ldu_reproduces_line_matrix_and_dense_solve(order):
     prob = _prob(n=9, b=3, p=2)
     M = O.RecursiveSweep(prob)
     rng = np.random.default_rng(5)
     checked = 0
-    for g, l, ln in M.lines():
+    for g, l, _ in M.lines():
         if (g, l) not in [(0, 0), (0, 2), (2, 0), (3, 4), (6, 6)]:
             continue
+        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order=order)
         K = ln.K.toarray()
         Nl = K.shape[0]
-        # block-ordered K and the product of the factors: Lc has diagonal S_i = T_i^{-1} and
-        # sub-diagonal K_{i+1,i}; Uc is unit upper with T_i K_{i,i+1}
-        perm = np.concatenate(ln.sel)
-        Kb = K[np.ix_(perm, perm)]
+        # K with its blocks in elimination order equals Lc Uc: Lc has the diagonal blocks
+        # S_i = T_i^{-1} and K_ij below it (j eliminated before i), Uc is unit upper with T_j K_ji
         B, n = ln.B, ln.n
+        pos = {i: t for t, i in enumerate(ln.order)}
+        perm = np.concatenate([ln.sel[i] for i in ln.order])
+        Kb = K[np.ix_(perm, perm)]
         Lc = np.zeros_like(Kb)
         Uc = np.eye(Nl, dtype=complex)
+        blk = lambda i: slice(pos[i] * B, (pos[i] + 1) * B)
         for i in range(n):
-            Lc[i * B:(i + 1) * B, i * B:(i + 1) * B] = np.linalg.inv(ln.T[i])
-            if i + 1 < n:
-                Lc[(i + 1) * B:(i + 2) * B, i * B:(i + 1) * B] = ln.lo[i].toarray()
-                Uc[i * B:(i + 1) * B, (i + 1) * B:(i + 2) * B] = ln.T[i] @ ln.up[i].toarray()
+            Lc[blk(i), blk(i)] = np.linalg.inv(ln.block_T[i])
+            for j in (i - 1, i + 1):
+                if 0 <= j < n and pos[j] < pos[i]:
+                    Lc[blk(i), blk(j)] = ln.Kc[(i, j)].toarray()
+                    Uc[blk(j), blk(i)] = ln.block_T[j] @ ln.Kc[(j, i)].toarray()
         assert np.linalg.norm(Lc @ Uc - Kb) <= 1e-12 * np.linalg.norm(Kb)
         r = rng.standard_normal((Nl, 2)) + 1j * rng.standard_normal((Nl, 2))
         assert _rel(ln.solve(r), np.linalg.solve(K, r)) < 1e-12
@@ -75,22 +80,27 @@ def test_line_ldu_reproduces_line_matrix_and_dense_solve():
     assert checked == 5
 
 
-def test_reverse_order_ldu_solves_the_same_line():
-    """The block LDU with the x1-blocks taken in reverse order solves the same line problem."""
-    prob = _prob(n=9, b=3, p=2)
+@pytest.mark.parametrize("n", [9, 10])
+def test_line_factor_ends_are_exact_blocks(n):
+    """The first block eliminated has T = K_ii^{-1}; the last one has T = (K^{-1})_ii (its
+    Schur complement is the whole matrix condensed onto it), in every elimination order."""
+    prob = _prob(n=n, b=3, p=2)
     from oracle.partition import groups
     Gz = groups(prob.n, prob.b, prob.d)
-    rng = np.random.default_rng(8)
-    for (g, l) in [(0, 1), (2, 3), (5, 2)]:
-        fwd = O.LineFactors(prob, Gz, g, Gz, l)
-        rev = O.LineFactors(prob, Gz, g, Gz, l, reverse=True)
-        Nl = fwd.K.shape[0]
-        r = rng.standard_normal((Nl, 2)) + 1j * rng.standard_normal((Nl, 2))
-        assert _rel(rev.solve(r), fwd.solve(r)) < 1e-12
-        assert _rel(rev.solve_adjoint(r), fwd.solve_adjoint(r)) < 1e-12
-        # the first block eliminated upwards is the last one eliminated downwards: both are D^{-1}
-        assert np.allclose(rev.block_T[prob.n - 1], np.linalg.inv(rev.K[rev.sel[0]][:, rev.sel[0]].toarray()))
-        assert np.allclose(fwd.block_T[0], np.linalg.inv(fwd.K[fwd.sel[0]][:, fwd.sel[0]].toarray()))
+    for (g, l) in [(0, 1), (2, 3), (4, 2)]:
+        for order in ["up", "down", "two-sided"]:
+            ln = O.LineFactors(prob, Gz, g, Gz, l, order=order)
+            K = ln.K.toarray()
+            Kinv = np.linalg.inv(K)
+            first, last = ln.order[0], ln.order[-1]
+            s0, s1 = ln.sel[first], ln.sel[last]
+            assert np.allclose(ln.block_T[first], np.linalg.inv(K[np.ix_(s0, s0)]), rtol=1e-12, atol=0)
+            ref = Kinv[np.ix_(s1, s1)]
+            assert np.linalg.norm(ln.block_T[last] - ref) <= 1e-10 * np.linalg.norm(ref)
+        two = O.elimination_order(n, "two-sided")
+        m = n // 2
+        assert two[-1] == m and sorted(two) == list(range(n))
+        assert two[:m] == list(range(m)) and two[m:-1] == list(range(n - 1, m, -1))
 
 
 def test_degenerate_single_groups_give_exact_inverse():
