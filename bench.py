@@ -43,6 +43,24 @@ def run_step(Helm, c, wl, F, prec):
     return H, u, its, rel, rc, st
 
 
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the committed counter run (FETCH_SIZE and WRITE_SIZE of
+    one 32-right-hand-side launch, each scaled by what the counter reads for a plain copy of
+    known size), or None when that run does not cover this workload or the sweep source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_sweep_c64_127cubed_32rhs_traffic.json")
+    src = os.path.join(ROOT, "paper_1502_07266_amd", "csrc", "sweep.hip")
+    if workload != "c3" or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec.get("sweep_source_sha256"):
+            return None
+    return rec
+
+
 def cpu_baseline(wl, iters, budget_s):
     """Oracle (numpy/scipy complex128, BLAS limited to one thread) on a bounded sample: the
     full factorisation of a few interior line problems and repeated single-right-hand-side
@@ -139,6 +157,9 @@ def main():
     sec_per_step = (t1 - t0) / args.steps
 
     apply_avg_ms = tot["apply_ms"] / max(tot["apply_launches"], 1)
+    # dependent block steps of one sweep: (2G - 1)^2 line solves of 2 (n/2) + 1 two-sided steps
+    G = 1 + -(-(n - wl["b"]) // wl["d"])
+    steps_per_sweep = (2 * G - 1) ** 2 * (2 * (n // 2) + 1)
     apply_bytes_per_launch = bpr * tot["apply_rhs"] / max(tot["apply_launches"], 1)
     achieved = apply_bytes_per_launch / (apply_avg_ms * 1e-3) / 1e9
     mv_gbs = mvb * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
@@ -165,6 +186,7 @@ def main():
                      "kernel": "k_sweep (complex64)", "avg_launch_ms": round(apply_avg_ms, 3),
                      "algorithmic_bytes_per_launch": apply_bytes_per_launch,
                      "chains_sharing_factor_stream": R},
+        "ns_per_dependent_step": round(apply_avg_ms * 1e6 / steps_per_sweep, 1),
         "iters": its_mix.tolist(),
         "relres_max": float(rel_mix.max()),
         "setup_ms": round(tot["setup_ms"] / args.steps, 2),
@@ -172,6 +194,13 @@ def main():
         "apply_launches_per_step": tot["apply_launches"] / args.steps,
         "matvec_gbs": round(mv_gbs, 1),
     }
+    tr = measured_traffic(args.workload)
+    if tr is not None:
+        result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+        result["roofline"]["traffic_gbs"] = round(tr["hbm_bytes_per_launch"] / (tr["apply_ms"] * 1e-3) / 1e9, 1)
+        result["roofline"]["traffic_note"] = ("HBM bytes of one 32-right-hand-side sweep launch "
+                                              "(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), "
+                                              "profiles/k_sweep_c64_127cubed_32rhs_traffic.json")
     log(f"mixed: {sec_per_step:.3f} s/step, sweep {achieved:.0f} GB/s algorithmic")
 
     if not args.no_fp64:

@@ -1,0 +1,66 @@
+"""Driver for hardware-counter runs of the sweep: one plain copy of a known size, then one
+batched sweep (helm_apply) of a workload, each a single kernel dispatch.
+
+    python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024
+
+Run it under `rocprofv3 --pmc FETCH_SIZE ...` and again under `--pmc WRITE_SIZE ...`: the
+copy kernel reads and writes exactly copy-mib MiB, which calibrates what the counters report
+per byte, and the sweep dispatch gives the sweep's memory traffic beyond L2.  Prints the
+device times of both (HIP events) and the sweep's algorithmic bytes.
+"""
+import argparse
+import json
+import time
+
+import torch
+
+from . import inputs
+from .binding import Helm
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--rhs", type=int, default=0, help="right-hand sides (0: all of the workload)")
+    args = ap.parse_args()
+
+    wl = inputs.workload(args.workload)
+    n = wl["n"]
+    nodes = wl["nodes"] if args.rhs <= 0 else wl["nodes"][:args.rhs]
+    R = len(nodes)
+    dev = torch.device("cuda:0")
+
+    nbytes = args.copy_mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1)
+    print(f"[profile] copy {args.copy_mib} MiB: {copy_ms:.3f} ms", flush=True)
+    del src, dst
+
+    c = torch.from_numpy(wl["c"]).to(dev)
+    F = torch.from_numpy(inputs.sources(n, nodes)).to(dev)
+    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec)
+    H.reset_stats()
+    t0 = time.perf_counter()
+    H.apply(F)
+    torch.cuda.synchronize()
+    st = H.stats()
+    print(f"[profile] apply {args.prec} R={R}: {st['apply_ms']:.1f} ms "
+          f"(host {1e3 * (time.perf_counter() - t0):.1f} ms)", flush=True)
+    print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R,
+                      "copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": copy_ms,
+                      "apply_ms": st["apply_ms"],
+                      "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R}), flush=True)
+    H.close()
+
+
+if __name__ == "__main__":
+    main()
