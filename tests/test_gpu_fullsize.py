@@ -1,0 +1,127 @@
+"""GPU parity at the workloads' full sizes.
+
+31^3 (plain method, complex128): the whole preconditioner is compared element by element with
+the oracle's Algorithm 6 on seeded right-hand sides, and the solve with a sparse direct solve.
+127^3 (the batched mixed-precision workload): the oracle cannot run a whole sweep in seconds,
+so sampled line factorisations are compared block by block with the oracle's, and the sweep is
+checked through properties that hold at any size: the adjoint dot test
+<M^{-1} x, y> = <x, M^{-H} y>, linearity, and the distance between the complex64 and the
+complex128 sweeps.  Tolerances as in test_gpu_parity.py; the complex64 sweep composes
+(2G - 1)^2 = 60 025 line solves at 127^3 and is allowed 1e-3.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from oracle.partition import groups
+from paper_1502_07266_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        wl = inputs.workload(name)
+        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"])
+        _cache[name] = (wl, prob)
+    return _cache[name]
+
+
+def helm(wl, prec):
+    from paper_1502_07266_amd.binding import Helm
+    c = torch.from_numpy(wl["c"]).cuda()
+    return Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def cdot(a, b):
+    return complex(torch.sum(torch.conj(a) * b).item())
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    wl, prob = workload("c1")
+    return wl, prob, O.RecursiveSweep(prob)
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+def test_c1_apply_matches_oracle(c1_oracle, prec, tol):
+    wl, prob, M = c1_oracle
+    n = wl["n"]
+    x = inputs.random_rhs(n, 2, seed=21)
+    H = helm(wl, prec)
+    z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    H.close()
+    ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
+    err = rel(z, ref)
+    print(f"c1 apply {prec}: rel err {err:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_c1_solve_matches_direct_solve(c1_oracle, prec):
+    wl, prob, M = c1_oracle
+    n = wl["n"]
+    f = inputs.sources(n, wl["nodes"])
+    H = helm(wl, prec)
+    u, its, relres, rc = H.solve(torch.from_numpy(f).cuda(), tol=1e-10, restart=50, maxit=200)
+    H.close()
+    assert rc == 0
+    ref = spla.spsolve(M.A.tocsc(), f.reshape(len(f), -1).T).T.reshape(f.shape)
+    err = rel(u.cpu().numpy(), ref)
+    print(f"c1 solve {prec}: iterations {its.tolist()}, rel err vs direct {err:.2e}")
+    assert err <= 1e-8
+
+
+@pytest.fixture(scope="module")
+def c3_handles():
+    wl, prob = workload("c3")
+    H128 = helm(wl, "c128")
+    H64 = helm(wl, "c64")
+    yield wl, prob, H128, H64
+    H128.close()
+    H64.close()
+
+
+def test_c3_sampled_line_factors(c3_handles):
+    wl, prob, H128, H64 = c3_handles
+    G = groups(wl["n"], wl["b"], wl["d"])
+    last = len(G) - 1
+    for (g, l) in [(0, 0), (0, last), (last // 2, last // 2 + 1), (last, 3)]:
+        ln = O.LineFactors(prob, G, g, G, l, order="two-sided")
+        ref = np.stack(ln.block_T)
+        for H, tol in [(H128, 1e-10), (H64, 1e-3)]:
+            T = H.line_factors(g, l).cpu().numpy()
+            err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
+            print(f"c3 line ({g}, {l}) B={ln.B} {H.prec}: worst block rel err {err:.2e}")
+            assert err <= tol
+
+
+def test_c3_sweep_dot_test_and_linearity(c3_handles):
+    wl, prob, H128, H64 = c3_handles
+    n = wl["n"]
+    x = torch.from_numpy(inputs.random_rhs(n, 1, seed=31)).cuda()
+    y = torch.from_numpy(inputs.random_rhs(n, 1, seed=32)).cuda()
+    Mx = H128.apply(x)
+    MHy = H128.apply(y, adjoint=True)
+    lhs, rhs = cdot(Mx, y), cdot(x, MHy)
+    dot_err = abs(lhs - rhs) / abs(lhs)
+    # linearity: M^{-1}(2x + 3iy) = 2 M^{-1}x + 3i M^{-1}y
+    My = H128.apply(y)
+    comb = H128.apply(2 * x + 3j * y)
+    lin_err = float((comb - (2 * Mx + 3j * My)).norm() / comb.norm())
+    print(f"c3 complex128 sweep: dot test {dot_err:.2e}, linearity {lin_err:.2e}")
+    assert dot_err <= 1e-10
+    assert lin_err <= 1e-10
+    # complex64 sweep against complex128 on the same input
+    Mx64 = H64.apply(x)
+    prec_err = float((Mx64 - Mx).norm() / Mx.norm())
+    print(f"c3 complex64 vs complex128 sweep: {prec_err:.2e}")
+    assert prec_err <= 1e-3
