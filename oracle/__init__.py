@@ -29,13 +29,13 @@ Parity status of each function is recorded in its module docstring.
 
 from .problem import (Problem, sigma, stretch, boundary_profile, axis_profile,
                       assemble_box, helmholtz_matrix)
-from .partition import groups, window
+from .partition import groups, groups_two_fronts, window, window_fronts
 from .sweep import LineFactors, SlabSweep, RecursiveSweep, elimination_order
 from .krylov import fgmres
 from .gradient import misfit_and_gradient
 
 __all__ = [
     "Problem", "sigma", "stretch", "boundary_profile", "axis_profile", "assemble_box",
-    "helmholtz_matrix", "groups", "window", "LineFactors", "SlabSweep", "RecursiveSweep", "elimination_order",
+    "helmholtz_matrix", "groups", "groups_two_fronts", "window", "window_fronts", "LineFactors", "SlabSweep", "RecursiveSweep", "elimination_order",
     "fgmres", "misfit_and_gradient",
 ]

@@ -58,6 +58,15 @@ def moving_profile(t, first_phys, p, n, C, omega):
     return stretch(sigma(xi, (p + 1) * h, C), omega)
 
 
+def moving_profile_above(t, last_phys, p, n, C, omega):
+    """Mirror image of ``moving_profile``: a moving PML of p cells right above node
+    ``last_phys``, its zero-Dirichlet plane p+1 spacings above that node (the auxiliary
+    problems of a front sweeping from x = 1 downwards, Sec. 4.2 note on PML on all faces)."""
+    h = 1.0 / (n + 1)
+    xi = 0.5 * (2 * (last_phys + p + 1) - np.asarray(t, dtype=np.float64)) * h
+    return stretch(sigma(xi, (p + 1) * h, C), omega)
+
+
 @dataclass
 class AxisProfile:
     """s along one axis of a window [w0, w1] (1-based global node indices).
@@ -71,10 +80,11 @@ class AxisProfile:
     half: np.ndarray
 
 
-def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0):
+def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0, last_phys=None):
     """Profile of a window.  With ``first_phys`` set, positions strictly below that node use
     the moving PML (the auxiliary profile replaces the original one there, Sec. 3 and 4.1);
-    positions at or above it keep the boundary profile, including the far-face PML."""
+    with ``last_phys`` set, positions strictly above that node use the mirrored moving PML;
+    all other positions keep the boundary profile, including the far-face PML."""
     m = np.arange(w0, w1 + 1)
     t_node = 2 * m
     t_half = 2 * np.arange(w0, w1 + 2) - 1
@@ -85,6 +95,11 @@ def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0):
         below_h = t_half < 2 * first_phys
         node = np.where(below_n, moving_profile(t_node, first_phys, p, n, C, omega), node)
         half = np.where(below_h, moving_profile(t_half, first_phys, p, n, C, omega), half)
+    if last_phys is not None:
+        above_n = t_node > 2 * last_phys
+        above_h = t_half > 2 * last_phys
+        node = np.where(above_n, moving_profile_above(t_node, last_phys, p, n, C, omega), node)
+        half = np.where(above_h, moving_profile_above(t_half, last_phys, p, n, C, omega), half)
     return AxisProfile(w0, w1, node, half)
 
 
@@ -134,7 +149,9 @@ class Problem:
     indexed [k, j, i] (x3, x2, x1); omega; b: boundary PML cells (eta = b h); C: the constant
     of sigma; p: moving-PML cells; d: physical layers per auxiliary problem (same in x2 and
     x3); first_y / first_z: size of the first group along x2 / x3 (b by default; other
-    values only serve the degenerate-partition pins).
+    values only serve the degenerate-partition pins); fronts: 1 for the single-front outer
+    sweep of Algorithm 6, 2 for the outer sweep from both x3-faces meeting in a middle slab
+    (the configuration of the paper's experiments, Sec. 4.2 note 3 and Sec. 5).
     """
     n: int
     c: np.ndarray
@@ -145,6 +162,7 @@ class Problem:
     d: int = 1
     first_y: Optional[int] = None
     first_z: Optional[int] = None
+    fronts: int = 1
     h: float = field(init=False)
 
     def __post_init__(self):

@@ -36,7 +36,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .problem import axis_profile, assemble_box, helmholtz_matrix
-from .partition import groups, window
+from .partition import groups, groups_two_fronts, window, window_fronts
 
 
 def _dense_times_sparse(M, S):
@@ -81,11 +81,11 @@ class LineFactors:
 
     def __init__(self, prob, Gz, zg, Gy, yg, order="up"):
         n, h = prob.n, prob.h
-        zw0, zw1, zfirst = window(Gz, zg, prob.p)
+        zw0, zw1, zfirst, zlast = window_fronts(Gz, zg, prob.p, prob.fronts)
         yw0, yw1, yfirst = window(Gy, yg, prob.p)
         px = prob.boundary_axis()
         py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p)
-        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p)
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast)
         K = assemble_box(prob.kappa[zw0 - 1:zw1, yw0 - 1:yw1, :], px, py, pz, h)
         self.Wy, self.Wz = yw1 - yw0 + 1, zw1 - zw0 + 1
         self.n, self.B = n, self.Wy * self.Wz
@@ -156,16 +156,16 @@ class SlabSweep:
 
     def __init__(self, prob, Gz, zg, Gy):
         n = prob.n
-        zw0, zw1, zfirst = window(Gz, zg, prob.p)
+        zw0, zw1, zfirst, zlast = window_fronts(Gz, zg, prob.p, prob.fronts)
         ax = prob.boundary_axis()
-        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p)
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast)
         self.H = assemble_box(prob.kappa[zw0 - 1:zw1], ax, ax, pz, prob.h)
         self.HH = self.H.conj().T.tocsr()
         self.Wz = zw1 - zw0 + 1
         idx = np.arange(self.H.shape[0]).reshape(self.Wz, n, n)
         self.rows = [idx[:, a - 1:e, :].ravel() for (a, e) in Gy]
         a, e = Gz[zg]
-        self.phys = idx[self.Wz - (e - a + 1):, :, :].ravel()
+        self.phys = idx[a - zw0:e - zw0 + 1, :, :].ravel()
         self.lines = [LineFactors(prob, Gz, zg, Gy, yg) for yg in range(len(Gy))]  # Alg. 3
 
     def _line(self, yg, alpha, adjoint):
@@ -195,12 +195,21 @@ class SlabSweep:
 
 class RecursiveSweep:
     """Algorithm 5 (setup) and Algorithm 6 (apply) of Sec. 4.2; ``apply(.., adjoint=True)``
-    gives M^{-H} (module docstring).  Vectors are ordered x1 fastest (Sec. 3)."""
+    gives M^{-H} (module docstring).  Vectors are ordered x1 fastest (Sec. 3).
+
+    With ``prob.fronts == 2`` the outer sweep runs from both x3-faces (Sec. 4.2 note 3, the
+    configuration of Sec. 5): the block LDU of Algorithm 6 with the x3-groups eliminated in
+    the order 0..mid-1 (upwards), G-1..mid+1 (downwards), mid, each Schur complement replaced
+    by the auxiliary problem padded on its eliminated side(s) (``partition.window_fronts``);
+    forward, the two fronts carry f - A u from their eliminated neighbour and the middle group
+    takes both; backward, each front subtracts the correction from the neighbour nearer the
+    middle.  The inner sweep is the single-front Algorithm 4 either way."""
 
     def __init__(self, prob):
         self.prob = prob
         n = prob.n
-        self.Gz = groups(n, prob.first_z, prob.d)
+        self.Gz = (groups_two_fronts(n, prob.b, prob.d) if prob.fronts == 2
+                   else groups(n, prob.first_z, prob.d))
         self.Gy = groups(n, prob.first_y, prob.d)
         self.A = helmholtz_matrix(prob)
         self.AH = self.A.conj().T.tocsr()
@@ -216,6 +225,8 @@ class RecursiveSweep:
         return s.apply(gv, adjoint)[s.phys]
 
     def apply(self, f, adjoint=False):
+        if self.prob.fronts == 2:
+            return self._apply_two_fronts(f, adjoint)
         A = self.AH if adjoint else self.A
         f = _cols(f)
         u = np.zeros(f.shape, np.complex128)
@@ -228,6 +239,33 @@ class RecursiveSweep:
             u[Ls[g]] = self._TT(g, rhs, adjoint)
         for g in range(G - 2, -1, -1):
             u[Ls[g]] = u[Ls[g]] - self._TT(g, A[Ls[g]][:, Ls[g + 1]] @ u[Ls[g + 1]], adjoint)
+        return u
+
+    def _apply_two_fronts(self, f, adjoint):
+        A = self.AH if adjoint else self.A
+        f = _cols(f)
+        u = np.zeros(f.shape, np.complex128)
+        Ls = self.layers
+        G = len(Ls)
+        mid = G // 2
+        blk = lambda g, h: A[Ls[g]][:, Ls[h]]
+        for g in range(mid):                              # front from x3 = 0, upwards
+            rhs = f[Ls[g]].astype(np.complex128)
+            if g > 0:
+                rhs = rhs - blk(g, g - 1) @ u[Ls[g - 1]]
+            u[Ls[g]] = self._TT(g, rhs, adjoint)
+        for g in range(G - 1, mid, -1):                   # front from x3 = 1, downwards
+            rhs = f[Ls[g]].astype(np.complex128)
+            if g < G - 1:
+                rhs = rhs - blk(g, g + 1) @ u[Ls[g + 1]]
+            u[Ls[g]] = self._TT(g, rhs, adjoint)
+        rhs = (f[Ls[mid]] - blk(mid, mid - 1) @ u[Ls[mid - 1]]
+               - blk(mid, mid + 1) @ u[Ls[mid + 1]])      # the middle group, both sides
+        u[Ls[mid]] = self._TT(mid, rhs, adjoint)
+        for g in range(mid - 1, -1, -1):
+            u[Ls[g]] = u[Ls[g]] - self._TT(g, blk(g, g + 1) @ u[Ls[g + 1]], adjoint)
+        for g in range(mid + 1, G):
+            u[Ls[g]] = u[Ls[g]] - self._TT(g, blk(g, g - 1) @ u[Ls[g - 1]], adjoint)
         return u
 
     def lines(self):

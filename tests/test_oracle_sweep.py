@@ -182,3 +182,85 @@ def test_preconditioner_is_close_to_inverse():
     z = M.apply(f)[:, 0]
     assert _rel(z, x) < 0.8
     assert np.linalg.norm(f - M.A @ z) < 0.8 * np.linalg.norm(f)
+
+
+# ---------------------------------------------------------------------------------------
+# two fronts in x3 (Sec. 4.2 note 3, Sec. 5)
+# ---------------------------------------------------------------------------------------
+from oracle.partition import groups_two_fronts, window_fronts
+from oracle.problem import moving_profile, moving_profile_above
+
+
+def test_two_front_groups_and_windows():
+    G = groups_two_fronts(15, 3, 2)
+    assert G == [(1, 3), (4, 5), (6, 7), (8, 9), (10, 11), (12, 12), (13, 15)]
+    mid = len(G) // 2
+    assert mid == 3
+    assert window_fronts(G, 0, 2, 2) == (1, 3, None, None)
+    assert window_fronts(G, 6, 2, 2) == (13, 15, None, None)
+    assert window_fronts(G, 1, 2, 2) == (2, 5, 4, None)          # below the middle: padded below
+    assert window_fronts(G, 5, 2, 2) == (12, 14, None, 12)       # above: padded above
+    assert window_fronts(G, 3, 2, 2) == (6, 11, 8, 9)            # middle: both sides
+    # every node in exactly one group
+    nodes = [k for a, e in G for k in range(a, e + 1)]
+    assert nodes == list(range(1, 16))
+
+
+def test_moving_profile_above_is_the_mirror_image():
+    """The PML padded above node e equals the one padded below node n+1-e under x -> 1-x
+    (half-step position t -> 2(n+1) - t)."""
+    n, p, C, om = 20, 4, 17.0, 9.0
+    for e in (8, 13):
+        t = np.arange(2 * e, 2 * (e + p + 1) + 1)
+        up = moving_profile_above(t, e, p, n, C, om)
+        down = moving_profile(2 * (n + 1) - t, n + 1 - e, p, n, C, om)
+        assert np.allclose(up, down, rtol=1e-15, atol=0)
+    # undamped at the last physical node, damped at the padding, sigma = 0 outside
+    assert moving_profile_above(2 * 8, 8, p, n, C, om) == 1.0
+    assert abs(moving_profile_above(2 * 9, 8, p, n, C, om) - 1.0) > 1e-3
+
+
+def _mirror_z(v, n):
+    """x3 -> 1 - x3 on vectors ordered x1 fastest (unknown (k, j, i) -> (n-1-k, j, i))."""
+    return np.asarray(v).reshape(n, n, n, -1)[::-1].reshape(n ** 3, -1)
+
+
+@pytest.mark.parametrize("n,b,p", [(11, 3, 3), (13, 3, 2)])
+def test_two_front_sweep_commutes_with_x3_mirror(n, b, p):
+    """With a medium symmetric in x3 and a symmetric two-front partition (d = 1 and n - 2b odd,
+    so the middle group is the central layer), the preconditioner
+    commutes with the reflection x3 -> 1 - x3: the front sweeping down from x3 = 1 and the
+    middle slab's double-sided PML are the mirror images of the other side.  (The one-front
+    sweep does not have this symmetry.)"""
+    case = inputs.small_case(n=n, b=b, p=p, d=1)
+    c = case["c"]
+    c = 0.5 * (c + c[::-1])                      # symmetric in x3
+    kw = dict(n=n, c=c, omega=case["omega"], b=b, C=case["C"], p=p, d=1)
+    M2 = O.RecursiveSweep(O.Problem(fronts=2, **kw))
+    f = inputs.random_rhs(n, 2, seed=19).reshape(2, -1).T
+    lhs = M2.apply(_mirror_z(f, n))
+    rhs = _mirror_z(M2.apply(f), n)
+    assert _rel(lhs, rhs) < 1e-12
+    M1 = O.RecursiveSweep(O.Problem(fronts=1, **kw))
+    assert _rel(M1.apply(_mirror_z(f, n)), _mirror_z(M1.apply(f), n)) > 1e-6
+
+
+def test_two_front_preconditioner_linear_adjoint_and_effective():
+    prob = _prob(n=11, fronts=2)
+    M = O.RecursiveSweep(prob)
+    x, y = inputs.random_rhs(11, 2, seed=7).reshape(2, -1)
+    a, bb = 0.3 - 1.1j, 2.0 + 0.5j
+    assert _rel(M.apply(a * x + bb * y)[:, 0], a * M.apply(x)[:, 0] + bb * M.apply(y)[:, 0]) < 1e-13
+    d1 = np.vdot(M.apply(x)[:, 0], y)
+    d2 = np.vdot(x, M.apply(y, adjoint=True)[:, 0])
+    assert abs(d1 - d2) <= 1e-13 * abs(d1)
+    # as good an approximate inverse as the single front: GMRES converges to the direct solve
+    f = inputs.random_rhs(11, 1, seed=3).reshape(-1)
+    xs = spla.spsolve(M.A.tocsc(), f)
+    z = M.apply(f)[:, 0]
+    assert _rel(z, xs) < 0.8
+    u, its, _ = O.fgmres(lambda v: M.A @ v, lambda v: M.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
+    assert _rel(u, xs) < 1e-8
+    M1 = O.RecursiveSweep(_prob(n=11))
+    _, its1, _ = O.fgmres(lambda v: M1.A @ v, lambda v: M1.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
+    assert its <= its1 + 3, (its, its1)
