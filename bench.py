@@ -34,16 +34,16 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_step(Helm, c, wl, F, prec):
+def run_step(Helm, c, wl, F, prec, fronts):
     import torch
-    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec)
+    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts)
     u, its, rel, rc = H.solve(F, tol=wl["tol"], restart=wl["restart"], maxit=wl.get("maxit", 400))
     torch.cuda.synchronize()
     st = H.stats()
     return H, u, its, rel, rc, st
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, fronts):
     """HBM bytes per sweep launch from the committed counter run (FETCH_SIZE and WRITE_SIZE of
     one 32-right-hand-side launch, each scaled by what the counter reads for a plain copy of
     known size), or None when that run does not cover this workload or the sweep source has
@@ -55,6 +55,8 @@ def measured_traffic(workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    if rec.get("fronts", 1) != fronts:
+        return None
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != rec.get("sweep_source_sha256"):
             return None
@@ -106,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
+    ap.add_argument("--fronts", type=int, default=1, choices=[1, 2],
+                    help="outer sweep from x3 = 0 only (1) or from both faces (2)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -130,7 +134,7 @@ def main():
     log(f"workload {args.workload}: n={n} R={R} b={wl['b']} p={wl['p']} d={wl['d']} omega={wl['omega']:.4f}")
 
     for w in range(args.warmup):
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64")
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts)
         log(f"warmup {w}: iters {its.tolist()} setup {st['setup_ms']:.1f} ms apply {st['apply_ms']:.0f} ms")
         H.close()
         del u
@@ -141,7 +145,7 @@ def main():
            "matvec_ms": 0.0, "matvec_launches": 0, "matvec_rhs": 0}
     u_mix = None
     for k in range(args.steps):
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64")
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts)
         for key in tot:
             tot[key] += st[key]
         bpr, mvb = st["apply_bytes_per_rhs"], st["matvec_bytes_per_rhs"]
@@ -157,9 +161,19 @@ def main():
     sec_per_step = (t1 - t0) / args.steps
 
     apply_avg_ms = tot["apply_ms"] / max(tot["apply_launches"], 1)
-    # dependent block steps of one sweep: (2G - 1)^2 line solves of 2 (n/2) + 1 two-sided steps
-    G = 1 + -(-(n - wl["b"]) // wl["d"])
-    steps_per_sweep = (2 * G - 1) ** 2 * (2 * (n // 2) + 1)
+    # dependent block steps of one sweep (the longest chain of one workgroup): line solves of
+    # 2 (n/2) + 1 two-sided steps; with two fronts each front does max(mid, Gz-1-mid) slabs
+    # forward and backward, and the middle slab's lines take 2n - 1 one-chain steps
+    Gy = 1 + -(-(n - wl["b"]) // wl["d"])
+    lines_per_slab = 2 * Gy - 1
+    if args.fronts == 1:
+        steps_per_sweep = (2 * Gy - 1) * lines_per_slab * (2 * (n // 2) + 1)
+    else:
+        Gz = 2 + -(-(n - 2 * wl["b"]) // wl["d"])
+        zmid = Gz // 2
+        front = max(zmid, Gz - 1 - zmid)
+        steps_per_sweep = (2 * front * lines_per_slab * (2 * (n // 2) + 1)
+                           + lines_per_slab * (2 * n - 1))
     apply_bytes_per_launch = bpr * tot["apply_rhs"] / max(tot["apply_launches"], 1)
     achieved = apply_bytes_per_launch / (apply_avg_ms * 1e-3) / 1e9
     mv_gbs = mvb * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
@@ -178,7 +192,9 @@ def main():
         "dtype": "c64 sweep / f64 GMRES",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n}^3, {R} point sources, b=p={wl['b']}, d={wl['d']}, "
-                               f"omega/2pi={wl['omega'] / (2 * np.pi):.0f}, GMRES({wl['restart']}) to {wl['tol']:g}",
+                               f"omega/2pi={wl['omega'] / (2 * np.pi):.0f}, GMRES({wl['restart']}) to {wl['tol']:g}, "
+                               f"{args.fronts} front(s) in x3",
+                   "fronts": args.fronts,
                    "n": n, "rhs": R, "b": wl["b"], "p": wl["p"], "slab_layers": wl["d"],
                    "factor_bytes": info["factor_bytes"], "lines": info["n_lines"], "max_block": info["max_block"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -194,7 +210,7 @@ def main():
         "apply_launches_per_step": tot["apply_launches"] / args.steps,
         "matvec_gbs": round(mv_gbs, 1),
     }
-    tr = measured_traffic(args.workload)
+    tr = measured_traffic(args.workload, args.fronts)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
         result["roofline"]["traffic_gbs"] = round(tr["hbm_bytes_per_launch"] / (tr["apply_ms"] * 1e-3) / 1e9, 1)
@@ -207,7 +223,7 @@ def main():
         log("fp64 path: one step with complex128 sweeps")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128")
+        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", args.fronts)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         H.close()

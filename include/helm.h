@@ -51,22 +51,33 @@ typedef struct {
   int b;                    /* boundary PML cells, eta = b h (Sec. 2)                      */
   double C;                 /* the constant C of sigma (Sec. 2), > 0                        */
   int p;                    /* moving-PML cells of each auxiliary problem (Sec. 3, 4.2)    */
+  int fronts;               /* outer sweep over x3: 1 (or 0) = from x3 = 0 only, as in     */
+                            /* Algorithm 6; 2 = from both faces meeting in a middle slab   */
+                            /* padded with moving PML on both sides (Sec. 4.2 note 3, the  */
+                            /* configuration of Sec. 5)                                    */
 } helm_pml;
 
 /*
  * helm_setup -- Algorithm 5 (with Algorithm 3 per slab, Sec. 4.2): form and block-LDU factor
  * every quasi-1D auxiliary ("line") problem.
- *   grid, pml     : host structs.  Requires n >= 2b+1, b >= 1, 0 <= p <= b, C > 0.
+ *   grid, pml     : host structs.  Requires n >= 2b+1, b >= 1, 0 <= p <= b, C > 0,
+ *                   pml->fronts in {0, 1, 2}.
  *   c_dev         : n^3 float64 velocities at the nodes, all finite and > 0; may be freed
  *                   after the call (the handle keeps omega^2/c^2).
  *   omega         : angular frequency > 0.
  *   slab_layers   : d >= 1, physical layers per auxiliary problem in x3 and in x2 (Sec. 4.2).
  *   prec          : HELM_C64 or HELM_C128 (precision of factors and sweeps).
  *   out           : receives the handle (NULL on error).
- * Groups along x3 and x2: nodes 1..b, then consecutive groups of d nodes (the last may be
- * shorter).  The auxiliary problem of every group but the first is padded with p moving-PML
- * nodes whose zero-Dirichlet plane lies p+1 spacings below the group, with sigma(.; (p+1)h)
- * measured from that plane; above the group's first node the boundary profile is kept.
+ * Groups along x2 (and x3 with one front): nodes 1..b, then consecutive groups of d nodes
+ * (the last may be shorter).  The auxiliary problem of every group but the first is padded
+ * with p moving-PML nodes whose zero-Dirichlet plane lies p+1 spacings below the group, with
+ * sigma(.; (p+1)h) measured from that plane; above the group's first node the boundary
+ * profile is kept.  With two fronts the x3-groups are nodes 1..b, groups of d over
+ * b+1..n-b (the last may be shorter) and nodes n-b+1..n; with G of them the middle one is
+ * group G/2; groups below it are padded below as above, groups above it padded above with
+ * the mirror image (plane p+1 spacings above the group), the middle group on both sides, and
+ * the first and last groups not at all.  Limits: every line block B = (x2 window) x (x3
+ * window) <= 64, except the two-front middle slab's, <= 128 (complex64) or 96 (complex128).
  * Errors: HELM_EINVAL, HELM_ENOMEM (factor bytes > free memory), HELM_ESINGULAR, HELM_EHIP.
  * Synchronises `stream`.
  */
@@ -76,7 +87,11 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
 /*
  * helm_apply -- Algorithm 6 (outer sweep over x3-groups; each slab block applied by
  * Algorithm 4, the inner sweep over x2-groups; each line block solved exactly by its block
- * LDU): z = M^{-1} r for R right-hand sides in one persistent launch.
+ * LDU): z = M^{-1} r for R right-hand sides in one persistent launch.  With two fronts the
+ * outer sweep is the block LDU with the x3-groups eliminated from both faces towards the
+ * middle group (forward: each front carries its f - A u coupling, the middle slab takes
+ * both; backward: each front subtracts the correction from its neighbour nearer the middle),
+ * in three launches (fronts forward, middle slab, fronts backward).
  *   r_dev, z_dev : R*n^3 complex128 each (may not alias).  In HELM_C64 mode r is rounded to
  *                  complex64 on entry and z is widened on exit.
  */
@@ -157,10 +172,11 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
  * and x2-group) into dst_dev: n blocks of B*B complex values, block i (0-based x1 index)
  * holding the factor of x1-block i, row-major within a block, unknowns of a block ordered
  * (x2 window row, x3 window layer) with x3 fastest.  The blocks are eliminated from both
- * ends towards the middle block m = n/2 (0-based, integer division): block i < m holds the inverse Schur
- * complement after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks
- * i+1..n-1, and block m the one after all others, which equals the (m, m) block of the line
- * matrix's inverse.  The solve is exact for any such order.
+ * ends towards the middle block m (0-based): block i < m holds the inverse Schur complement
+ * after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks i+1..n-1, and
+ * block m the one after all others, which equals the (m, m) block of the line matrix's
+ * inverse.  m = n/2 (integer division), except for the lines of the two-front middle slab,
+ * where m = n-1 (the x1 order of Sec. 3).  The solve is exact for any such order.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
  * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
  */

@@ -11,7 +11,9 @@
 namespace {
 thread_local std::string g_last_error;
 
-constexpr int kBlockLimit = 64;          // largest block B the sweep and setup kernels take
+constexpr int kBlockLimit = 64;          // largest block B of the two-chain sweep shapes
+constexpr int kBlockLimitOne = 128;      // ... of the one-chain shapes (two-front middle slab)
+constexpr size_t kSetupLds = 144 * 1024; // dynamic LDS of the setup (one B x B block at least)
 constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
 constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
 
@@ -27,12 +29,19 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   if (prec != HELM_C64 && prec != HELM_C128) return fail(HELM_EINVAL, "prec must be HELM_C64 or HELM_C128");
   if (!(pml->C > 0.0) || !std::isfinite(pml->C)) return fail(HELM_EINVAL, "PML constant C must be finite and > 0");
   std::string msg;
-  int rc = build_plan(grid->n, pml->b, pml->p, d, plan, msg);
+  const int fronts = pml->fronts == 0 ? 1 : pml->fronts;
+  int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
-  if (plan.maxB > kBlockLimit)
-    return fail(HELM_EINVAL, "block size (b or p+d per axis, squared) exceeds 64");
-  const size_t lds = LdsLayout(plan.n, plan.maxB, (int)csize(prec)).bytes;
-  if (lds > kLdsBytes) return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
+  const int front_B = fronts == 2 ? plan.maxB_front : plan.maxB;
+  if (front_B > kBlockLimit)
+    return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 64");
+  if (fronts == 2 && plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
+    return fail(HELM_EINVAL, "middle-slab block size (two fronts) exceeds 128 (complex64) or 96 (complex128)");
+  if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
+    return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
+  for (int B : {front_B, fronts == 2 ? plan.maxB_mid : 0})
+    if (B && LdsLayout(plan.n, B, (int)csize(prec)).bytes > kLdsBytes)
+      return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
   return HELM_OK;
 }
 
@@ -40,20 +49,21 @@ size_t planned_bytes(const Plan& p, int prec) {
   const size_t N = (size_t)p.n * p.n * p.n;
   return ((size_t)p.total_elems + kFactorPad) * csize(prec) + N * sizeof(double) +
          (size_t)(2 * (p.n + 1) + 1 + 2 * p.p + 2 + 5 * (p.n + 2)) * sizeof(double2) +
-         (size_t)p.G * sizeof(GroupInfo) + (size_t)p.G * p.G * sizeof(long long);
+         (size_t)(p.Gz + p.Gy) * sizeof(GroupInfo) + (size_t)p.Gz * p.Gy * sizeof(long long);
 }
 
 // algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
 // inner pass it takes part in (twice unless l is the last x2-group) and once per outer pass
-// (twice unless g is the last x3-group); each solve visits its n blocks twice (forward and
-// backward substitution) and reads B*B entries per visit; plus the input (complex128) read
-// and the output written once.
+// (twice unless g is the last x3-group with one front, or the middle one with two fronts);
+// each solve visits its n blocks twice (forward and backward substitution) and reads B*B
+// entries per visit; plus the input (complex128) read and the output written once.
 double sweep_bytes_per_rhs(const Plan& p, int prec) {
   double acc = 0.0;
-  for (int g = 0; g < p.G; ++g)
-    for (int l = 0; l < p.G; ++l) {
-      const double mult = (g < p.G - 1 ? 2.0 : 1.0) * (l < p.G - 1 ? 2.0 : 1.0);
-      const double B = p.line_B[(size_t)g * p.G + l];
+  for (int g = 0; g < p.Gz; ++g)
+    for (int l = 0; l < p.Gy; ++l) {
+      const bool once = p.fronts == 2 ? g == p.zmid : g == p.Gz - 1;
+      const double mult = (once ? 1.0 : 2.0) * (l < p.Gy - 1 ? 2.0 : 1.0);
+      const double B = p.line_B[(size_t)g * p.Gy + l];
       acc += mult * 2.0 * p.n * B * B;
     }
   const double N = (double)p.n * p.n * p.n;
@@ -96,7 +106,7 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
   int rc = validate(grid, pml, slab_layers, prec, plan);
   if (rc != HELM_OK) return rc;
   if (bytes) *bytes = planned_bytes(plan, prec);
-  if (n_lines) *n_lines = plan.G * plan.G;
+  if (n_lines) *n_lines = plan.Gz * plan.Gy;
   if (max_block) *max_block = plan.maxB;
   return HELM_OK;
 }
@@ -139,8 +149,8 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   ALLOC(h->smv, (size_t)(2 * plan.p + 2) * sizeof(double2));
   ALLOC(h->coef, (size_t)4 * (plan.n + 2) * sizeof(double2));
   ALLOC(h->diag, (size_t)(plan.n + 2) * sizeof(double2));
-  ALLOC(h->d_groups, (size_t)plan.G * sizeof(GroupInfo));
-  ALLOC(h->d_line_off, (size_t)plan.G * plan.G * sizeof(long long));
+  ALLOC(h->d_groups, plan.groups.size() * sizeof(GroupInfo));
+  ALLOC(h->d_line_off, plan.line_off.size() * sizeof(long long));
   // the sweep's row-major block walk may read up to 64 entries past the last block
   ALLOC(h->factors, ((size_t)plan.total_elems + kFactorPad) * csize(prec));
   ALLOC(h->d_err, 2 * sizeof(int));
@@ -148,7 +158,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   if (hipMemsetAsync((char*)h->factors + (size_t)plan.total_elems * csize(prec), 0,
                      kFactorPad * csize(prec), s) != hipSuccess)
     return bail(HELM_EHIP, "clearing the factor padding failed");
-  if (hipMemcpyAsync(h->d_groups, plan.groups.data(), plan.G * sizeof(GroupInfo),
+  if (hipMemcpyAsync(h->d_groups, plan.groups.data(), plan.groups.size() * sizeof(GroupInfo),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(h->d_line_off, plan.line_off.data(), plan.line_off.size() * sizeof(long long),
                      hipMemcpyHostToDevice, s) != hipSuccess)
@@ -264,7 +274,7 @@ int helm_set_medium(helm_handle* h, const double* c_dev, void* stream) {
 int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max_block) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
   if (factor_bytes) *factor_bytes = (size_t)h->plan.total_elems * csize(h->prec);
-  if (n_lines) *n_lines = h->plan.G * h->plan.G;
+  if (n_lines) *n_lines = h->plan.Gz * h->plan.Gy;
   if (max_block) *max_block = h->plan.maxB;
   return HELM_OK;
 }
@@ -272,9 +282,9 @@ int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max
 int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* B_out,
                       void* stream) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
-  const int G = h->plan.G;
-  if (zg < 0 || zg >= G || yg < 0 || yg >= G) return fail(HELM_EINVAL, "group index out of range");
-  const size_t line = (size_t)zg * G + yg;
+  if (zg < 0 || zg >= h->plan.Gz || yg < 0 || yg >= h->plan.Gy)
+    return fail(HELM_EINVAL, "group index out of range");
+  const size_t line = (size_t)zg * h->plan.Gy + yg;
   const int B = h->plan.line_B[line];
   if (B_out) *B_out = B;
   if (!dst_dev) return HELM_OK;
@@ -288,8 +298,8 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
                     int adjoint, void* stream) {
   int rc = check_batch(h, r_dev, x_dev, R);
   if (rc != HELM_OK) return rc;
-  const int G = h->plan.G;
-  if (zg < 0 || zg >= G || yg < 0 || yg >= G) return fail(HELM_EINVAL, "group index out of range");
+  if (zg < 0 || zg >= h->plan.Gz || yg < 0 || yg >= h->plan.Gy)
+    return fail(HELM_EINVAL, "group index out of range");
   HIP_TRY(launch_line_solve(h, zg, yg, (const double2*)r_dev, (double2*)x_dev, R, adjoint != 0,
                             S(stream)));
   return HELM_OK;
@@ -305,7 +315,8 @@ int helm_set_launch(helm_handle* h, int lanes_per_row) {
 
 // ---- launch-shape autotuner -------------------------------------------------------------
 static std::string tune_key(const helm_handle* h) {
-  return "n=" + std::to_string(h->n) + ",maxB=" + std::to_string(h->plan.maxB) +
+  const int B = h->plan.fronts == 2 ? h->plan.maxB_front : h->plan.maxB;
+  return "n=" + std::to_string(h->n) + ",maxB=" + std::to_string(B) +
          ",prec=" + (h->prec == HELM_C64 ? "c64" : "c128");
 }
 
@@ -340,9 +351,11 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
     }
   }
   hipStream_t s = S(stream);
-  // an interior line with the largest block: group (G/2, G/2)
-  const int G = h->plan.G, g = G / 2;
-  const int B = h->plan.line_B[(size_t)g * G + g];
+  // an interior line with the largest two-chain block: x3-group Gz/2 (the one below the middle
+  // with two fronts), x2-group Gy/2
+  const Plan& P = h->plan;
+  const int g = P.fronts == 2 ? P.zmid - 1 : P.Gz / 2, l = P.Gy / 2;
+  const int B = P.line_B[(size_t)g * P.Gy + l];
   const size_t elems = (size_t)h->n * B;
   double2 *r = nullptr, *x = nullptr;
   HIP_TRY(hipMalloc((void**)&r, elems * sizeof(double2)));
@@ -357,7 +370,7 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
   const int reps = 8;
   for (int lanes : {16, 8, 4}) {
     h->lanes_override = lanes;
-    if (launch_line_solve(h, g, g, r, x, 1, false, s) != hipSuccess) {   // warm-up / validity
+    if (launch_line_solve(h, g, l, r, x, 1, false, s) != hipSuccess) {   // warm-up / validity
       (void)hipGetLastError();
       continue;
     }
@@ -366,7 +379,7 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
     (void)hipEventCreate(&b);
     (void)hipEventRecord(a, s);
     bool ok = true;
-    for (int k = 0; k < reps && ok; ++k) ok = launch_line_solve(h, g, g, r, x, 1, false, s) == hipSuccess;
+    for (int k = 0; k < reps && ok; ++k) ok = launch_line_solve(h, g, l, r, x, 1, false, s) == hipSuccess;
     (void)hipEventRecord(b, s);
     float ms = 0.f;
     if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {

@@ -55,11 +55,15 @@ template <> __host__ __device__ inline double2 cvt<double2, float2>(float2 s) {
 // ---------------------------------------------------------------------------------------
 // LDS of the sweep kernels
 // ---------------------------------------------------------------------------------------
-constexpr int kZMax = 64;   // largest NC * CW of the sweep's launch shapes
+// largest NC * CW of the sweep's launch shapes and largest block B (the one-chain shapes of
+// the two-front middle slab reach 8 x 16 columns); sizes the published vectors and the zero
+// and junk rows
+constexpr int kZMax = 128;
 
 // LDS layout of the sweep kernels, in complex elements from the base (the step table follows
 // at a 16-byte boundary): line vector, published vectors, zero and junk rows, couplings, the
-// per-step couplings and the per-step table of the two chains.
+// per-step couplings and the per-step table (2 (n + 3) entries each: two chains of at most
+// n + 3, or one chain of at most 2n + 1).
 struct LdsLayout {
   int ybuf, zb, zeros, junk, cf, cb, ctab;
   size_t tab_byte, bytes;
@@ -87,16 +91,26 @@ struct GroupInfo {
 };
 
 struct Plan {
-  int n = 0, b = 0, p = 0, d = 0, G = 0;
-  std::vector<GroupInfo> groups;      // same partition along x2 and x3
-  std::vector<long long> line_off;    // [G*G] offset (complex elements) of line (g, l) = g*G + l
-  std::vector<int> line_B;            // [G*G]
+  int n = 0, b = 0, p = 0, d = 0;
+  int fronts = 1;                     // outer sweep from one face (Algorithm 6) or from both
+  int Gz = 0, Gy = 0;                 // x3-groups (outer sweep), x2-groups (inner sweep)
+  int zmid = -1;                      // two fronts: the middle x3-group (eliminated last)
+  std::vector<GroupInfo> groups;      // [Gz] x3-groups, then [Gy] x2-groups
+  std::vector<long long> line_off;    // [Gz*Gy] offset (complex elements) of line (g, l) = g*Gy + l
+  std::vector<int> line_B;            // [Gz*Gy]
   long long total_elems = 0;          // sum over lines of n * B^2
-  int maxB = 0, maxW = 0;
+  int maxB = 0, maxW = 0;             // over all lines / windows
+  int maxB_front = 0, maxB_mid = 0;   // two fronts: lines off / on the middle x3-group
+  const GroupInfo& zg(int g) const { return groups[g]; }
+  const GroupInfo& yg(int l) const { return groups[Gz + l]; }
+  // middle block of line (g, l)'s elimination order: both ends towards n/2, except the lines
+  // of the two-front middle slab, eliminated in x1 order (their blocks are too large for two
+  // chains per workgroup; see the sweep)
+  int line_mid(int g) const { return (fronts == 2 && g == zmid) ? n - 1 : n / 2; }
 };
 
 // builds the plan; returns HELM_OK or HELM_EINVAL (with a message)
-int build_plan(int n, int b, int p, int d, Plan& plan, std::string& msg);
+int build_plan(int n, int b, int p, int d, int fronts, Plan& plan, std::string& msg);
 
 // ---------------------------------------------------------------------------------------
 // device-time accounting: event pairs recorded around launches, resolved lazily
@@ -164,8 +178,8 @@ struct helm_handle {
   double2* smv = nullptr;          // moving profile s at half-steps u = 0 .. 2p+1 from its plane
   double2* coef = nullptr;         // [4][n+2]: A[m,m-1], A[m,m+1], A^H[m,m-1], A^H[m,m+1]
   double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
-  GroupInfo* d_groups = nullptr;   // [G]
-  long long* d_line_off = nullptr; // [G*G]
+  GroupInfo* d_groups = nullptr;   // [Gz + Gy]
+  long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128
   int* d_err = nullptr;            // [2]: error flag, first failing line
 

@@ -1,18 +1,22 @@
 // Host-side partition of the sweep axes and the factor layout.
 //
-// Along x3 (outer sweep) and x2 (inner sweep) the nodes 1..b form group 0, handled as one
-// block (Sec. 3: the first b layers, in the boundary PML); the rest is cut into groups of
-// d nodes, the last possibly shorter (Sec. 4.2: several layers per auxiliary problem).
-// The auxiliary window of group g >= 1 adds p moving-PML nodes below the group (Sec. 4.2:
-// the auxiliary PML may be thinner than b).
+// x2 (inner sweep, and x3 with one front): the nodes 1..b form group 0, handled as one block
+// (Sec. 3: the first b layers, in the boundary PML); the rest is cut into groups of d nodes,
+// the last possibly shorter (Sec. 4.2: several layers per auxiliary problem).  The auxiliary
+// window of group g >= 1 adds p moving-PML nodes below the group (Sec. 4.2: the auxiliary PML
+// may be thinner than b).
+//
+// x3 with two fronts (Sec. 4.2 note 3, the configuration of Sec. 5): the b layers at each face
+// form the first and the last group, the interior is cut into groups of d; groups below the
+// middle group (index Gz/2) are padded with p moving-PML nodes below, groups above it with p
+// nodes above, the middle group on both sides; the first and last groups are not padded.
 //
 // Line problem (g, l) pairs x3-group g with x2-group l; its grid is x1 = 1..n times the two
-// windows, so its blocks have B = W_l * W_g unknowns.  Factors are stored line after line in
-// the order the forward sweeps consume them (g major, l minor), each line's n blocks
-// contiguous, each block B*B row-major.
+// windows, so its blocks have B = W_l * W_g unknowns.  Factors are stored line after line
+// (g major, l minor), each line's n blocks contiguous, each block B*B row-major.
 #include "common.h"
 
-int build_plan(int n, int b, int p, int d, Plan& plan, std::string& msg) {
+int build_plan(int n, int b, int p, int d, int fronts, Plan& plan, std::string& msg) {
   if (b < 1 || n < 2 * b + 1) {
     msg = "need b >= 1 and n >= 2b+1";
     return HELM_EINVAL;
@@ -25,30 +29,64 @@ int build_plan(int n, int b, int p, int d, Plan& plan, std::string& msg) {
     msg = "need slab_layers >= 1";
     return HELM_EINVAL;
   }
+  if (fronts != 1 && fronts != 2) {
+    msg = "fronts must be 1 or 2";
+    return HELM_EINVAL;
+  }
   plan = Plan();
   plan.n = n;
   plan.b = b;
   plan.p = p;
   plan.d = d;
-  plan.groups.push_back(GroupInfo{1, b, 1, b});
+  plan.fronts = fronts;
+  std::vector<GroupInfo> zs, ys;
+  ys.push_back(GroupInfo{1, b, 1, b});
   for (int k = b + 1; k <= n; k += d) {
-    int last = k + d - 1 < n ? k + d - 1 : n;
-    plan.groups.push_back(GroupInfo{k, last, k - p, last - (k - p) + 1});
+    const int last = k + d - 1 < n ? k + d - 1 : n;
+    ys.push_back(GroupInfo{k, last, k - p, last - (k - p) + 1});
   }
-  plan.G = (int)plan.groups.size();
-  plan.line_off.resize((size_t)plan.G * plan.G);
-  plan.line_B.resize((size_t)plan.G * plan.G);
+  if (fronts == 1) {
+    zs = ys;
+  } else {
+    std::vector<std::pair<int, int>> cut;
+    cut.push_back({1, b});
+    for (int k = b + 1; k <= n - b; k += d) cut.push_back({k, k + d - 1 < n - b ? k + d - 1 : n - b});
+    cut.push_back({n - b + 1, n});
+    const int G = (int)cut.size(), mid = G / 2;
+    for (int g = 0; g < G; ++g) {
+      const int a = cut[g].first, e = cut[g].second;
+      int w0 = a, w1 = e;
+      if (g > 0 && g < G - 1) {
+        if (g <= mid) w0 = a - p;
+        if (g >= mid) w1 = e + p;
+      }
+      zs.push_back(GroupInfo{a, e, w0, w1 - w0 + 1});
+    }
+    plan.zmid = mid;
+  }
+  plan.Gz = (int)zs.size();
+  plan.Gy = (int)ys.size();
+  plan.groups = zs;
+  plan.groups.insert(plan.groups.end(), ys.begin(), ys.end());
+  plan.line_off.resize((size_t)plan.Gz * plan.Gy);
+  plan.line_B.resize((size_t)plan.Gz * plan.Gy);
   long long off = 0;
-  for (int g = 0; g < plan.G; ++g) {
-    for (int l = 0; l < plan.G; ++l) {
-      int B = plan.groups[g].W * plan.groups[l].W;
-      plan.line_off[(size_t)g * plan.G + l] = off;
-      plan.line_B[(size_t)g * plan.G + l] = B;
+  for (int g = 0; g < plan.Gz; ++g) {
+    for (int l = 0; l < plan.Gy; ++l) {
+      const int B = plan.zg(g).W * plan.yg(l).W;
+      plan.line_off[(size_t)g * plan.Gy + l] = off;
+      plan.line_B[(size_t)g * plan.Gy + l] = B;
       off += (long long)n * B * B;
       if (B > plan.maxB) plan.maxB = B;
+      if (fronts == 2 && g == plan.zmid) {
+        if (B > plan.maxB_mid) plan.maxB_mid = B;
+      } else if (B > plan.maxB_front) {
+        plan.maxB_front = B;
+      }
     }
-    if (plan.groups[g].W > plan.maxW) plan.maxW = plan.groups[g].W;
   }
+  for (const GroupInfo& gi : plan.groups)
+    if (gi.W > plan.maxW) plan.maxW = gi.W;
   plan.total_elems = off;
   return HELM_OK;
 }

@@ -14,18 +14,22 @@
 // One workgroup owns one line: it forms S_i in LDS, inverts it by Gauss-Jordan elimination
 // with partial pivoting (row interchanges inside the block only), stores T_i = S_i^{-1} and
 // reuses it for the next Schur update.  The blocks are eliminated from both ends towards the
-// middle (see the order below), which halves the dependent chain of the line solve.  All ~G^2 lines are independent (Sec. 6 notes that
-// the setup is O(n^2) independent quasi-1D problems), so one launch covers them all.
+// middle (see the order below), which halves the dependent chain of the line solve.  All
+// lines are independent (Sec. 6 notes that the setup is O(n^2) independent quasi-1D
+// problems), so one launch covers them all.
 #include "common.h"
 
 namespace {
 
 constexpr int kMaxW = 64;
-constexpr int kMaxB = 64;
+constexpr int kMaxB = 128;
 constexpr int kSetupThreads = 256;
+constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may take (of 160 KiB)
 
 struct SetupArgs {
-  int n, G, p;
+  int n, Gz, Gy, p;
+  int fronts, zmid;
+  int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
   double h;
   const GroupInfo* groups;
   const long long* line_off;
@@ -36,10 +40,14 @@ struct SetupArgs {
   int* err;
 };
 
-// s at half-step t of the window of group gi (the moving profile replaces the boundary one
-// strictly below the group's first node, groups other than the first)
-__device__ inline double2 window_s(const SetupArgs& a, const GroupInfo& gi, bool moving, int t) {
-  return (moving && t < 2 * gi.first) ? a.smv[t - 2 * (gi.first - a.p - 1)] : a.sbd[t];
+// s at half-step t of the window of group gi: the moving profile replaces the boundary one
+// strictly below the group's first node when the window extends below it, and (mirrored,
+// measured from the plane p+1 spacings above the last node) strictly above the group's last
+// node when the window extends above it
+__device__ inline double2 window_s(const SetupArgs& a, const GroupInfo& gi, int t) {
+  if (gi.w0 < gi.first && t < 2 * gi.first) return a.smv[t - 2 * (gi.first - a.p - 1)];
+  if (gi.w0 + gi.W - 1 > gi.last && t > 2 * gi.last) return a.smv[2 * (gi.last + a.p + 1) - t];
+  return a.sbd[t];
 }
 
 template <typename R>
@@ -53,29 +61,32 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   __shared__ int piv_s, bad_s;
 
   const int line = blockIdx.x;
-  const int g = line / a.G, l = line % a.G;
-  const GroupInfo gz = a.groups[g], gy = a.groups[l];
+  const int g = line / a.Gy, l = line % a.Gy;
+  const GroupInfo gz = a.groups[g], gy = a.groups[a.Gz + l];
   const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
   const int n = a.n;
   const int tid = threadIdx.x, NT = blockDim.x;
   C* S = reinterpret_cast<C*>(smem_raw);
-  C* Tb = S + B * B;
   C* out = reinterpret_cast<C*>(a.factors) + a.line_off[line];
   const double ih2 = 1.0 / (a.h * a.h);
 
-  if (tid < Wy) syn[tid] = window_s(a, gy, l > 0, 2 * (gy.w0 + tid));
-  if (tid <= Wy) syh[tid] = window_s(a, gy, l > 0, 2 * (gy.w0 + tid) - 1);
-  if (tid < Wz) szn[tid] = window_s(a, gz, g > 0, 2 * (gz.w0 + tid));
-  if (tid <= Wz) szh[tid] = window_s(a, gz, g > 0, 2 * (gz.w0 + tid) - 1);
+  if (tid < Wy) syn[tid] = window_s(a, gy, 2 * (gy.w0 + tid));
+  if (tid <= Wy) syh[tid] = window_s(a, gy, 2 * (gy.w0 + tid) - 1);
+  if (tid < Wz) szn[tid] = window_s(a, gz, 2 * (gz.w0 + tid));
+  if (tid <= Wz) szh[tid] = window_s(a, gz, 2 * (gz.w0 + tid) - 1);
   if (tid == 0) bad_s = 0;
   __syncthreads();
 
   // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
-  // middle block m = n/2 (integer division) last, whose Schur complement takes the update from both sides.
-  // It is the block LDU of Sec. 3 with the blocks in that order (every block eliminated is an
-  // end of the remaining chain, so there is no fill); the sweep runs the two halves of each
-  // line solve as two concurrent chains.
-  const int mid = n / 2;
+  // middle block m last, whose Schur complement takes the update from both sides; m = n/2
+  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines of a two-front
+  // middle slab.  It is the block LDU of Sec. 3 with the blocks in that order (every block
+  // eliminated is an end of the remaining chain, so there is no fill); the sweep runs the two
+  // halves of each line solve as two concurrent chains.
+  const int mid = (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2;
+  // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
+  C* Tlds = S + B * B;
+  const C* Tprev = Tlds;
   const bool has_lower = mid + 1 <= n - 1;
   const C* T_mid_minus1 = out + (long long)(mid - 1) * B * B;   // T_{m-1}, stored at t = m - 1
   for (int t = 0; t < n; ++t) {
@@ -87,11 +98,11 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
     // update from the block above: u_i l_{i+1} = (s_m s_{m+1/2} / h^2)(s_{m+1} s_{m+1/2} / h^2)
     const C sc_below = cvt<C>(cmul(cscale(cmul(sxn, sxd), ih2), cscale(cmul(a.sbd[2 * m - 2], sxd), ih2)));
     const C sc_above = cvt<C>(cmul(cscale(cmul(sxn, sxu), ih2), cscale(cmul(a.sbd[2 * m + 2], sxu), ih2)));
-    // (scale, factor) pairs of the Schur update; Tb holds the factor computed last
+    // (scale, factor) pairs of the Schur update; Tprev holds the factor computed last
     const bool is_mid = t == n - 1;
     const bool use_a = (t > 0 && t < mid) || (t > mid && t < n - 1) || is_mid;
     const C scA = (t < mid || is_mid) ? sc_below : sc_above;
-    const C* TA = (is_mid && has_lower) ? T_mid_minus1 : Tb;
+    const C* TA = (is_mid && has_lower) ? T_mid_minus1 : Tprev;
     const bool use_b = is_mid && has_lower;
     for (int e = tid; e < B * B; e += NT) {
       const int r = e / B, c = e - r * B;
@@ -113,7 +124,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
       }
       C v = cvt<C>(val);
       if (use_a) v = csub(v, cmul(scA, TA[e]));
-      if (use_b) v = csub(v, cmul(sc_above, Tb[e]));
+      if (use_b) v = csub(v, cmul(sc_above, Tprev[e]));
       S[e] = v;
     }
     __syncthreads();
@@ -173,13 +184,22 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
       }
     }
     __syncthreads();
-    for (int e = tid; e < B * B; e += NT) {
-      const int r = e / B, q = e - r * B;
-      Tb[r * B + rho[q]] = S[e];
-    }
-    __syncthreads();
     C* dst = out + (long long)i * B * B;
-    for (int e = tid; e < B * B; e += NT) dst[e] = Tb[e];
+    if (a.prev_in_lds) {
+      for (int e = tid; e < B * B; e += NT) {
+        const int r = e / B, q = e - r * B;
+        Tlds[r * B + rho[q]] = S[e];
+      }
+      __syncthreads();
+      for (int e = tid; e < B * B; e += NT) dst[e] = Tlds[e];
+    } else {
+      for (int e = tid; e < B * B; e += NT) {
+        const int r = e / B, q = e - r * B;
+        dst[r * B + rho[q]] = S[e];
+      }
+      __syncthreads();   // the next block's Schur update reads dst (workgroup-scope fence)
+      Tprev = dst;
+    }
   }
   if (tid == 0 && bad_s) {
     atomicOr(&a.err[0], 1);
@@ -193,8 +213,11 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   const Plan& P = h->plan;
   SetupArgs a;
   a.n = h->n;
-  a.G = P.G;
+  a.Gz = P.Gz;
+  a.Gy = P.Gy;
   a.p = P.p;
+  a.fronts = P.fronts;
+  a.zmid = P.zmid;
   a.h = h->h;
   a.groups = h->d_groups;
   a.line_off = h->d_line_off;
@@ -203,15 +226,17 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   a.kappa = h->kappa;
   a.factors = h->factors;
   a.err = h->d_err;
-  const unsigned lines = (unsigned)(P.G * P.G);
+  const unsigned lines = (unsigned)(P.Gz * P.Gy);
+  const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
+  // keep the previous factor in LDS when two B x B blocks fit, else re-read it from HBM
+  a.prev_in_lds = 2 * (size_t)P.maxB * P.maxB * csz <= kSetupLdsBytes;
+  const size_t sm = (a.prev_in_lds ? 2 : 1) * (size_t)P.maxB * P.maxB * csz;
   if (h->prec == HELM_C64) {
-    size_t sm = 2 * (size_t)P.maxB * P.maxB * sizeof(float2);
     hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
     k_line_setup<float><<<lines, kSetupThreads, sm, s>>>(a);
   } else {
-    size_t sm = 2 * (size_t)P.maxB * P.maxB * sizeof(double2);
     hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;

@@ -6,7 +6,7 @@
 // sweep's long chain of dependent block steps never returns to the host).  Workgroups of
 // different right-hand sides are independent and read the same factor stream.
 //
-// Data flow for one right-hand side:
+// Data flow for one right-hand side (one front; the two-front outer sweep is below):
 //   outer forward  g = 0..G-1 : slab input  f on the group's layers, minus A[k0,k0-1] u[k0-1]
 //   outer backward g = G-2..0 : slab input  A[k1,k1+1] u[k1+1] on the group's last layer
 //     inner forward  l = 0..G-1 : line input  slab input on the group's rows, minus
@@ -27,14 +27,33 @@
 // double-buffered LDS slot, so one barrier separates consecutive steps.  The factor blocks do
 // not depend on the data: each thread keeps its slice of the next D blocks in registers
 // (a ring refilled D steps ahead), which hides the HBM latency behind D dependent steps.
+//
+// Two fronts in x3 (Sec. 4.2 note 3, Sec. 5): three launches.  (1) Two workgroups per
+// right-hand side run the fronts concurrently: the lower one x3-groups 0..mid-1 upwards
+// (input f - A[k0,k0-1] u[k0-1]), the upper one groups G-1..mid+1 downwards (input
+// f - A[k1,k1+1] u[k1+1]).  (2) One workgroup per right-hand side solves the middle slab
+// (input f minus both couplings).  (3) The fronts run backwards: the lower one groups
+// mid-1..0 (input A[k1,k1+1] u[k1+1], subtracted), the upper one groups mid+1..G-1 (input
+// A[k0,k0-1] u[k0-1]).  The launch boundaries order the fronts and the middle slab; inside a
+// launch no workgroup waits for another.  The middle slab's line problems have moving PML on
+// both sides in x3 and larger blocks; their factors are in x1 order and each is solved by one
+// chain spanning the whole workgroup.
 #include "common.h"
 
 namespace {
 
 
+// what a workgroup does with one x3-group: forward from below / from above / the middle
+// slab with both couplings; backward with the coupling from above / from below
+enum SlabKind { kFwdLow = 0, kFwdHigh = 1, kFwdMid = 2, kBwdLow = 3, kBwdHigh = 4 };
+
 struct SweepArgs {
-  int n, G, maxW, maxB;
-  int tpc;               // threads per line chain (the launch has two chains)
+  int n, Gz, Gy, maxW, maxB;
+  int fronts, zmid;
+  int pass;              // 0: one front, whole sweep; 1: two fronts forward; 2: middle slab;
+                         // 3: two fronts backward
+  int nfront;            // workgroups per right-hand side in this launch (1 or 2)
+  int tpc;               // threads per line chain (two chains, or one spanning the workgroup)
   long long N, in_stride, out_stride;
   const GroupInfo* groups;
   const long long* line_off;
@@ -98,11 +117,12 @@ __device__ __forceinline__ void lds_barrier() {
 // for each chain and step, the LDS rows to read and write and the factor block to prefetch,
 // and every lane of a block row writes the row's (identical) result, so no lane masking is
 // needed.  Steps without a destination write to a junk row.
-template <typename R, int NC, int CW, int D, bool ADJ>
+template <typename R, int NC, int CW, int D, bool ADJ, int CH>
 struct LineSolver {
   using C = typename cx<R>::type;
   static constexpr int ZS = NC * CW;   // stride of one published vector (>= B, zero-padded)
   static_assert(D % 2 == 0, "the ring depth must be even (published-vector parity per slot)");
+  static_assert(ZS <= kZMax, "published vector longer than its LDS slot");
   C ring[D][CW];
   unsigned off0;                       // this thread's byte offset inside a B x B block
   unsigned offa[ADJ ? CW : 1];         // adjoint walk: one offset per column
@@ -130,10 +150,10 @@ struct LineSolver {
   // row-major (non-adjoint) walk they run into the next row, or past the last block into the
   // padding that follows the factor array, so they read finite values; the adjoint walk
   // clamps them.
-  __device__ __forceinline__ void begin_line(const C* T, int B, int n) {
+  __device__ __forceinline__ void begin_line(const C* T, int B, int n, int line_mid) {
     n_ = n;
     B_ = B;
-    mid = n / 2;
+    mid = line_mid;
     steps = 2 * mid + 1;
     BBb = (unsigned)(B * B) * (unsigned)sizeof(C);
     const unsigned long long tp = reinterpret_cast<unsigned long long>(T);
@@ -256,13 +276,13 @@ struct LineSolver {
   __device__ __forceinline__ void run(C* sb, int ybuf, int zb, int zeros, int junk, C* ctab,
                                       int4* tab, const C* cf, const C* cb) {
     const C zero = mk((R)0, (R)0);
-    const int B = B_, ts = steps + 2;   // table entries per chain
+    const int B = B_, ts = steps + 2;   // table entries per chain (CH * ts <= 2 (n + 3))
     for (int e = threadIdx.x; e < 4 * ZS; e += blockDim.x)
       if (e % ZS >= B) sb[zb + e] = zero;
     // per chain and step: couplings (forward upper l_{i+1}, lower u_{i-1}; backward upper u_i,
     // lower l_i; middle -1; block i is x1-node i + 1: l_i = cf[i + 1], u_i = cb[i + 1]) and
     // the table {operand row, result row, published-vector row, prefetch offset}
-    for (int e = threadIdx.x; e < 2 * ts; e += blockDim.x) {
+    for (int e = threadIdx.x; e < CH * ts; e += blockDim.x) {
       const int ch = e >= ts, t = e - ch * ts;
       const int d = mid > t ? mid - t : t - mid;
       const int i = ch ? mid + d : mid - d;
@@ -273,10 +293,12 @@ struct LineSolver {
       if (t < mid) {
         c = ch ? cb[i] : cf[i + 2];
         const bool last_lower = ch && t == mid - 1;
-        en.x = last_lower ? zeros : ybuf + (ch ? i - 1 : i + 1) * B;
         if (valid) {
+          en.x = last_lower ? zeros : ybuf + (ch ? i - 1 : i + 1) * B;
           en.y = ybuf + i * B;
           en.z = znext;
+        } else if (ch && i == n_) {
+          en.x = ybuf + (n_ - 1) * B;   // (even n, t = 0: the lower chain has no block yet)
         }
       } else if (t == mid) {
         en.y = ch ? junk : ybuf + mid * B;
@@ -290,9 +312,14 @@ struct LineSolver {
       ctab[e] = c;
       tab[e] = en;
     }
-    if (row < B) {   // each chain starts from the q of its first block
+    // each chain starts from the q of its first block; without lower blocks (mid = n - 1) the
+    // lower chain's published vectors stay zero, so the middle step adds nothing
+    if (mid == n_ - 1)
+      for (int e = threadIdx.x; e < 2 * ZS; e += blockDim.x) sb[zb + 2 * ZS + e] = zero;
+    lds_barrier();
+    if (row < B) {
       if (!lower) sb[zb + row] = sb[ybuf + row];
-      else sb[zb + (2 + ((2 * mid - n_ + 1) & 1)) * ZS + row] = sb[ybuf + (n_ - 1) * B + row];
+      else if (mid < n_ - 1) sb[zb + (2 + ((2 * mid - n_ + 1) & 1)) * ZS + row] = sb[ybuf + (n_ - 1) * B + row];
     }
     lds_barrier();
     const int4* tb = tab + lower * ts;
@@ -308,14 +335,31 @@ struct LineSolver {
   }
 };
 
-// threads of a launch: two chains of round-up-to-64(B * NC) threads each
-template <int NC, int CW> constexpr int max_threads() { return 2 * ((NC * NC * CW + 63) / 64 * 64); }
+// threads of a launch: CH chains (2, or 1 spanning the workgroup) of round-up-to-64(B * NC)
+template <int NC, int CW, int CH> constexpr int max_threads() { return CH * ((NC * NC * CW + 63) / 64 * 64); }
 
-template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ>
-__global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) {
+// the x3-groups a workgroup handles in this launch, in order: count, and the s-th (group, kind)
+__device__ __forceinline__ int slab_count(const SweepArgs& a, int front) {
+  switch (a.pass) {
+    case 0: return 2 * a.Gz - 1;
+    case 2: return 1;
+    default: return front == 0 ? a.zmid : a.Gz - 1 - a.zmid;
+  }
+}
+__device__ __forceinline__ int2 slab_at(const SweepArgs& a, int front, int s) {
+  switch (a.pass) {
+    case 0: return s < a.Gz ? make_int2(s, kFwdLow) : make_int2(2 * a.Gz - 2 - s, kBwdLow);
+    case 1: return front == 0 ? make_int2(s, kFwdLow) : make_int2(a.Gz - 1 - s, kFwdHigh);
+    case 2: return make_int2(a.zmid, kFwdMid);
+    default: return front == 0 ? make_int2(a.zmid - 1 - s, kBwdLow) : make_int2(a.zmid + 1 + s, kBwdHigh);
+  }
+}
+
+template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ, int CH>
+__global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs a) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = a.n, G = a.G;
+  const int n = a.n, Gz = a.Gz, Gy = a.Gy;
   const LdsLayout L(n, a.maxB, (int)sizeof(C));
   C* sb = reinterpret_cast<C*>(smem_raw);
   C* ybuf = sb + L.ybuf;
@@ -325,7 +369,8 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) 
   C* ctab = sb + L.ctab;
   int4* tab = reinterpret_cast<int4*>(smem_raw + L.tab_byte);
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int q = a.rhs_idx ? a.rhs_idx[blockIdx.x] : (int)blockIdx.x;
+  const int slot = (int)blockIdx.x / a.nfront, front = (int)blockIdx.x - slot * a.nfront;
+  const int q = a.rhs_idx ? a.rhs_idx[slot] : slot;
   const TI* __restrict__ f = reinterpret_cast<const TI*>(a.in) + (long long)q * a.in_stride;
   TO* u = reinterpret_cast<TO*>(a.out) + (long long)q * a.out_stride;
   C* v = reinterpret_cast<C*>(a.scratch) + (long long)blockIdx.x * n * n * a.maxW;
@@ -339,21 +384,27 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) 
   auto gidx = [&](int i, int j, int k) -> long long {  // i 0-based, j, k 1-based
     return ((long long)(k - 1) * n + (j - 1)) * n + i;
   };
-  LineSolver<R, NC, CW, D, ADJ> ls(a.tpc);
+  LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
 
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool ofwd = pass == 0;
-    for (int gi = 0; gi < (ofwd ? G : G - 1); ++gi) {
-      const int g = ofwd ? gi : G - 2 - gi;
+  const int nslab = slab_count(a, front);
+  for (int si = 0; si < nslab; ++si) {
+    {
+      const int2 gk = slab_at(a, front, si);
+      const int g = gk.x, kind = gk.y;
+      const bool ofwd = kind <= kFwdMid;
+      // couplings of the slab input: from the layer below (k0 - 1) and/or above (k1 + 1)
+      const bool from_below = (kind == kFwdLow && g > 0) || kind == kFwdMid || kind == kBwdHigh;
+      const bool from_above = (kind == kFwdHigh && g < Gz - 1) || kind == kFwdMid || kind == kBwdLow;
       const GroupInfo gz = a.groups[g];
       const int Wz = gz.W, k0 = gz.first, k1 = gz.last, zw0 = gz.w0;
-      for (int lp = 0; lp < 2 * G - 1; ++lp) {
-        const bool ifwd = lp < G;
-        const int l = ifwd ? lp : 2 * G - 2 - lp;
-        const GroupInfo gy = a.groups[l];
+      const int line_mid = (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2;
+      for (int lp = 0; lp < 2 * Gy - 1; ++lp) {
+        const bool ifwd = lp < Gy;
+        const int l = ifwd ? lp : 2 * Gy - 2 - lp;
+        const GroupInfo gy = a.groups[Gz + l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
-        const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-        ls.begin_line(T, B, n);
+        const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
+        ls.begin_line(T, B, n, line_mid);
         ls.fill();   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
@@ -363,12 +414,15 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) 
           if (ifwd) {
             if (j >= j0) {
               if (ofwd) {
-                if (k >= k0) {
+                if (k >= k0 && k <= k1) {
                   val = cvt<C>(f[gidx(i, j, k)]);
-                  if (g > 0 && k == k0) val = csub(val, cmul(cf[k0], cvt<C>(u[gidx(i, j, k0 - 1)])));
+                  if (from_below && k == k0) val = csub(val, cmul(cf[k0], cvt<C>(u[gidx(i, j, k0 - 1)])));
+                  if (from_above && k == k1) val = csub(val, cmul(cb[k1], cvt<C>(u[gidx(i, j, k1 + 1)])));
                 }
-              } else if (k == k1) {
+              } else if (from_above && k == k1) {
                 val = cmul(cb[k1], cvt<C>(u[gidx(i, j, k1 + 1)]));
+              } else if (from_below && k == k0) {
+                val = cmul(cf[k0], cvt<C>(u[gidx(i, j, k0 - 1)]));
               }
               if (l > 0 && j == j0) val = csub(val, cmul(cf[j0], v[((long long)kk * n + (j0 - 2)) * n + i]));
             }
@@ -393,7 +447,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) 
       const int nph = k1 - k0 + 1;
       for (int e = tid; e < n * n * nph; e += NT) {
         const int i = e % n, jm = (e / n) % n, kp = e / (n * n);
-        const int kk = Wz - nph + kp;
+        const int kk = k0 - zw0 + kp;
         const C val = v[((long long)kk * n + jm) * n + i];
         const long long id = gidx(i, jm + 1, k0 + kp);
         u[id] = ofwd ? cvt<TO>(val) : cvt<TO>(csub(cvt<C>(u[id]), val));
@@ -404,11 +458,11 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_sweep(SweepArgs a) 
 }
 
 // Exact solve of a single line problem on its own grid (exposes the building block).
-template <typename R, int NC, int CW, int D, bool ADJ>
-__global__ void __launch_bounds__((max_threads<NC, CW>())) k_line_solve(SweepArgs a, int g, int l) {
+template <typename R, int NC, int CW, int D, bool ADJ, int CH>
+__global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_line_solve(SweepArgs a, int g, int l) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = a.n, G = a.G;
+  const int n = a.n, Gy = a.Gy;
   const LdsLayout L(n, a.maxB, (int)sizeof(C));
   C* sb = reinterpret_cast<C*>(smem_raw);
   C* ybuf = sb + L.ybuf;
@@ -423,12 +477,12 @@ __global__ void __launch_bounds__((max_threads<NC, CW>())) k_line_solve(SweepArg
     cb[m] = cvt<C>(a.coef[(ADJ ? 3 : 1) * (n + 2) + m]);
   }
   for (int m = tid; m < kZMax; m += NT) zeros[m] = mk((R)0, (R)0);
-  const int Wz = a.groups[g].W, Wy = a.groups[l].W, B = Wy * Wz;
+  const int Wz = a.groups[g].W, Wy = a.groups[a.Gz + l].W, B = Wy * Wz;
   const double2* r = reinterpret_cast<const double2*>(a.in) + (long long)blockIdx.x * n * B;
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
-  const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * G + l];
-  LineSolver<R, NC, CW, D, ADJ> ls(a.tpc);
-  ls.begin_line(T, B, n);
+  const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
+  LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
+  ls.begin_line(T, B, n, (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2);
   ls.fill();
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
@@ -483,43 +537,92 @@ hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Arg
   X(4, 5, 16, 12) X(4, 7, 16, 12) X(4, 9, 8, 4) X(4, 13, 6, 2) X(4, 16, 4, 2)          \
   X(8, 3, 16, 12) X(8, 4, 16, 10) X(8, 5, 8, 4) X(8, 7, 4, 0) X(8, 8, 2, 0)            \
   X(16, 1, 16, 16) X(16, 2, 16, 8)
+// one chain spanning the workgroup (the two-front middle slab, blocks up to 128): 8 lanes
+// per row
+#define HELM_SHAPES_ONE(X) X(8, 3, 16, 12) X(8, 6, 8, 6) X(8, 9, 4, 2) X(8, 12, 2, 2) X(8, 16, 2, 0)
+
+Shape choose_shape_one(int maxB) {
+  static const int cw[] = {3, 6, 9, 12, 16};
+  for (int c : cw)
+    if (8 * c >= maxB) return {8, c};
+  return {8, -1};
+}
 
 template <typename R, typename TI, typename TO, bool ADJ>
-hipError_t dispatch_sweep(Shape sh, int grid, size_t sm, hipStream_t s, SweepArgs a) {
-  const int t = 2 * a.tpc;
+hipError_t dispatch_sweep(Shape sh, int chains, int grid, size_t sm, hipStream_t s, SweepArgs a) {
   constexpr bool c64 = sizeof(R) == 4;
+  if (chains == 2) {
+    const int t = 2 * a.tpc;
 #define X(NC, CW, D64, D128)                                                              \
-  if (sh.nc == NC && sh.cw == CW) {                                                       \
-    if constexpr ((c64 ? D64 : D128) > 0)                                                 \
-      return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a); \
-    return hipErrorInvalidValue;                                                          \
-  }
-  HELM_SHAPES(X)
+    if (sh.nc == NC && sh.cw == CW) {                                                     \
+      if constexpr ((c64 ? D64 : D128) > 0)                                               \
+        return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ, 2>, grid, t, sm, s, a); \
+      return hipErrorInvalidValue;                                                        \
+    }
+    HELM_SHAPES(X)
 #undef X
+  } else {
+    const int t = a.tpc;
+#define X(NC, CW, D64, D128)                                                              \
+    if (sh.nc == NC && sh.cw == CW) {                                                     \
+      if constexpr ((c64 ? D64 : D128) > 0)                                               \
+        return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ, 1>, grid, t, sm, s, a); \
+      return hipErrorInvalidValue;                                                        \
+    }
+    HELM_SHAPES_ONE(X)
+#undef X
+  }
   return hipErrorInvalidValue;
 }
 
 template <typename R, bool ADJ>
-hipError_t dispatch_line(Shape sh, int grid, size_t sm, hipStream_t s, SweepArgs a, int g, int l) {
-  const int t = 2 * a.tpc;
+hipError_t dispatch_line(Shape sh, int chains, int grid, size_t sm, hipStream_t s, SweepArgs a,
+                         int g, int l) {
   constexpr bool c64 = sizeof(R) == 4;
+  if (chains == 2) {
+    const int t = 2 * a.tpc;
 #define X(NC, CW, D64, D128)                                                              \
-  if (sh.nc == NC && sh.cw == CW) {                                                       \
-    if constexpr ((c64 ? D64 : D128) > 0)                                                 \
-      return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ>, grid, t, sm, s, a, g, l); \
-    return hipErrorInvalidValue;                                                          \
-  }
-  HELM_SHAPES(X)
+    if (sh.nc == NC && sh.cw == CW) {                                                     \
+      if constexpr ((c64 ? D64 : D128) > 0)                                               \
+        return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ, 2>, grid, t, sm, s, a, g, l); \
+      return hipErrorInvalidValue;                                                        \
+    }
+    HELM_SHAPES(X)
 #undef X
+  } else {
+    const int t = a.tpc;
+#define X(NC, CW, D64, D128)                                                              \
+    if (sh.nc == NC && sh.cw == CW) {                                                     \
+      if constexpr ((c64 ? D64 : D128) > 0)                                               \
+        return launch_k(k_line_solve<R, NC, CW, (c64 ? D64 : D128), ADJ, 1>, grid, t, sm, s, a, g, l); \
+      return hipErrorInvalidValue;                                                        \
+    }
+    HELM_SHAPES_ONE(X)
+#undef X
+  }
   return hipErrorInvalidValue;
+}
+
+// the LDS regions of LdsLayout hold what a launch of this shape touches: published vectors of
+// NC*CW, zero/junk rows of B, and the step tables of its chains (2 (n/2) + 3 entries each with
+// two chains, 2n + 1 with one)
+bool lds_fits(int n, int maxB, Shape sh, int chains) {
+  const int ts = chains == 2 ? 2 * (n / 2) + 3 : 2 * n + 1;
+  return sh.nc * sh.cw <= kZMax && maxB <= kZMax && maxB <= sh.nc * sh.cw && chains * ts <= 2 * (n + 3);
 }
 
 SweepArgs base_args(helm_handle* h) {
   SweepArgs a;
+  const Plan& P = h->plan;
   a.n = h->n;
-  a.G = h->plan.G;
-  a.maxW = h->plan.maxW;
-  a.maxB = h->plan.maxB;
+  a.Gz = P.Gz;
+  a.Gy = P.Gy;
+  a.maxW = P.maxW;
+  a.maxB = P.maxB;
+  a.fronts = P.fronts;
+  a.zmid = P.zmid;
+  a.pass = 0;
+  a.nfront = 1;
   a.tpc = 0;
   a.N = (long long)h->n * h->n * h->n;
   a.in_stride = a.out_stride = a.N;
@@ -534,8 +637,30 @@ SweepArgs base_args(helm_handle* h) {
   return a;
 }
 
-size_t sweep_lds(const helm_handle* h, size_t csz) {
-  return LdsLayout(h->n, h->plan.maxB, (int)csz).bytes;
+// one launch of the sweep: pass (see SweepArgs), blocks up to maxB, two chains (shape from
+// the lanes override) or one chain spanning the workgroup
+template <typename R, typename TI, typename TO>
+hipError_t sweep_pass(helm_handle* h, SweepArgs a, int pass, int nfront, int maxB, int chains,
+                      int R_, bool adjoint, hipStream_t s) {
+  a.pass = pass;
+  a.nfront = nfront;
+  a.maxB = maxB;
+  const Shape sh = chains == 2 ? choose_shape(maxB, h->lanes_override) : choose_shape_one(maxB);
+  if (sh.cw < 0 || !lds_fits(h->n, maxB, sh, chains)) return hipErrorInvalidValue;
+  a.tpc = chain_threads(maxB, sh.nc);
+  const size_t sm = LdsLayout(h->n, maxB, (int)sizeof(typename cx<R>::type)).bytes;
+  return adjoint ? dispatch_sweep<R, TI, TO, true>(sh, chains, R_ * nfront, sm, s, a)
+                 : dispatch_sweep<R, TI, TO, false>(sh, chains, R_ * nfront, sm, s, a);
+}
+
+template <typename R, typename TI, typename TO>
+hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStream_t s) {
+  const Plan& P = h->plan;
+  if (P.fronts == 1) return sweep_pass<R, TI, TO>(h, a, 0, 1, P.maxB, 2, R_, adjoint, s);
+  hipError_t e = sweep_pass<R, TI, TO>(h, a, 1, 2, P.maxB_front, 2, R_, adjoint, s);
+  if (e == hipSuccess) e = sweep_pass<R, TI, TO>(h, a, 2, 1, P.maxB_mid, 1, R_, adjoint, s);
+  if (e == hipSuccess) e = sweep_pass<R, TI, TO>(h, a, 3, 2, P.maxB_front, 2, R_, adjoint, s);
+  return e;
 }
 
 }  // namespace
@@ -547,7 +672,8 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   const int n = h->n;
   const bool c64 = h->prec == HELM_C64;
   const size_t csz = c64 ? sizeof(float2) : sizeof(double2);
-  const size_t need = (size_t)R * n * n * h->plan.maxW * csz;
+  // one slab iterate per workgroup: two per right-hand side with two fronts
+  const size_t need = (size_t)R * h->plan.fronts * n * n * h->plan.maxW * csz;
   if (need > h->slab_scratch_bytes) {
     if (h->slab_scratch) {
       hipError_t e = hipFree(h->slab_scratch);
@@ -566,24 +692,16 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   a.out_stride = z_stride;
   a.rhs_idx = rhs_idx;
   a.scratch = h->slab_scratch;
-  const size_t sm = sweep_lds(h, csz);
-  const int mb = h->plan.maxB;
-  const Shape sh = choose_shape(mb, h->lanes_override);
-  if (sh.cw < 0) return hipErrorInvalidValue;
-  a.tpc = chain_threads(mb, sh.nc);
   if (!r64) return hipErrorInvalidValue;  // inputs are always complex128
   if (!c64 && !z64) return hipErrorInvalidValue;
   hipEvent_t ev = h->t_apply.begin(s);
   hipError_t e;
   if (!c64)
-    e = adjoint ? dispatch_sweep<double, double2, double2, true>(sh, R, sm, s, a)
-                : dispatch_sweep<double, double2, double2, false>(sh, R, sm, s, a);
+    e = sweep_all<double, double2, double2>(h, a, R, adjoint, s);
   else if (z64)
-    e = adjoint ? dispatch_sweep<float, double2, double2, true>(sh, R, sm, s, a)
-                : dispatch_sweep<float, double2, double2, false>(sh, R, sm, s, a);
+    e = sweep_all<float, double2, double2>(h, a, R, adjoint, s);
   else
-    e = adjoint ? dispatch_sweep<float, double2, float2, true>(sh, R, sm, s, a)
-                : dispatch_sweep<float, double2, float2, false>(sh, R, sm, s, a);
+    e = sweep_all<float, double2, float2>(h, a, R, adjoint, s);
   h->t_apply.end(ev, s, R);
   return e;
 }
@@ -592,17 +710,22 @@ hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, d
                              bool adjoint, hipStream_t s) {
   const bool c64 = h->prec == HELM_C64;
   const size_t csz = c64 ? sizeof(float2) : sizeof(double2);
+  const Plan& P = h->plan;
   SweepArgs a = base_args(h);
   a.in = r;
   a.out = x;
-  const size_t sm = sweep_lds(h, csz);
-  const int mb = h->plan.maxB;
-  const Shape sh = choose_shape(mb, h->lanes_override);
-  if (sh.cw < 0) return hipErrorInvalidValue;
+  // lines of the two-front middle slab: one chain over the workgroup, x1-order factors
+  const bool one = P.fronts == 2 && zg == P.zmid;
+  const int mb = one ? P.maxB_mid : (P.fronts == 2 ? P.maxB_front : P.maxB);
+  a.maxB = mb;
+  const size_t sm = LdsLayout(h->n, mb, (int)csz).bytes;
+  const Shape sh = one ? choose_shape_one(mb) : choose_shape(mb, h->lanes_override);
+  if (sh.cw < 0 || !lds_fits(h->n, mb, sh, one ? 1 : 2)) return hipErrorInvalidValue;
   a.tpc = chain_threads(mb, sh.nc);
+  const int chains = one ? 1 : 2;
   if (c64)
-    return adjoint ? dispatch_line<float, true>(sh, R, sm, s, a, zg, yg)
-                   : dispatch_line<float, false>(sh, R, sm, s, a, zg, yg);
-  return adjoint ? dispatch_line<double, true>(sh, R, sm, s, a, zg, yg)
-                 : dispatch_line<double, false>(sh, R, sm, s, a, zg, yg);
+    return adjoint ? dispatch_line<float, true>(sh, chains, R, sm, s, a, zg, yg)
+                   : dispatch_line<float, false>(sh, chains, R, sm, s, a, zg, yg);
+  return adjoint ? dispatch_line<double, true>(sh, chains, R, sm, s, a, zg, yg)
+                 : dispatch_line<double, false>(sh, chains, R, sm, s, a, zg, yg);
 }

@@ -1,7 +1,8 @@
 """GPU parity at the workloads' full sizes.
 
 31^3 (plain method, complex128): the whole preconditioner is compared element by element with
-the oracle's Algorithm 6 on seeded right-hand sides, and the solve with a sparse direct solve.
+the oracle's Algorithm 6 on seeded right-hand sides (one front and two fronts), and the solve
+with a sparse direct solve.
 127^3 (the batched mixed-precision workload): the oracle cannot run a whole sweep in seconds,
 so sampled line factorisations are compared block by block with the oracle's, and the sweep is
 checked through properties that hold at any size: the adjoint dot test
@@ -62,6 +63,30 @@ def test_c1_apply_matches_oracle(c1_oracle, prec, tol):
     ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
     err = rel(z, ref)
     print(f"c1 apply {prec}: rel err {err:.2e}")
+    assert err <= tol
+
+
+@pytest.fixture(scope="module")
+def c1_two_front_oracle():
+    wl, _ = workload("c1")
+    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], fronts=2)
+    return wl, O.RecursiveSweep(prob)
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
+    """Two fronts at 31^3: the middle slab's lines have blocks of 13 x 7 = 91 unknowns (moving
+    PML on both sides in x3), solved by the one-chain shapes."""
+    wl, M = c1_two_front_oracle
+    n = wl["n"]
+    x = inputs.random_rhs(n, 2, seed=22)
+    from paper_1502_07266_amd.binding import Helm
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=2)
+    z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    H.close()
+    ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
+    err = rel(z, ref)
+    print(f"c1 two-front apply {prec}: rel err {err:.2e}")
     assert err <= tol
 
 

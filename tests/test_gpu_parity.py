@@ -25,6 +25,12 @@ CASES = {
     # the shortest lines: n = 3 has no lower chain in the two-sided line solve, n = 4 one block
     "tiny3": dict(n=3, b=1, p=1, d=1),
     "tiny4": dict(n=4, b=1, p=1, d=1),
+    # two fronts in x3: the fronts run in separate workgroups and launches, the middle slab's
+    # lines (moving PML on both sides in x3, larger blocks) in x1 order with one chain
+    "b4p4_2f": dict(n=15, b=4, p=4, d=1, fronts=2),
+    "ragged_2f": dict(n=16, b=3, p=2, d=2, fronts=2),
+    "tiny3_2f": dict(n=3, b=1, p=1, d=1, fronts=2),
+    "tiny4_2f": dict(n=4, b=1, p=1, d=1, fronts=2),
 }
 _cache = {}
 
@@ -33,7 +39,8 @@ def case(name):
     if name not in _cache:
         cfg = CASES[name]
         sc = inputs.small_case(n=cfg["n"], b=cfg["b"], p=cfg["p"], d=cfg["d"])
-        prob = O.Problem(n=cfg["n"], c=sc["c"], omega=sc["omega"], b=cfg["b"], C=sc["C"], p=cfg["p"], d=cfg["d"])
+        prob = O.Problem(n=cfg["n"], c=sc["c"], omega=sc["omega"], b=cfg["b"], C=sc["C"], p=cfg["p"], d=cfg["d"],
+                         fronts=cfg.get("fronts", 1))
         _cache[name] = (sc, prob, O.RecursiveSweep(prob))
     return _cache[name]
 
@@ -42,7 +49,7 @@ def helm(name, prec):
     from paper_1502_07266_amd.binding import Helm
     sc, prob, _ = case(name)
     c = torch.from_numpy(sc["c"]).cuda()
-    return Helm(c, sc["omega"], prob.b, prob.C, prob.p, prob.d, prec=prec)
+    return Helm(c, sc["omega"], prob.b, prob.C, prob.p, prob.d, prec=prec, fronts=prob.fronts)
 
 
 def rel(a, b):
@@ -80,8 +87,10 @@ def test_line_factors(name, prec, tol):
     worst = 0.0
     for g, l, ln in M.lines():
         T = H.line_factors(g, l).cpu().numpy()
-        # the library eliminates the x1-blocks from both ends towards the middle
-        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order="two-sided")
+        # the library eliminates the x1-blocks from both ends towards the middle, except on the
+        # two-front middle slab (x1 order)
+        mid_slab = prob.fronts == 2 and g == len(M.Gz) // 2
+        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order="up" if mid_slab else "two-sided")
         ref = np.stack(ln.block_T)
         assert T.shape == ref.shape
         e = max(rel(T[i], ref[i]) for i in range(prob.n))
@@ -97,7 +106,7 @@ def test_line_solve(name, adjoint):
     H = helm(name, "c128")
     rng = np.random.default_rng(3)
     Gz, Gy = len(M.Gz), len(M.Gy)
-    picks = [(0, 0), (1, 0), (0, 2), (3, 5), (Gz - 1, Gy - 1)]
+    picks = [(0, 0), (1, 0), (0, 2), (3, 5), (Gz - 1, Gy - 1), (Gz // 2, 0), (Gz // 2, Gy - 1)]
     for (g, l) in [(g, l) for (g, l) in picks if g < Gz and l < Gy]:
         ln = M.slabs[g].lines[l]
         Nl = ln.K.shape[0]
@@ -123,11 +132,12 @@ def test_apply(name, prec, tol, adjoint):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("name", ["b4p4", "b4p4_2f"])
 @pytest.mark.parametrize("lanes", [4, 8, 16])
-def test_apply_launch_shape_invariant(lanes):
-    sc, prob, M = case("b4p4")
+def test_apply_launch_shape_invariant(lanes, name):
+    sc, prob, M = case(name)
     x = rhs(prob.n, 2, seed=8)
-    H = helm("b4p4", "c128")
+    H = helm(name, "c128")
     H.set_launch(lanes)
     z = H.apply(to_gpu(x)).cpu().numpy()
     ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
