@@ -205,7 +205,8 @@ int helm_set_launch(helm_handle* h, int lanes_per_row);
  * in / appended to that file (one JSON object per line, keyed by n, largest block and
  * precision), so the timing runs once per configuration.  *lanes_out (may be NULL) receives
  * the choice and *ns_per_step (may be NULL) its measured time per x1-block of a line solve,
- * i.e. the time of one line solve divided by n (0 when taken from the cache).  Results of later sweeps change only by rounding (summation order).
+ * i.e. the time of one line solve divided by n (0 when taken from the cache).  Results of
+ * later sweeps change only by rounding (summation order).
  * Synchronises `stream`.
  */
 int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,
@@ -227,6 +228,12 @@ typedef struct {
   long long matvec_rhs;
   double matvec_ms;
   double matvec_bytes_per_rhs; /* 40 bytes per grid point (u, kappa read; y written)          */
+  /* the sweep's dominant kernel: the whole sweep with one front; with two fronts the two   */
+  /* launches that run both fronts (forward, then backward), without the middle slab        */
+  long long kernel_launches;
+  long long kernel_rhs;
+  double kernel_ms;
+  double kernel_bytes_per_rhs; /* algorithmic bytes of one such launch per right-hand side    */
 } helm_stats;
 
 /* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */

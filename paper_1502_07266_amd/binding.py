@@ -29,7 +29,9 @@ class helm_stats(ctypes.Structure):
                 ("apply_rhs", ctypes.c_longlong), ("apply_ms", ctypes.c_double),
                 ("apply_bytes_per_rhs", ctypes.c_double), ("matvec_launches", ctypes.c_longlong),
                 ("matvec_rhs", ctypes.c_longlong), ("matvec_ms", ctypes.c_double),
-                ("matvec_bytes_per_rhs", ctypes.c_double)]
+                ("matvec_bytes_per_rhs", ctypes.c_double), ("kernel_launches", ctypes.c_longlong),
+                ("kernel_rhs", ctypes.c_longlong), ("kernel_ms", ctypes.c_double),
+                ("kernel_bytes_per_rhs", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p

@@ -70,9 +70,26 @@ double sweep_bytes_per_rhs(const Plan& p, int prec) {
   return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
 }
 
+// the same for one launch of the dominant kernel: with two fronts, one of the two launches
+// that run both fronts over every x3-group but the middle one (each line once per inner pass)
+double kernel_bytes_per_rhs(const Plan& p, int prec) {
+  if (p.fronts == 1) return sweep_bytes_per_rhs(p, prec);
+  double acc = 0.0;
+  for (int g = 0; g < p.Gz; ++g) {
+    if (g == p.zmid) continue;
+    for (int l = 0; l < p.Gy; ++l) {
+      const double B = p.line_B[(size_t)g * p.Gy + l];
+      acc += (l < p.Gy - 1 ? 2.0 : 1.0) * 2.0 * p.n * B * B;
+    }
+  }
+  const double N = (double)p.n * p.n * p.n;
+  return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
+}
+
 void release(helm_handle* h) {
   h->t_apply.reset();
   h->t_matvec.reset();
+  h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
                   h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
   for (void* p : ptrs)
@@ -164,6 +181,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return bail(HELM_EHIP, "copying the plan failed");
   h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
+  h->kernel_bytes_per_rhs = kernel_bytes_per_rhs(plan, prec);
   LaunchTimer t_setup;
   hipEvent_t ev = t_setup.begin(s);
   if (launch_coefficients(h, c_dev, true, s) != hipSuccess) return bail(HELM_EHIP, "coefficient kernels failed");
@@ -425,6 +443,11 @@ int helm_get_stats(helm_handle* h, helm_stats* out) {
   out->matvec_rhs = h->t_matvec.rhs;
   out->matvec_ms = h->t_matvec.ms;
   out->matvec_bytes_per_rhs = 40.0 * h->n * h->n * h->n;
+  h->t_kernel.flush();
+  out->kernel_launches = h->t_kernel.launches;
+  out->kernel_rhs = h->t_kernel.rhs;
+  out->kernel_ms = h->t_kernel.ms;
+  out->kernel_bytes_per_rhs = h->kernel_bytes_per_rhs;
   return HELM_OK;
 }
 
@@ -432,6 +455,7 @@ int helm_reset_stats(helm_handle* h) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
   h->t_apply.reset();
   h->t_matvec.reset();
+  h->t_kernel.reset();
   return HELM_OK;
 }
 

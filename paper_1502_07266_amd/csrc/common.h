@@ -185,8 +185,10 @@ struct helm_handle {
 
   // timing
   LaunchTimer t_apply, t_matvec;
+  LaunchTimer t_kernel;            // the sweep's dominant kernel (see helm_stats)
   double setup_ms = 0.0;
   double apply_bytes_per_rhs = 0.0;
+  double kernel_bytes_per_rhs = 0.0;
 
   // apply workspace (grown on demand)
   void* slab_scratch = nullptr;

@@ -653,13 +653,21 @@ hipError_t sweep_pass(helm_handle* h, SweepArgs a, int pass, int nfront, int max
                  : dispatch_sweep<R, TI, TO, false>(sh, chains, R_ * nfront, sm, s, a);
 }
 
+// the whole sweep; launches of the dominant kernel (all of it with one front, the two front
+// passes with two) are timed on their own as well
 template <typename R, typename TI, typename TO>
 hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStream_t s) {
   const Plan& P = h->plan;
-  if (P.fronts == 1) return sweep_pass<R, TI, TO>(h, a, 0, 1, P.maxB, 2, R_, adjoint, s);
-  hipError_t e = sweep_pass<R, TI, TO>(h, a, 1, 2, P.maxB_front, 2, R_, adjoint, s);
+  auto timed = [&](int pass, int nfront, int maxB, int chains) {
+    hipEvent_t ev = h->t_kernel.begin(s);
+    hipError_t e = sweep_pass<R, TI, TO>(h, a, pass, nfront, maxB, chains, R_, adjoint, s);
+    h->t_kernel.end(ev, s, R_);
+    return e;
+  };
+  if (P.fronts == 1) return timed(0, 1, P.maxB, 2);
+  hipError_t e = timed(1, 2, P.maxB_front, 2);
   if (e == hipSuccess) e = sweep_pass<R, TI, TO>(h, a, 2, 1, P.maxB_mid, 1, R_, adjoint, s);
-  if (e == hipSuccess) e = sweep_pass<R, TI, TO>(h, a, 3, 2, P.maxB_front, 2, R_, adjoint, s);
+  if (e == hipSuccess) e = timed(3, 2, P.maxB_front, 2);
   return e;
 }
 

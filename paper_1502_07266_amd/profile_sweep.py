@@ -1,5 +1,6 @@
 """Driver for hardware-counter runs of the sweep: one plain copy of a known size, then one
-batched sweep (helm_apply) of a workload, each a single kernel dispatch.
+batched sweep (helm_apply) of a workload (one kernel dispatch with one front; with two
+fronts, two dispatches of the front kernel and one of the middle slab).
 
     python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024
 
@@ -24,6 +25,7 @@ def main():
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--rhs", type=int, default=0, help="right-hand sides (0: all of the workload)")
+    ap.add_argument("--fronts", type=int, default=2, choices=[1, 2])
     args = ap.parse_args()
 
     wl = inputs.workload(args.workload)
@@ -47,7 +49,7 @@ def main():
 
     c = torch.from_numpy(wl["c"]).to(dev)
     F = torch.from_numpy(inputs.sources(n, nodes)).to(dev)
-    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec)
+    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec, fronts=args.fronts)
     H.reset_stats()
     t0 = time.perf_counter()
     H.apply(F)
@@ -55,10 +57,12 @@ def main():
     st = H.stats()
     print(f"[profile] apply {args.prec} R={R}: {st['apply_ms']:.1f} ms "
           f"(host {1e3 * (time.perf_counter() - t0):.1f} ms)", flush=True)
-    print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R,
+    print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R, "fronts": args.fronts,
                       "copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": copy_ms,
                       "apply_ms": st["apply_ms"],
-                      "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R}), flush=True)
+                      "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R,
+                      "kernel_launches": st["kernel_launches"], "kernel_ms": st["kernel_ms"],
+                      "kernel_algorithmic_bytes_per_launch": st["kernel_bytes_per_rhs"] * R}), flush=True)
     H.close()
 
 
