@@ -151,7 +151,8 @@ class Problem:
     x3); first_y / first_z: size of the first group along x2 / x3 (b by default; other
     values only serve the degenerate-partition pins); fronts: 1 for the single-front outer
     sweep of Algorithm 6, 2 for the outer sweep from both x3-faces meeting in a middle slab
-    (the configuration of the paper's experiments, Sec. 4.2 note 3 and Sec. 5).
+    (the configuration of the paper's experiments, Sec. 4.2 note 3 and Sec. 5); fronts_inner:
+    the same choice for the inner sweep over x2 (Algorithm 4).
     """
     n: int
     c: np.ndarray
@@ -163,6 +164,7 @@ class Problem:
     first_y: Optional[int] = None
     first_z: Optional[int] = None
     fronts: int = 1
+    fronts_inner: int = 1
     h: float = field(init=False)
 
     def __post_init__(self):

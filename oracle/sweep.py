@@ -82,9 +82,9 @@ class LineFactors:
     def __init__(self, prob, Gz, zg, Gy, yg, order="up"):
         n, h = prob.n, prob.h
         zw0, zw1, zfirst, zlast = window_fronts(Gz, zg, prob.p, prob.fronts)
-        yw0, yw1, yfirst = window(Gy, yg, prob.p)
+        yw0, yw1, yfirst, ylast = window_fronts(Gy, yg, prob.p, prob.fronts_inner)
         px = prob.boundary_axis()
-        py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p)
+        py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p, ylast)
         pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast)
         K = assemble_box(prob.kappa[zw0 - 1:zw1, yw0 - 1:yw1, :], px, py, pz, h)
         self.Wy, self.Wz = yw1 - yw0 + 1, zw1 - zw0 + 1
@@ -110,8 +110,8 @@ class LineFactors:
             done.add(i)
         self.rank = {i: t for t, i in enumerate(self.order)}
         # line-grid unknowns of the physical rows (those of G_yg), in (kk, j, i) C-order
-        a = Gy[yg][0]
-        self.phys = idx[:, a - yw0:, :].ravel()
+        a, e = Gy[yg]
+        self.phys = idx[:, a - yw0:e - yw0 + 1, :].ravel()
 
     def _nbrs(self, i, before):
         """Neighbours of block i eliminated before (or after) it."""
@@ -166,6 +166,7 @@ class SlabSweep:
         self.rows = [idx[:, a - 1:e, :].ravel() for (a, e) in Gy]
         a, e = Gz[zg]
         self.phys = idx[a - zw0:e - zw0 + 1, :, :].ravel()
+        self.fronts_inner = prob.fronts_inner
         self.lines = [LineFactors(prob, Gz, zg, Gy, yg) for yg in range(len(Gy))]  # Alg. 3
 
     def _line(self, yg, alpha, adjoint):
@@ -177,12 +178,34 @@ class SlabSweep:
         return x[ln.phys]
 
     def apply(self, gv, adjoint=False):
-        """Algorithm 4: v ~ H^{-1} g (or the adjoint with H^H couplings and line adjoints)."""
+        """Algorithm 4: v ~ H^{-1} g (or the adjoint with H^H couplings and line adjoints).
+        With two inner fronts the x2-groups are eliminated 0..mid-1, L-1..mid+1, mid (the same
+        block order and couplings as the two-front outer sweep, one level down)."""
         H = self.HH if adjoint else self.H
         gv = _cols(gv)
         v = np.zeros(gv.shape, np.complex128)
         R = self.rows
         L = len(R)
+        if self.fronts_inner == 2:
+            blk = lambda a, b: H[R[a]][:, R[b]]
+            mid = L // 2
+            for yg in range(mid):
+                rhs = gv[R[yg]].astype(np.complex128)
+                if yg > 0:
+                    rhs = rhs - blk(yg, yg - 1) @ v[R[yg - 1]]
+                v[R[yg]] = self._line(yg, rhs, adjoint)
+            for yg in range(L - 1, mid, -1):
+                rhs = gv[R[yg]].astype(np.complex128)
+                if yg < L - 1:
+                    rhs = rhs - blk(yg, yg + 1) @ v[R[yg + 1]]
+                v[R[yg]] = self._line(yg, rhs, adjoint)
+            rhs = gv[R[mid]] - blk(mid, mid - 1) @ v[R[mid - 1]] - blk(mid, mid + 1) @ v[R[mid + 1]]
+            v[R[mid]] = self._line(mid, rhs, adjoint)
+            for yg in range(mid - 1, -1, -1):
+                v[R[yg]] = v[R[yg]] - self._line(yg, blk(yg, yg + 1) @ v[R[yg + 1]], adjoint)
+            for yg in range(mid + 1, L):
+                v[R[yg]] = v[R[yg]] - self._line(yg, blk(yg, yg - 1) @ v[R[yg - 1]], adjoint)
+            return v
         for yg in range(L):
             rhs = gv[R[yg]].astype(np.complex128)
             if yg > 0:
@@ -210,7 +233,8 @@ class RecursiveSweep:
         n = prob.n
         self.Gz = (groups_two_fronts(n, prob.b, prob.d) if prob.fronts == 2
                    else groups(n, prob.first_z, prob.d))
-        self.Gy = groups(n, prob.first_y, prob.d)
+        self.Gy = (groups_two_fronts(n, prob.b, prob.d) if prob.fronts_inner == 2
+                   else groups(n, prob.first_y, prob.d))
         self.A = helmholtz_matrix(prob)
         self.AH = self.A.conj().T.tocsr()
         idx = np.arange(n ** 3).reshape(n, n, n)

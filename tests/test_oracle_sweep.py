@@ -264,3 +264,42 @@ def test_two_front_preconditioner_linear_adjoint_and_effective():
     M1 = O.RecursiveSweep(_prob(n=11))
     _, its1, _ = O.fgmres(lambda v: M1.A @ v, lambda v: M1.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
     assert its <= its1 + 3, (its, its1)
+
+
+def _mirror_y(v, n):
+    """x2 -> 1 - x2 on vectors ordered x1 fastest (unknown (k, j, i) -> (k, n-1-j, i))."""
+    return np.asarray(v).reshape(n, n, n, -1)[:, ::-1].reshape(n ** 3, -1)
+
+
+@pytest.mark.parametrize("fronts", [1, 2])
+def test_two_inner_fronts_commute_with_x2_mirror(fronts):
+    """Two fronts in the inner sweep (x2): with a medium symmetric in x2 and a symmetric x2
+    partition, M^{-1} commutes with x2 -> 1 - x2 (the single inner front does not)."""
+    n, b, p = 11, 3, 3
+    case = inputs.small_case(n=n, b=b, p=p, d=1)
+    c = case["c"]
+    c = 0.5 * (c + c[:, ::-1])                   # symmetric in x2
+    kw = dict(n=n, c=c, omega=case["omega"], b=b, C=case["C"], p=p, d=1, fronts=fronts)
+    M = O.RecursiveSweep(O.Problem(fronts_inner=2, **kw))
+    f = inputs.random_rhs(n, 2, seed=23).reshape(2, -1).T
+    assert _rel(M.apply(_mirror_y(f, n)), _mirror_y(M.apply(f), n)) < 1e-12
+    M1 = O.RecursiveSweep(O.Problem(fronts_inner=1, **kw))
+    assert _rel(M1.apply(_mirror_y(f, n)), _mirror_y(M1.apply(f), n)) > 1e-6
+
+
+def test_two_inner_fronts_linear_adjoint_and_effective():
+    prob = _prob(n=11, fronts=2, fronts_inner=2)
+    M = O.RecursiveSweep(prob)
+    x, y = inputs.random_rhs(11, 2, seed=9).reshape(2, -1)
+    a, bb = 1.3 + 0.2j, -0.7 + 2.0j
+    assert _rel(M.apply(a * x + bb * y)[:, 0], a * M.apply(x)[:, 0] + bb * M.apply(y)[:, 0]) < 1e-13
+    d1 = np.vdot(M.apply(x)[:, 0], y)
+    d2 = np.vdot(x, M.apply(y, adjoint=True)[:, 0])
+    assert abs(d1 - d2) <= 1e-13 * abs(d1)
+    f = inputs.random_rhs(11, 1, seed=4).reshape(-1)
+    xs = spla.spsolve(M.A.tocsc(), f)
+    u, its, _ = O.fgmres(lambda v: M.A @ v, lambda v: M.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
+    assert _rel(u, xs) < 1e-8
+    M1 = O.RecursiveSweep(_prob(n=11))
+    _, its1, _ = O.fgmres(lambda v: M1.A @ v, lambda v: M1.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
+    assert its <= its1 + 3, (its, its1)
