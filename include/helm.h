@@ -55,29 +55,33 @@ typedef struct {
                             /* Algorithm 6; 2 = from both faces meeting in a middle slab   */
                             /* padded with moving PML on both sides (Sec. 4.2 note 3, the  */
                             /* configuration of Sec. 5)                                    */
+  int fronts_inner;         /* the same choice for the inner sweep over x2 (Algorithm 4):  */
+                            /* 1 (or 0) from x2 = 0 only; 2 from both faces, meeting in a  */
+                            /* middle x2-group                                              */
 } helm_pml;
 
 /*
  * helm_setup -- Algorithm 5 (with Algorithm 3 per slab, Sec. 4.2): form and block-LDU factor
  * every quasi-1D auxiliary ("line") problem.
  *   grid, pml     : host structs.  Requires n >= 2b+1, b >= 1, 0 <= p <= b, C > 0,
- *                   pml->fronts in {0, 1, 2}.
+ *                   pml->fronts and pml->fronts_inner in {0, 1, 2}.
  *   c_dev         : n^3 float64 velocities at the nodes, all finite and > 0; may be freed
  *                   after the call (the handle keeps omega^2/c^2).
  *   omega         : angular frequency > 0.
  *   slab_layers   : d >= 1, physical layers per auxiliary problem in x3 and in x2 (Sec. 4.2).
  *   prec          : HELM_C64 or HELM_C128 (precision of factors and sweeps).
  *   out           : receives the handle (NULL on error).
- * Groups along x2 (and x3 with one front): nodes 1..b, then consecutive groups of d nodes
+ * Groups along an axis swept from one face: nodes 1..b, then consecutive groups of d nodes
  * (the last may be shorter).  The auxiliary problem of every group but the first is padded
  * with p moving-PML nodes whose zero-Dirichlet plane lies p+1 spacings below the group, with
  * sigma(.; (p+1)h) measured from that plane; above the group's first node the boundary
- * profile is kept.  With two fronts the x3-groups are nodes 1..b, groups of d over
- * b+1..n-b (the last may be shorter) and nodes n-b+1..n; with G of them the middle one is
- * group G/2; groups below it are padded below as above, groups above it padded above with
- * the mirror image (plane p+1 spacings above the group), the middle group on both sides, and
- * the first and last groups not at all.  Limits: every line block B = (x2 window) x (x3
- * window) <= 64, except the two-front middle slab's, <= 128 (complex64) or 96 (complex128).
+ * profile is kept.  Along an axis swept from both faces (x3 with fronts = 2, x2 with
+ * fronts_inner = 2) the groups are nodes 1..b, groups of d over b+1..n-b (the last may be
+ * shorter) and nodes n-b+1..n; with G of them the middle one is group G/2; groups below it
+ * are padded below as above, groups above it padded above with the mirror image (plane p+1
+ * spacings above the group), the middle group on both sides, and the first and last groups
+ * not at all.  Limits: every line block B = (x2 window) x (x3 window) <= 64, except on a
+ * middle group, <= 128 (complex64) or 96 (complex128).
  * Errors: HELM_EINVAL, HELM_ENOMEM (factor bytes > free memory), HELM_ESINGULAR, HELM_EHIP.
  * Synchronises `stream`.
  */
@@ -91,7 +95,9 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
  * outer sweep is the block LDU with the x3-groups eliminated from both faces towards the
  * middle group (forward: each front carries its f - A u coupling, the middle slab takes
  * both; backward: each front subtracts the correction from its neighbour nearer the middle),
- * in three launches (fronts forward, middle slab, fronts backward).
+ * in three launches (fronts forward, middle slab, fronts backward).  Two inner fronts do the
+ * same over the x2-groups of every slab, in three launches per slab (inner fronts forward,
+ * middle line, inner fronts backward).
  *   r_dev, z_dev : R*n^3 complex128 each (may not alias).  In HELM_C64 mode r is rounded to
  *                  complex64 on entry and z is widened on exit.
  */
@@ -175,8 +181,9 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
  * ends towards the middle block m (0-based): block i < m holds the inverse Schur complement
  * after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks i+1..n-1, and
  * block m the one after all others, which equals the (m, m) block of the line matrix's
- * inverse.  m = n/2 (integer division), except for the lines of the two-front middle slab,
- * where m = n-1 (the x1 order of Sec. 3).  The solve is exact for any such order.
+ * inverse.  m = n/2 (integer division), except for the lines on a middle group (the middle
+ * x3-group with two fronts, the middle x2-group with two inner fronts), where m = n-1 (the
+ * x1 order of Sec. 3).  The solve is exact for any such order.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
  * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
  */
@@ -228,12 +235,15 @@ typedef struct {
   long long matvec_rhs;
   double matvec_ms;
   double matvec_bytes_per_rhs; /* 40 bytes per grid point (u, kappa read; y written)          */
-  /* the sweep's dominant kernel: the whole sweep with one front; with two fronts the two   */
-  /* launches that run both fronts (forward, then backward), without the middle slab        */
+  /* the sweep's dominant kernel: its two-chain launches (all lines but those on a middle    */
+  /* group; one launch per outer pass with one inner front, two per slab with two)          */
   long long kernel_launches;
   long long kernel_rhs;
   double kernel_ms;
-  double kernel_bytes_per_rhs; /* algorithmic bytes of one such launch per right-hand side    */
+  double kernel_bytes_per_rhs; /* algorithmic bytes of one such launch per right-hand side,   */
+                               /* averaged over a sweep's launches: factor bytes of its line  */
+                               /* solves plus 16 bytes per grid point it reads as input and   */
+                               /* 16 per point it writes as output                            */
 } helm_stats;
 
 /* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */

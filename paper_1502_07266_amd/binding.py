@@ -21,7 +21,8 @@ class helm_grid(ctypes.Structure):
 
 
 class helm_pml(ctypes.Structure):
-    _fields_ = [("b", ctypes.c_int), ("C", ctypes.c_double), ("p", ctypes.c_int), ("fronts", ctypes.c_int)]
+    _fields_ = [("b", ctypes.c_int), ("C", ctypes.c_double), ("p", ctypes.c_int), ("fronts", ctypes.c_int),
+                ("fronts_inner", ctypes.c_int)]
 
 
 class helm_stats(ctypes.Structure):
@@ -103,10 +104,11 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def plan_bytes(n, b, C, p, slab_layers=1, prec=HELM_C64, fronts=1):
+def plan_bytes(n, b, C, p, slab_layers=1, prec=HELM_C64, fronts=1, fronts_inner=1):
     """Device bytes of a setup, computed on the host: (bytes, n_lines, max_block)."""
     nb, nl, mb = ctypes.c_size_t(), _I(), _I()
-    _check(lib().helm_plan_bytes(ctypes.byref(helm_grid(n)), ctypes.byref(helm_pml(b, C, p, fronts)),
+    pml = helm_pml(b, C, p, fronts, fronts_inner)
+    _check(lib().helm_plan_bytes(ctypes.byref(helm_grid(n)), ctypes.byref(pml),
                                  slab_layers, prec, ctypes.byref(nb), ctypes.byref(nl),
                                  ctypes.byref(mb)), "helm_plan_bytes")
     return nb.value, nl.value, mb.value
@@ -117,10 +119,11 @@ class Helm:
 
     c: float64 CUDA tensor of shape (n, n, n), indexed [k, j, i] (x1 fastest).  All vector
     arguments are complex128 CUDA tensors of shape (R, n, n, n) or (n, n, n).  fronts: 1 for
-    the outer sweep from x3 = 0 (Algorithm 6), 2 for two fronts meeting in a middle slab.
+    the outer sweep from x3 = 0 (Algorithm 6), 2 for two fronts meeting in a middle slab;
+    fronts_inner: the same for the inner sweep over x2 (Algorithm 4).
     """
 
-    def __init__(self, c, omega, b, C, p, slab_layers=1, prec="c64", fronts=1):
+    def __init__(self, c, omega, b, C, p, slab_layers=1, prec="c64", fronts=1, fronts_inner=1):
         import torch
         if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64):
             raise TypeError("c must be a float64 CUDA tensor")
@@ -129,11 +132,11 @@ class Helm:
         if tuple(c.shape) != (n, n, n):
             raise ValueError("c must have shape (n, n, n)")
         self.n, self.omega, self.b, self.C, self.p, self.d = n, float(omega), b, float(C), p, slab_layers
-        self.fronts = fronts
+        self.fronts, self.fronts_inner = fronts, fronts_inner
         self.prec = HELM_C64 if prec in ("c64", HELM_C64) else HELM_C128
         h = ctypes.c_void_p()
         _check(lib().helm_setup(ctypes.byref(helm_grid(n)), _ptr(c), self.omega,
-                                ctypes.byref(helm_pml(b, self.C, p, fronts)), slab_layers, self.prec,
+                                ctypes.byref(helm_pml(b, self.C, p, fronts, fronts_inner)), slab_layers, self.prec,
                                 _stream(), ctypes.byref(h)), "helm_setup")
         self._h = h
 

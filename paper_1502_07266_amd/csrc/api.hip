@@ -1,6 +1,7 @@
 // C ABI of libhelm: argument validation, memory planning and ownership, error codes.
 // Every numerical step runs in the HIP kernels of this library; the host only plans,
 // allocates, launches and reads the scalars GMRES needs to decide.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,7 +13,7 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kBlockLimit = 64;          // largest block B of the two-chain sweep shapes
-constexpr int kBlockLimitOne = 128;      // ... of the one-chain shapes (two-front middle slab)
+constexpr int kBlockLimitOne = 128;      // ... of the one-chain shapes (lines on a middle group)
 constexpr size_t kSetupLds = 144 * 1024; // dynamic LDS of the setup (one B x B block at least)
 constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
 constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
@@ -30,16 +31,17 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   if (!(pml->C > 0.0) || !std::isfinite(pml->C)) return fail(HELM_EINVAL, "PML constant C must be finite and > 0");
   std::string msg;
   const int fronts = pml->fronts == 0 ? 1 : pml->fronts;
-  int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, plan, msg);
+  const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
+  int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
-  const int front_B = fronts == 2 ? plan.maxB_front : plan.maxB;
-  if (front_B > kBlockLimit)
+  if (plan.maxB_front > kBlockLimit)
     return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 64");
-  if (fronts == 2 && plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
-    return fail(HELM_EINVAL, "middle-slab block size (two fronts) exceeds 128 (complex64) or 96 (complex128)");
+  if (plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
+    return fail(HELM_EINVAL, "block size of a line on a middle group (two fronts) exceeds 128 "
+                             "(complex64) or 96 (complex128)");
   if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
     return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
-  for (int B : {front_B, fronts == 2 ? plan.maxB_mid : 0})
+  for (int B : {plan.maxB_front, plan.maxB_mid})
     if (B && LdsLayout(plan.n, B, (int)csize(prec)).bytes > kLdsBytes)
       return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
   return HELM_OK;
@@ -53,16 +55,18 @@ size_t planned_bytes(const Plan& p, int prec) {
 }
 
 // algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
-// inner pass it takes part in (twice unless l is the last x2-group) and once per outer pass
-// (twice unless g is the last x3-group with one front, or the middle one with two fronts);
-// each solve visits its n blocks twice (forward and backward substitution) and reads B*B
-// entries per visit; plus the input (complex128) read and the output written once.
+// inner pass it takes part in (twice unless l is the last x2-group with one inner front, or
+// the middle one with two) and once per outer pass (twice unless g is the last x3-group with
+// one front, or the middle one with two fronts); each solve visits its n blocks twice
+// (forward and backward substitution) and reads B*B entries per visit; plus the input
+// (complex128) read and the output written once.
 double sweep_bytes_per_rhs(const Plan& p, int prec) {
   double acc = 0.0;
   for (int g = 0; g < p.Gz; ++g)
     for (int l = 0; l < p.Gy; ++l) {
       const bool once = p.fronts == 2 ? g == p.zmid : g == p.Gz - 1;
-      const double mult = (once ? 1.0 : 2.0) * (l < p.Gy - 1 ? 2.0 : 1.0);
+      const bool ionce = p.fronts_inner == 2 ? l == p.ymid : l == p.Gy - 1;
+      const double mult = (once ? 1.0 : 2.0) * (ionce ? 1.0 : 2.0);
       const double B = p.line_B[(size_t)g * p.Gy + l];
       acc += mult * 2.0 * p.n * B * B;
     }
@@ -70,20 +74,42 @@ double sweep_bytes_per_rhs(const Plan& p, int prec) {
   return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
 }
 
-// the same for one launch of the dominant kernel: with two fronts, one of the two launches
-// that run both fronts over every x3-group but the middle one (each line once per inner pass)
+// the same for one launch of the dominant kernel (the two-chain launches of sweep_schedule),
+// averaged over its launches in one sweep: the factor bytes of the line solves of a launch,
+// plus 16 bytes per grid point of its slabs' rows for reading the input and 16 for writing
+// the output, each counted in the launch that does it (an inner-front forward launch reads
+// the input on its lines' rows, the backward one writes the output there; a launch that runs
+// whole inner sweeps does both on every row)
 double kernel_bytes_per_rhs(const Plan& p, int prec) {
-  if (p.fronts == 1) return sweep_bytes_per_rhs(p, prec);
-  double acc = 0.0;
-  for (int g = 0; g < p.Gz; ++g) {
-    if (g == p.zmid) continue;
-    for (int l = 0; l < p.Gy; ++l) {
-      const double B = p.line_B[(size_t)g * p.Gy + l];
-      acc += (l < p.Gy - 1 ? 2.0 : 1.0) * 2.0 * p.n * B * B;
+  double total = 0.0;
+  int launches = 0;
+  for (const SweepLaunch& L : sweep_schedule(p)) {
+    if (!L.timed) continue;
+    ++launches;
+    double fac = 0.0, pts = 0.0;
+    const int io = L.ipass == 0 ? 32 : 16;
+    for (int fr = 0; fr < L.nfront; ++fr) {
+      const int cnt = std::min(L.slab_hi, sweep_count(L.pass, p.Gz, p.zmid, fr));
+      for (int si = L.slab_lo; si < cnt; ++si) {
+        const int g = sweep_at(L.pass, p.Gz, p.zmid, fr, si).x;
+        const double nph = p.zg(g).last - p.zg(g).first + 1;
+        int rows = 0;
+        for (int inf = 0; inf < L.ninner; ++inf) {
+          const int lc = sweep_count(L.ipass, p.Gy, p.ymid, inf);
+          for (int k = 0; k < lc; ++k) {
+            const int l = sweep_at(L.ipass, p.Gy, p.ymid, inf, k).x;
+            const double B = p.line_B[(size_t)g * p.Gy + l];
+            fac += 2.0 * p.n * B * B;
+            if (L.ipass != 0) rows += p.yg(l).last - p.yg(l).first + 1;
+          }
+        }
+        if (L.ipass == 0) rows = p.n;
+        pts += (double)p.n * rows * nph;
+      }
     }
+    total += fac * csize(prec) + pts * io;
   }
-  const double N = (double)p.n * p.n * p.n;
-  return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
+  return launches ? total / launches : 0.0;
 }
 
 void release(helm_handle* h) {
@@ -333,7 +359,7 @@ int helm_set_launch(helm_handle* h, int lanes_per_row) {
 
 // ---- launch-shape autotuner -------------------------------------------------------------
 static std::string tune_key(const helm_handle* h) {
-  const int B = h->plan.fronts == 2 ? h->plan.maxB_front : h->plan.maxB;
+  const int B = h->plan.maxB_front;
   return "n=" + std::to_string(h->n) + ",maxB=" + std::to_string(B) +
          ",prec=" + (h->prec == HELM_C64 ? "c64" : "c128");
 }
@@ -369,10 +395,11 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
     }
   }
   hipStream_t s = S(stream);
-  // an interior line with the largest two-chain block: x3-group Gz/2 (the one below the middle
-  // with two fronts), x2-group Gy/2
+  // an interior line with the largest two-chain block: x3-group Gz/2 and x2-group Gy/2, or
+  // the groups just below the middle ones with two fronts
   const Plan& P = h->plan;
-  const int g = P.fronts == 2 ? P.zmid - 1 : P.Gz / 2, l = P.Gy / 2;
+  const int g = P.fronts == 2 ? P.zmid - 1 : P.Gz / 2;
+  const int l = P.fronts_inner == 2 ? P.ymid - 1 : P.Gy / 2;
   const int B = P.line_B[(size_t)g * P.Gy + l];
   const size_t elems = (size_t)h->n * B;
   double2 *r = nullptr, *x = nullptr;

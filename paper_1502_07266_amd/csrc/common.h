@@ -93,24 +93,66 @@ struct GroupInfo {
 struct Plan {
   int n = 0, b = 0, p = 0, d = 0;
   int fronts = 1;                     // outer sweep from one face (Algorithm 6) or from both
+  int fronts_inner = 1;               // the same for the inner sweep over x2 (Algorithm 4)
   int Gz = 0, Gy = 0;                 // x3-groups (outer sweep), x2-groups (inner sweep)
   int zmid = -1;                      // two fronts: the middle x3-group (eliminated last)
+  int ymid = -1;                      // two inner fronts: the middle x2-group
   std::vector<GroupInfo> groups;      // [Gz] x3-groups, then [Gy] x2-groups
   std::vector<long long> line_off;    // [Gz*Gy] offset (complex elements) of line (g, l) = g*Gy + l
   std::vector<int> line_B;            // [Gz*Gy]
   long long total_elems = 0;          // sum over lines of n * B^2
   int maxB = 0, maxW = 0;             // over all lines / windows
-  int maxB_front = 0, maxB_mid = 0;   // two fronts: lines off / on the middle x3-group
+  int maxB_front = 0, maxB_mid = 0;   // largest block of the two-chain / one-chain lines
   const GroupInfo& zg(int g) const { return groups[g]; }
   const GroupInfo& yg(int l) const { return groups[Gz + l]; }
-  // middle block of line (g, l)'s elimination order: both ends towards n/2, except the lines
-  // of the two-front middle slab, eliminated in x1 order (their blocks are too large for two
-  // chains per workgroup; see the sweep)
-  int line_mid(int g) const { return (fronts == 2 && g == zmid) ? n - 1 : n / 2; }
+  // lines on a middle group (x3 with two fronts, x2 with two inner fronts) have moving PML on
+  // both sides of that group and blocks too large for two chains per workgroup: they are
+  // eliminated in x1 order and solved by one chain spanning the workgroup (see the sweep)
+  bool one_chain(int g, int l) const {
+    return (fronts == 2 && g == zmid) || (fronts_inner == 2 && l == ymid);
+  }
+  // middle block of line (g, l)'s elimination order: both ends towards n/2, or n - 1 (x1 order)
+  int line_mid(int g, int l) const { return one_chain(g, l) ? n - 1 : n / 2; }
 };
 
 // builds the plan; returns HELM_OK or HELM_EINVAL (with a message)
-int build_plan(int n, int b, int p, int d, int fronts, Plan& plan, std::string& msg);
+int build_plan(int n, int b, int p, int d, int fronts, int fronts_inner, Plan& plan,
+               std::string& msg);
+
+// what a workgroup does with one group (an x3-group of the outer sweep or an x2-group of the
+// inner sweep): forward from below / from above / the middle group with both couplings;
+// backward with the coupling from above / from below
+enum SweepKind { kFwdLow = 0, kFwdHigh = 1, kFwdMid = 2, kBwdLow = 3, kBwdHigh = 4 };
+
+// The groups a front visits in one pass over an axis of G groups (middle group mid):
+//   pass 0 (one front): 0..G-1 forward from below, then G-2..0 backward
+//   pass 1 (two fronts forward): front 0 takes 0..mid-1 from below, front 1 G-1..mid+1 from above
+//   pass 2: the middle group with both couplings
+//   pass 3 (two fronts backward): front 0 mid-1..0, front 1 mid+1..G-1
+__host__ __device__ inline int sweep_count(int pass, int G, int mid, int front) {
+  switch (pass) {
+    case 0: return 2 * G - 1;
+    case 2: return 1;
+    default: return front == 0 ? mid : G - 1 - mid;
+  }
+}
+__host__ __device__ inline int2 sweep_at(int pass, int G, int mid, int front, int s) {
+  switch (pass) {
+    case 0: return s < G ? make_int2(s, kFwdLow) : make_int2(2 * G - 2 - s, kBwdLow);
+    case 1: return front == 0 ? make_int2(s, kFwdLow) : make_int2(G - 1 - s, kFwdHigh);
+    case 2: return make_int2(mid, kFwdMid);
+    default: return front == 0 ? make_int2(mid - 1 - s, kBwdLow) : make_int2(mid + 1 + s, kBwdHigh);
+  }
+}
+
+// one launch of the sweep: outer pass and its fronts, the range of the pass's slab steps,
+// inner pass and its fronts, line chains per workgroup, largest block, and whether it is a
+// launch of the dominant (two-chain) kernel
+struct SweepLaunch {
+  int pass, nfront, slab_lo, slab_hi, ipass, ninner, chains, maxB;
+  bool timed;
+};
+std::vector<SweepLaunch> sweep_schedule(const Plan& P);
 
 // ---------------------------------------------------------------------------------------
 // device-time accounting: event pairs recorded around launches, resolved lazily
@@ -142,6 +184,7 @@ struct LaunchTimer {
       return;
     }
     pending.push_back({a, b, nrhs});
+    if (pending.size() >= 2048) flush();   // bounds the events alive between reads
   }
   void flush() {
     for (auto& p : pending) {

@@ -28,7 +28,7 @@ constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may tak
 
 struct SetupArgs {
   int n, Gz, Gy, p;
-  int fronts, zmid;
+  int fronts, zmid, fronts_inner, ymid;
   int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
   double h;
   const GroupInfo* groups;
@@ -79,11 +79,12 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
 
   // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
   // middle block m last, whose Schur complement takes the update from both sides; m = n/2
-  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines of a two-front
-  // middle slab.  It is the block LDU of Sec. 3 with the blocks in that order (every block
+  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines on a middle group
+  // (x3 with two fronts, x2 with two inner fronts).  It is the block LDU of Sec. 3 with the blocks in that order (every block
   // eliminated is an end of the remaining chain, so there is no fill); the sweep runs the two
   // halves of each line solve as two concurrent chains.
-  const int mid = (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2;
+  const bool one_chain = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
+  const int mid = one_chain ? n - 1 : n / 2;
   // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
   C* Tlds = S + B * B;
   const C* Tprev = Tlds;
@@ -218,6 +219,8 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   a.p = P.p;
   a.fronts = P.fronts;
   a.zmid = P.zmid;
+  a.fronts_inner = P.fronts_inner;
+  a.ymid = P.ymid;
   a.h = h->h;
   a.groups = h->d_groups;
   a.line_off = h->d_line_off;

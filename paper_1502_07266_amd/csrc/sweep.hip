@@ -38,21 +38,21 @@
 // launch no workgroup waits for another.  The middle slab's line problems have moving PML on
 // both sides in x3 and larger blocks; their factors are in x1 order and each is solved by one
 // chain spanning the whole workgroup.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
 
 
-// what a workgroup does with one x3-group: forward from below / from above / the middle
-// slab with both couplings; backward with the coupling from above / from below
-enum SlabKind { kFwdLow = 0, kFwdHigh = 1, kFwdMid = 2, kBwdLow = 3, kBwdHigh = 4 };
-
 struct SweepArgs {
   int n, Gz, Gy, maxW, maxB;
-  int fronts, zmid;
-  int pass;              // 0: one front, whole sweep; 1: two fronts forward; 2: middle slab;
-                         // 3: two fronts backward
-  int nfront;            // workgroups per right-hand side in this launch (1 or 2)
+  int fronts, zmid, fronts_inner, ymid;
+  int pass;              // outer pass over the x3-groups (sweep_count / sweep_at)
+  int nfront;            // outer fronts in this launch: workgroups per right-hand side (1, 2)
+  int slab_lo, slab_hi;  // the range of the pass's slabs this launch handles
+  int ipass;             // inner pass over the x2-groups of each slab
+  int ninner;            // inner fronts in this launch (workgroups per outer front: 1, 2)
   int tpc;               // threads per line chain (two chains, or one spanning the workgroup)
   long long N, in_stride, out_stride;
   const GroupInfo* groups;
@@ -338,23 +338,6 @@ struct LineSolver {
 // threads of a launch: CH chains (2, or 1 spanning the workgroup) of round-up-to-64(B * NC)
 template <int NC, int CW, int CH> constexpr int max_threads() { return CH * ((NC * NC * CW + 63) / 64 * 64); }
 
-// the x3-groups a workgroup handles in this launch, in order: count, and the s-th (group, kind)
-__device__ __forceinline__ int slab_count(const SweepArgs& a, int front) {
-  switch (a.pass) {
-    case 0: return 2 * a.Gz - 1;
-    case 2: return 1;
-    default: return front == 0 ? a.zmid : a.Gz - 1 - a.zmid;
-  }
-}
-__device__ __forceinline__ int2 slab_at(const SweepArgs& a, int front, int s) {
-  switch (a.pass) {
-    case 0: return s < a.Gz ? make_int2(s, kFwdLow) : make_int2(2 * a.Gz - 2 - s, kBwdLow);
-    case 1: return front == 0 ? make_int2(s, kFwdLow) : make_int2(a.Gz - 1 - s, kFwdHigh);
-    case 2: return make_int2(a.zmid, kFwdMid);
-    default: return front == 0 ? make_int2(a.zmid - 1 - s, kBwdLow) : make_int2(a.zmid + 1 + s, kBwdHigh);
-  }
-}
-
 template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ, int CH>
 __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs a) {
   using C = typename cx<R>::type;
@@ -369,11 +352,14 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
   C* ctab = sb + L.ctab;
   int4* tab = reinterpret_cast<int4*>(smem_raw + L.tab_byte);
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int slot = (int)blockIdx.x / a.nfront, front = (int)blockIdx.x - slot * a.nfront;
+  // workgroup = (right-hand side, outer front, inner front); the inner fronts of one outer
+  // front share its slab iterate and write disjoint rows of it
+  const int fw = (int)blockIdx.x / a.ninner, ifront = (int)blockIdx.x - fw * a.ninner;
+  const int slot = fw / a.nfront, front = fw - slot * a.nfront;
   const int q = a.rhs_idx ? a.rhs_idx[slot] : slot;
   const TI* __restrict__ f = reinterpret_cast<const TI*>(a.in) + (long long)q * a.in_stride;
   TO* u = reinterpret_cast<TO*>(a.out) + (long long)q * a.out_stride;
-  C* v = reinterpret_cast<C*>(a.scratch) + (long long)blockIdx.x * n * n * a.maxW;
+  C* v = reinterpret_cast<C*>(a.scratch) + (long long)fw * n * n * a.maxW;
   const C zero = mk((R)0, (R)0);
   for (int m = tid; m < n + 2; m += NT) {
     cf[m] = cvt<C>(a.coef[(ADJ ? 2 : 0) * (n + 2) + m]);
@@ -386,10 +372,11 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
   };
   LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
 
-  const int nslab = slab_count(a, front);
-  for (int si = 0; si < nslab; ++si) {
+  const int nslab = min(a.slab_hi, sweep_count(a.pass, Gz, a.zmid, front));
+  const int nline = sweep_count(a.ipass, Gy, a.ymid, ifront);
+  for (int si = a.slab_lo; si < nslab; ++si) {
     {
-      const int2 gk = slab_at(a, front, si);
+      const int2 gk = sweep_at(a.pass, Gz, a.zmid, front, si);
       const int g = gk.x, kind = gk.y;
       const bool ofwd = kind <= kFwdMid;
       // couplings of the slab input: from the layer below (k0 - 1) and/or above (k1 + 1)
@@ -397,14 +384,23 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
       const bool from_above = (kind == kFwdHigh && g < Gz - 1) || kind == kFwdMid || kind == kBwdLow;
       const GroupInfo gz = a.groups[g];
       const int Wz = gz.W, k0 = gz.first, k1 = gz.last, zw0 = gz.w0;
-      const int line_mid = (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2;
-      for (int lp = 0; lp < 2 * Gy - 1; ++lp) {
-        const bool ifwd = lp < Gy;
-        const int l = ifwd ? lp : 2 * Gy - 2 - lp;
+      for (int lp = 0; lp < nline; ++lp) {
+        const int2 lk = sweep_at(a.ipass, Gy, a.ymid, ifront, lp);
+        const int l = lk.x, lkind = lk.y;
+        const bool ifwd = lkind <= kFwdMid;
+        // couplings of the line input: forward, the new iterate on the row below (j0 - 1)
+        // and/or above (j1 + 1) is subtracted; backward, the input is the coupling to the row
+        // above (lower front) or below (upper front)
+        const bool in_below = (lkind == kFwdLow && l > 0) || lkind == kFwdMid;
+        const bool in_above = (lkind == kFwdHigh && l < Gy - 1) || lkind == kFwdMid;
         const GroupInfo gy = a.groups[Gz + l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
         const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
-        ls.begin_line(T, B, n, line_mid);
+        const bool one = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
+        // the host launches lines on a middle group with one chain and all others with two;
+        // a mismatch would overrun the step table, so such a line is left alone
+        if (one != (CH == 1)) continue;
+        ls.begin_line(T, B, n, one ? n - 1 : n / 2);
         ls.fill();   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
@@ -412,7 +408,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
           const int j = yw0 + jj, k = zw0 + kk;
           C val = zero;
           if (ifwd) {
-            if (j >= j0) {
+            if (j >= j0 && j <= j1) {
               if (ofwd) {
                 if (k >= k0 && k <= k1) {
                   val = cvt<C>(f[gidx(i, j, k)]);
@@ -424,10 +420,13 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
               } else if (from_below && k == k0) {
                 val = cmul(cf[k0], cvt<C>(u[gidx(i, j, k0 - 1)]));
               }
-              if (l > 0 && j == j0) val = csub(val, cmul(cf[j0], v[((long long)kk * n + (j0 - 2)) * n + i]));
+              if (in_below && j == j0) val = csub(val, cmul(cf[j0], v[((long long)kk * n + (j0 - 2)) * n + i]));
+              if (in_above && j == j1) val = csub(val, cmul(cb[j1], v[((long long)kk * n + j1) * n + i]));
             }
-          } else if (j == j1) {
+          } else if (lkind == kBwdLow && j == j1) {
             val = cmul(cb[j1], v[((long long)kk * n + j1) * n + i]);
+          } else if (lkind == kBwdHigh && j == j0) {
+            val = cmul(cf[j0], v[((long long)kk * n + (j0 - 2)) * n + i]);
           }
           ybuf[i * B + qq] = val;
         }
@@ -437,16 +436,28 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
         const int npy = j1 - j0 + 1;
         for (int e = tid; e < n * Wz * npy; e += NT) {
           const int i = e % n, kk = (e / n) % Wz, jp = e / (n * Wz);
-          const int qq = (Wy - npy + jp) * Wz + kk;
+          const int qq = (j0 - yw0 + jp) * Wz + kk;
           C* p = v + ((long long)kk * n + (j0 + jp - 1)) * n + i;
           *p = ifwd ? ybuf[i * B + qq] : csub(*p, ybuf[i * B + qq]);
         }
         __syncthreads();
       }
-      // ---- slab output on the group's layers ----
-      const int nph = k1 - k0 + 1;
-      for (int e = tid; e < n * n * nph; e += NT) {
-        const int i = e % n, jm = (e / n) % n, kp = e / (n * n);
+      // ---- slab output on the group's layers, on the rows final after this inner pass: all
+      // of them (one inner front), the middle x2-group's (middle line), the rows of the lines
+      // this workgroup swept backwards (two inner fronts) ----
+      int r0 = 1, r1 = n;
+      if (a.ipass == 1) {
+        r1 = 0;
+      } else if (a.ipass == 2) {
+        r0 = a.groups[Gz + a.ymid].first;
+        r1 = a.groups[Gz + a.ymid].last;
+      } else if (a.ipass == 3) {
+        if (ifront == 0) r1 = a.groups[Gz + a.ymid - 1].last;
+        else r0 = a.groups[Gz + a.ymid + 1].first;
+      }
+      const int nph = k1 - k0 + 1, nr = r1 - r0 + 1;
+      for (int e = tid; e < n * nr * nph; e += NT) {
+        const int i = e % n, jm = r0 - 1 + (e / n) % nr, kp = e / (n * nr);
         const int kk = k0 - zw0 + kp;
         const C val = v[((long long)kk * n + jm) * n + i];
         const long long id = gidx(i, jm + 1, k0 + kp);
@@ -482,7 +493,9 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_line_solve(Swee
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
   LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
-  ls.begin_line(T, B, n, (a.fronts == 2 && g == a.zmid) ? n - 1 : n / 2);
+  const bool one = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
+  if (one != (CH == 1)) return;   // the host picks the chain count from the line
+  ls.begin_line(T, B, n, one ? n - 1 : n / 2);
   ls.fill();
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
@@ -621,8 +634,14 @@ SweepArgs base_args(helm_handle* h) {
   a.maxB = P.maxB;
   a.fronts = P.fronts;
   a.zmid = P.zmid;
+  a.fronts_inner = P.fronts_inner;
+  a.ymid = P.ymid;
   a.pass = 0;
   a.nfront = 1;
+  a.slab_lo = 0;
+  a.slab_hi = 1 << 30;
+  a.ipass = 0;
+  a.ninner = 1;
   a.tpc = 0;
   a.N = (long long)h->n * h->n * h->n;
   a.in_stride = a.out_stride = a.N;
@@ -637,41 +656,97 @@ SweepArgs base_args(helm_handle* h) {
   return a;
 }
 
-// one launch of the sweep: pass (see SweepArgs), blocks up to maxB, two chains (shape from
-// the lanes override) or one chain spanning the workgroup
+// one launch of the sweep (fields of SweepArgs: pass, nfront, slab range, ipass, ninner), blocks
+// up to maxB, two chains (shape from the lanes override) or one chain spanning the workgroup
 template <typename R, typename TI, typename TO>
-hipError_t sweep_pass(helm_handle* h, SweepArgs a, int pass, int nfront, int maxB, int chains,
-                      int R_, bool adjoint, hipStream_t s) {
-  a.pass = pass;
-  a.nfront = nfront;
-  a.maxB = maxB;
-  const Shape sh = chains == 2 ? choose_shape(maxB, h->lanes_override) : choose_shape_one(maxB);
-  if (sh.cw < 0 || !lds_fits(h->n, maxB, sh, chains)) return hipErrorInvalidValue;
-  a.tpc = chain_threads(maxB, sh.nc);
-  const size_t sm = LdsLayout(h->n, maxB, (int)sizeof(typename cx<R>::type)).bytes;
-  return adjoint ? dispatch_sweep<R, TI, TO, true>(sh, chains, R_ * nfront, sm, s, a)
-                 : dispatch_sweep<R, TI, TO, false>(sh, chains, R_ * nfront, sm, s, a);
+hipError_t sweep_launch(helm_handle* h, SweepArgs a, const SweepLaunch& L, int R_, bool adjoint,
+                        hipStream_t s) {
+  a.pass = L.pass;
+  a.nfront = L.nfront;
+  a.slab_lo = L.slab_lo;
+  a.slab_hi = L.slab_hi;
+  a.ipass = L.ipass;
+  a.ninner = L.ninner;
+  a.maxB = L.maxB;
+  const Shape sh = L.chains == 2 ? choose_shape(L.maxB, h->lanes_override) : choose_shape_one(L.maxB);
+  if (sh.cw < 0 || !lds_fits(h->n, L.maxB, sh, L.chains)) return hipErrorInvalidValue;
+  a.tpc = chain_threads(L.maxB, sh.nc);
+  const size_t sm = LdsLayout(h->n, L.maxB, (int)sizeof(typename cx<R>::type)).bytes;
+  const int grid = R_ * L.nfront * L.ninner;
+  return adjoint ? dispatch_sweep<R, TI, TO, true>(sh, L.chains, grid, sm, s, a)
+                 : dispatch_sweep<R, TI, TO, false>(sh, L.chains, grid, sm, s, a);
 }
 
-// the whole sweep; launches of the dominant kernel (all of it with one front, the two front
-// passes with two) are timed on their own as well
+// the whole sweep; launches of the dominant kernel (the two-chain launches) are timed on
+// their own as well
 template <typename R, typename TI, typename TO>
 hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStream_t s) {
-  const Plan& P = h->plan;
-  auto timed = [&](int pass, int nfront, int maxB, int chains) {
-    hipEvent_t ev = h->t_kernel.begin(s);
-    hipError_t e = sweep_pass<R, TI, TO>(h, a, pass, nfront, maxB, chains, R_, adjoint, s);
-    h->t_kernel.end(ev, s, R_);
-    return e;
-  };
-  if (P.fronts == 1) return timed(0, 1, P.maxB, 2);
-  hipError_t e = timed(1, 2, P.maxB_front, 2);
-  if (e == hipSuccess) e = sweep_pass<R, TI, TO>(h, a, 2, 1, P.maxB_mid, 1, R_, adjoint, s);
-  if (e == hipSuccess) e = timed(3, 2, P.maxB_front, 2);
+  hipError_t e = hipSuccess;
+  for (const SweepLaunch& L : sweep_schedule(h->plan)) {
+    if (L.timed) {
+      hipEvent_t ev = h->t_kernel.begin(s);
+      e = sweep_launch<R, TI, TO>(h, a, L, R_, adjoint, s);
+      h->t_kernel.end(ev, s, R_);
+    } else {
+      e = sweep_launch<R, TI, TO>(h, a, L, R_, adjoint, s);
+    }
+    if (e != hipSuccess) return e;
+  }
   return e;
 }
 
 }  // namespace
+
+// The launches of one sweep, in order.
+//   One inner front: one launch per outer pass, every workgroup sweeping its slabs and, in
+//   each, all lines (pass 0 with one front; passes 1, 2, 3 with two, the middle slab with one
+//   chain).
+//   Two inner fronts: per slab step of each outer pass, three launches: both inner fronts
+//   forward (two workgroups per outer front), the middle line (one chain), both inner fronts
+//   backward; the launch boundaries order them.  On the two-front middle slab every line has
+//   one chain.
+// Each launch's block bound is the largest block among the lines it solves.
+std::vector<SweepLaunch> sweep_schedule(const Plan& P) {
+  std::vector<SweepLaunch> out;
+  struct Outer {
+    int pass, nfront;
+  };
+  std::vector<Outer> outer;
+  if (P.fronts == 1) outer.push_back({0, 1});
+  else outer = {{1, 2}, {2, 1}, {3, 2}};
+  auto line_B = [&](int g, int l) { return P.line_B[(size_t)g * P.Gy + l]; };
+  for (const Outer& o : outer) {
+    const bool mid_slab = o.pass == 2;
+    if (P.fronts_inner == 1) {
+      SweepLaunch L{o.pass, o.nfront, 0, 1 << 30, 0, 1, mid_slab ? 1 : 2, 0, !mid_slab};
+      int mb = 0;
+      for (int g = 0; g < P.Gz; ++g)
+        if ((P.fronts == 2 && g == P.zmid) == mid_slab)
+          for (int l = 0; l < P.Gy; ++l) mb = std::max(mb, line_B(g, l));
+      L.maxB = mb;
+      out.push_back(L);
+      continue;
+    }
+    int steps = 0;
+    for (int fr = 0; fr < o.nfront; ++fr) steps = std::max(steps, sweep_count(o.pass, P.Gz, P.zmid, fr));
+    for (int si = 0; si < steps; ++si) {
+      for (int ip : {1, 2, 3}) {
+        const int ninner = ip == 2 ? 1 : 2;
+        int mb = 0;
+        for (int fr = 0; fr < o.nfront; ++fr) {
+          if (si >= sweep_count(o.pass, P.Gz, P.zmid, fr)) continue;
+          const int g = sweep_at(o.pass, P.Gz, P.zmid, fr, si).x;
+          for (int inf = 0; inf < ninner; ++inf)
+            for (int k = 0; k < sweep_count(ip, P.Gy, P.ymid, inf); ++k)
+              mb = std::max(mb, line_B(g, sweep_at(ip, P.Gy, P.ymid, inf, k).x));
+        }
+        const int chains = (mid_slab || ip == 2) ? 1 : 2;
+        out.push_back(SweepLaunch{o.pass, o.nfront, si, si + 1, ip, ninner, chains, mb, chains == 2});
+      }
+    }
+  }
+  return out;
+}
 
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
@@ -722,9 +797,9 @@ hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, d
   SweepArgs a = base_args(h);
   a.in = r;
   a.out = x;
-  // lines of the two-front middle slab: one chain over the workgroup, x1-order factors
-  const bool one = P.fronts == 2 && zg == P.zmid;
-  const int mb = one ? P.maxB_mid : (P.fronts == 2 ? P.maxB_front : P.maxB);
+  // lines on a middle group: one chain over the workgroup, x1-order factors
+  const bool one = P.one_chain(zg, yg);
+  const int mb = one ? P.maxB_mid : P.maxB_front;
   a.maxB = mb;
   const size_t sm = LdsLayout(h->n, mb, (int)csz).bytes;
   const Shape sh = one ? choose_shape_one(mb) : choose_shape(mb, h->lanes_override);

@@ -90,6 +90,32 @@ def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
     assert err <= tol
 
 
+@pytest.fixture(scope="module")
+def c1_two_inner_front_oracle():
+    wl, _ = workload("c1")
+    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                     fronts=1, fronts_inner=2)
+    return wl, O.RecursiveSweep(prob)
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+def test_c1_two_inner_front_apply_matches_oracle(c1_two_inner_front_oracle, prec, tol):
+    """Two inner fronts at 31^3 (one outer front): three launches per slab; the middle
+    x2-line of every slab has blocks of 13 x 7 = 91 unknowns, solved by one chain."""
+    wl, M = c1_two_inner_front_oracle
+    n = wl["n"]
+    x = inputs.random_rhs(n, 2, seed=24)
+    from paper_1502_07266_amd.binding import Helm
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec,
+             fronts=1, fronts_inner=2)
+    z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    H.close()
+    ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
+    err = rel(z, ref)
+    print(f"c1 two-inner-front apply {prec}: rel err {err:.2e}")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_c1_solve_matches_direct_solve(c1_oracle, prec):
     wl, prob, M = c1_oracle
@@ -150,3 +176,39 @@ def test_c3_sweep_dot_test_and_linearity(c3_handles):
     prec_err = float((Mx64 - Mx).norm() / Mx.norm())
     print(f"c3 complex64 vs complex128 sweep: {prec_err:.2e}")
     assert prec_err <= 1e-3
+
+
+def test_c3_two_fronts_both_axes():
+    """127^3, complex64, two fronts in x3 and in x2 (the launch configuration the benchmark
+    times): sampled line factors, including lines on the middle x2-group (blocks 11 x 6 = 66)
+    and the middle-middle line (11 x 11 = 121), against the oracle's; the adjoint dot test
+    and linearity of the whole sweep."""
+    from paper_1502_07266_amd.binding import Helm
+    wl, _ = workload("c3")
+    n = wl["n"]
+    prob = O.Problem(n=n, c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                     fronts=2, fronts_inner=2)
+    Gt = O.groups_two_fronts(n, wl["b"], wl["d"])
+    mid = len(Gt) // 2
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64",
+             fronts=2, fronts_inner=2)
+    for (g, l) in [(0, 0), (mid - 1, mid), (mid, mid), (mid + 3, mid - 1), (len(Gt) - 1, mid + 1)]:
+        one = g == mid or l == mid
+        ln = O.LineFactors(prob, Gt, g, Gt, l, order="up" if one else "two-sided")
+        ref = np.stack(ln.block_T)
+        T = H.line_factors(g, l).cpu().numpy()
+        err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
+        print(f"c3 2f2i line ({g}, {l}) B={ln.B}: worst block rel err {err:.2e}")
+        assert err <= 1e-3
+    x = torch.from_numpy(inputs.random_rhs(n, 1, seed=33)).cuda()
+    y = torch.from_numpy(inputs.random_rhs(n, 1, seed=34)).cuda()
+    Mx, My = H.apply(x), H.apply(y)
+    MHy = H.apply(y, adjoint=True)
+    lhs, rhs_ = cdot(Mx, y), cdot(x, MHy)
+    dot_err = abs(lhs - rhs_) / abs(lhs)
+    comb = H.apply(2 * x + 3j * y)
+    lin_err = float((comb - (2 * Mx + 3j * My)).norm() / comb.norm())
+    H.close()
+    print(f"c3 2f2i complex64 sweep: dot test {dot_err:.2e}, linearity {lin_err:.2e}")
+    assert dot_err <= 1e-4
+    assert lin_err <= 1e-4

@@ -31,6 +31,14 @@ CASES = {
     "ragged_2f": dict(n=16, b=3, p=2, d=2, fronts=2),
     "tiny3_2f": dict(n=3, b=1, p=1, d=1, fronts=2),
     "tiny4_2f": dict(n=4, b=1, p=1, d=1, fronts=2),
+    # two fronts in x2 as well: per slab, the inner fronts run in separate workgroups and
+    # launches and the middle x2-line (moving PML on both sides in x2) in x1 order with one
+    # chain; with two outer fronts the middle-middle line has moving PML on all four sides
+    "b4p4_2f2i": dict(n=15, b=4, p=4, d=1, fronts=2, fronts_inner=2),
+    "b4p4_1f2i": dict(n=15, b=4, p=4, d=1, fronts=1, fronts_inner=2),
+    "ragged_2f2i": dict(n=17, b=3, p=2, d=2, fronts=2, fronts_inner=2),
+    "tiny3_2f2i": dict(n=3, b=1, p=1, d=1, fronts=2, fronts_inner=2),
+    "tiny4_1f2i": dict(n=4, b=1, p=1, d=1, fronts=1, fronts_inner=2),
 }
 _cache = {}
 
@@ -40,7 +48,7 @@ def case(name):
         cfg = CASES[name]
         sc = inputs.small_case(n=cfg["n"], b=cfg["b"], p=cfg["p"], d=cfg["d"])
         prob = O.Problem(n=cfg["n"], c=sc["c"], omega=sc["omega"], b=cfg["b"], C=sc["C"], p=cfg["p"], d=cfg["d"],
-                         fronts=cfg.get("fronts", 1))
+                         fronts=cfg.get("fronts", 1), fronts_inner=cfg.get("fronts_inner", 1))
         _cache[name] = (sc, prob, O.RecursiveSweep(prob))
     return _cache[name]
 
@@ -49,7 +57,14 @@ def helm(name, prec):
     from paper_1502_07266_amd.binding import Helm
     sc, prob, _ = case(name)
     c = torch.from_numpy(sc["c"]).cuda()
-    return Helm(c, sc["omega"], prob.b, prob.C, prob.p, prob.d, prec=prec, fronts=prob.fronts)
+    return Helm(c, sc["omega"], prob.b, prob.C, prob.p, prob.d, prec=prec, fronts=prob.fronts,
+                fronts_inner=prob.fronts_inner)
+
+
+def on_middle_group(prob, M, g, l):
+    """Lines on a middle group are factored in x1 order, all others from both ends."""
+    return ((prob.fronts == 2 and g == len(M.Gz) // 2)
+            or (prob.fronts_inner == 2 and l == len(M.Gy) // 2))
 
 
 def rel(a, b):
@@ -87,10 +102,10 @@ def test_line_factors(name, prec, tol):
     worst = 0.0
     for g, l, ln in M.lines():
         T = H.line_factors(g, l).cpu().numpy()
-        # the library eliminates the x1-blocks from both ends towards the middle, except on the
-        # two-front middle slab (x1 order)
-        mid_slab = prob.fronts == 2 and g == len(M.Gz) // 2
-        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order="up" if mid_slab else "two-sided")
+        # the library eliminates the x1-blocks from both ends towards the middle, except on a
+        # middle group (x1 order)
+        order = "up" if on_middle_group(prob, M, g, l) else "two-sided"
+        ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order=order)
         ref = np.stack(ln.block_T)
         assert T.shape == ref.shape
         e = max(rel(T[i], ref[i]) for i in range(prob.n))
@@ -106,7 +121,8 @@ def test_line_solve(name, adjoint):
     H = helm(name, "c128")
     rng = np.random.default_rng(3)
     Gz, Gy = len(M.Gz), len(M.Gy)
-    picks = [(0, 0), (1, 0), (0, 2), (3, 5), (Gz - 1, Gy - 1), (Gz // 2, 0), (Gz // 2, Gy - 1)]
+    picks = [(0, 0), (1, 0), (0, 2), (3, 5), (Gz - 1, Gy - 1), (Gz // 2, 0), (Gz // 2, Gy - 1),
+             (0, Gy // 2), (Gz // 2, Gy // 2), (Gz - 1, Gy // 2)]
     for (g, l) in [(g, l) for (g, l) in picks if g < Gz and l < Gy]:
         ln = M.slabs[g].lines[l]
         Nl = ln.K.shape[0]
@@ -132,7 +148,7 @@ def test_apply(name, prec, tol, adjoint):
     assert max(errs) <= tol
 
 
-@pytest.mark.parametrize("name", ["b4p4", "b4p4_2f"])
+@pytest.mark.parametrize("name", ["b4p4", "b4p4_2f", "b4p4_2f2i"])
 @pytest.mark.parametrize("lanes", [4, 8, 16])
 def test_apply_launch_shape_invariant(lanes, name):
     sc, prob, M = case(name)
