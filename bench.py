@@ -4,16 +4,19 @@
 A step is the whole hot path on one batch: setup (all line factorisations) and the batched
 flexible-GMRES solve of every right-hand side to the workload's tolerance, with the sweep
 applied in complex64 and GMRES, matvec and residuals in FP64.  The outer sweep runs with two
-fronts (from both x3-faces, as in the paper's experiments) unless --fronts 1.  Inputs are resident on the GPU
-before the timed region.  Default workload: 127^3 interior points, 5-cell PML (C = 30 b),
+fronts (from both x3-faces, as in the paper's experiments) unless --fronts 1, and so does the
+inner sweep over x2 unless --fronts-inner 1.  Inputs are resident on the GPU before the timed
+region.  Default workload: 127^3 interior points, 5-cell PML (C = 30 b),
 moving PML 5 cells, one layer per auxiliary problem, a Gaussian random field in [1, 2]
 (correlation length 0.1), omega = 2 pi 16, 32 point sources at seeded interior nodes,
 GMRES(50) to relative residual 1e-6.
 
 Printed: one JSON line.  `value` is seconds per step (lower is better).  `roofline` is the
-sweep kernel (the dominant kernel): algorithmic bytes per launch divided by its average
-launch duration, both taken from HIP events recorded on the launch stream inside the timed
-steps.  The FP64 path (complex128 sweep) is run once after the timed steps and reported beside.
+sweep kernel (the dominant kernel: its two-chain launches): algorithmic bytes per launch
+divided by its average launch duration, both taken from HIP events recorded on the launch
+stream inside the timed steps.  The FP64 path (complex128 sweep) is run once after the timed
+steps and reported beside, with the same fronts where complex128 allows them (the line
+vector of a block larger than 96 does not fit in LDS in complex128: then one inner front).
 `cpu_baseline` is the oracle timed on a bounded sample of the same workload and scaled to
 one step.
 """
@@ -35,29 +38,60 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_step(Helm, c, wl, F, prec, fronts):
+def run_step(Helm, c, wl, F, prec, fronts, fronts_inner):
     import torch
-    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts)
+    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts,
+             fronts_inner=fronts_inner)
     u, its, rel, rc = H.solve(F, tol=wl["tol"], restart=wl["restart"], maxit=wl.get("maxit", 400))
     torch.cuda.synchronize()
     st = H.stats()
     return H, u, its, rel, rc, st
 
 
-def measured_traffic(workload, fronts):
+def group_count(n, b, d, fronts):
+    """x-groups of an axis swept from one face (1 + ceil((n - b) / d)) or from both
+    (2 + ceil((n - 2b) / d)); with two fronts the middle group is G // 2."""
+    return 1 + -(-(n - b) // d) if fronts == 1 else 2 + -(-(n - 2 * b) // d)
+
+
+def dependent_steps(n, b, d, fronts, fronts_inner):
+    """Dependent block steps of one sweep (the longest chain through its launches) and of one
+    launch of the dominant kernel.  A two-sided line solve takes 2 (n/2) + 1 steps, a
+    one-chain solve (lines on a middle group) 2n - 1."""
+    S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
+    Gz, Gy = group_count(n, b, d, fronts), group_count(n, b, d, fronts_inner)
+    Fz = max(Gz // 2, Gz - 1 - Gz // 2) if fronts == 2 else 0
+    Fy = max(Gy // 2, Gy - 1 - Gy // 2) if fronts_inner == 2 else 0
+    slab = (lambda S: (2 * Gy - 1) * S) if fronts_inner == 1 else (lambda S: 2 * Fy * S + S1)
+    sweep = (2 * Gz - 1) * slab(S2) if fronts == 1 else 2 * Fz * slab(S2) + slab(S1)
+    if fronts_inner == 2:
+        kernel = Fy * S2                       # one inner front's lines of one slab step
+    elif fronts == 1:
+        kernel = sweep                         # the whole sweep in one launch
+    else:
+        kernel = Fz * (2 * Gy - 1) * S2        # one outer front's slabs
+    return sweep, kernel
+
+
+def traffic_profile_name(fronts, fronts_inner):
+    return {(1, 1): "k_sweep", (2, 1): "k_sweep_front", (1, 2): "k_sweep_inner_fronts",
+            (2, 2): "k_sweep_fronts_both_axes"}[(fronts, fronts_inner)]
+
+
+def measured_traffic(workload, fronts, fronts_inner):
     """HBM bytes per sweep launch from the committed counter run (FETCH_SIZE and WRITE_SIZE of
     one 32-right-hand-side launch, each scaled by what the counter reads for a plain copy of
     known size), or None when that run does not cover this workload or the sweep source has
     changed since the counters were taken."""
     import hashlib
-    name = "k_sweep_front" if fronts == 2 else "k_sweep"
+    name = traffic_profile_name(fronts, fronts_inner)
     path = os.path.join(ROOT, "profiles", f"{name}_c64_127cubed_32rhs_traffic.json")
     src = os.path.join(ROOT, "paper_1502_07266_amd", "csrc", "sweep.hip")
     if workload != "c3" or not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("fronts", 1) != fronts:
+    if rec.get("fronts", 1) != fronts or rec.get("fronts_inner", 1) != fronts_inner:
         return None
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != rec.get("sweep_source_sha256"):
@@ -66,12 +100,13 @@ def measured_traffic(workload, fronts):
     return rec
 
 
-def cpu_baseline(wl, iters, budget_s):
+def cpu_baseline(wl, iters, budget_s, fronts=1, fronts_inner=1):
     """Oracle (numpy/scipy complex128, BLAS limited to one thread) on a bounded sample: the
     full factorisation of a few interior line problems and repeated single-right-hand-side
-    line solves, scaled to one step = all lines factored + (2G-1)^2 line solves per sweep and
-    one sweep per GMRES iteration per right-hand side (the sweep dominates the oracle's time;
-    matvecs and orthogonalisation are left out, so the estimate is a lower bound)."""
+    line solves, scaled to one step = all Gz Gy lines factored + (2Gz-1)(2Gy-1) line solves
+    per sweep (every group is visited twice but one, with one front or two) and one sweep per
+    GMRES iteration per right-hand side (the sweep dominates the oracle's time; matvecs and
+    orthogonalisation are left out, so the estimate is a lower bound)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import oracle as O
@@ -96,10 +131,11 @@ def cpu_baseline(wl, iters, budget_s):
             ln.solve(r)
             ns += 1
         t_sol = (time.perf_counter() - t1) / ns
-    solves_per_sweep = (2 * G - 1) ** 2
-    est = G * G * t_fac + float(np.sum(iters)) * solves_per_sweep * t_sol
+    Gz_, Gy_ = (group_count(wl["n"], wl["b"], wl["d"], fr) for fr in (fronts, fronts_inner))
+    solves_per_sweep = (2 * Gz_ - 1) * (2 * Gy_ - 1)
+    est = Gz_ * Gy_ * t_fac + float(np.sum(iters)) * solves_per_sweep * t_sol
     sample = (f"{len(lines)} interior line factorisations ({t_fac:.3f} s each) and {ns} line solves "
-              f"({t_sol * 1e3:.2f} ms each) of this workload, scaled to {G * G} factorisations + "
+              f"({t_sol * 1e3:.2f} ms each) of this workload, scaled to {Gz_ * Gy_} factorisations + "
               f"{int(np.sum(iters))} sweeps x {solves_per_sweep} line solves")
     return est, sample
 
@@ -114,6 +150,11 @@ def main():
     ap.add_argument("--fronts", type=int, default=2, choices=[1, 2],
                     help="outer sweep from both x3-faces meeting in a middle slab (2, the "
                          "configuration of the paper's experiments) or from x3 = 0 only (1)")
+    ap.add_argument("--fronts-inner", type=int, default=2, choices=[1, 2],
+                    help="the same for the inner sweep over x2")
+    ap.add_argument("--ref-tol", type=float, default=1e-10,
+                    help="after the FP64 solve, continue it to this residual for a reference "
+                         "solution the two 1e-6 solves are measured against (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -138,7 +179,7 @@ def main():
     log(f"workload {args.workload}: n={n} R={R} b={wl['b']} p={wl['p']} d={wl['d']} omega={wl['omega']:.4f}")
 
     for w in range(args.warmup):
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts)
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
         log(f"warmup {w}: iters {its.tolist()} setup {st['setup_ms']:.1f} ms apply {st['apply_ms']:.0f} ms")
         H.close()
         del u
@@ -150,7 +191,7 @@ def main():
            "kernel_ms": 0.0, "kernel_launches": 0, "kernel_rhs": 0}
     u_mix = None
     for k in range(args.steps):
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts)
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
         for key in tot:
             tot[key] += st[key]
         bpr, mvb, kbr = st["apply_bytes_per_rhs"], st["matvec_bytes_per_rhs"], st["kernel_bytes_per_rhs"]
@@ -166,24 +207,10 @@ def main():
     sec_per_step = (t1 - t0) / args.steps
 
     apply_avg_ms = tot["apply_ms"] / max(tot["apply_launches"], 1)
-    # the dominant kernel (with two fronts: the launches running both fronts)
+    # the dominant kernel (its two-chain launches)
     kernel_avg_ms = tot["kernel_ms"] / max(tot["kernel_launches"], 1)
     kernel_bytes_per_launch = kbr * tot["kernel_rhs"] / max(tot["kernel_launches"], 1)
-    # dependent block steps of one sweep (the longest chain of one workgroup): line solves of
-    # 2 (n/2) + 1 two-sided steps; with two fronts each front does max(mid, Gz-1-mid) slabs
-    # forward and backward, and the middle slab's lines take 2n - 1 one-chain steps
-    Gy = 1 + -(-(n - wl["b"]) // wl["d"])
-    lines_per_slab = 2 * Gy - 1
-    if args.fronts == 1:
-        steps_per_sweep = (2 * Gy - 1) * lines_per_slab * (2 * (n // 2) + 1)
-        steps_per_kernel = steps_per_sweep
-    else:
-        Gz = 2 + -(-(n - 2 * wl["b"]) // wl["d"])
-        zmid = Gz // 2
-        front = max(zmid, Gz - 1 - zmid)
-        steps_per_sweep = (2 * front * lines_per_slab * (2 * (n // 2) + 1)
-                           + lines_per_slab * (2 * n - 1))
-        steps_per_kernel = front * lines_per_slab * (2 * (n // 2) + 1)
+    steps_per_sweep, steps_per_kernel = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner)
     apply_bytes_per_launch = bpr * tot["apply_rhs"] / max(tot["apply_launches"], 1)
     achieved = kernel_bytes_per_launch / (kernel_avg_ms * 1e-3) / 1e9
     mv_gbs = mvb * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
@@ -203,14 +230,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n}^3, {R} point sources, b=p={wl['b']}, d={wl['d']}, "
                                f"omega/2pi={wl['omega'] / (2 * np.pi):.0f}, GMRES({wl['restart']}) to {wl['tol']:g}, "
-                               f"{args.fronts} front(s) in x3",
-                   "fronts": args.fronts,
+                               f"{args.fronts} front(s) in x3, {args.fronts_inner} in x2",
+                   "fronts": args.fronts, "fronts_inner": args.fronts_inner,
                    "n": n, "rhs": R, "b": wl["b"], "p": wl["p"], "slab_layers": wl["d"],
                    "factor_bytes": info["factor_bytes"], "lines": info["n_lines"], "max_block": info["max_block"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ("k_sweep, complex64" + (", the two launches per sweep that run both fronts"
-                                                        if args.fronts == 2 else ", one launch per sweep")),
+                     "kernel": "k_sweep, complex64, two-chain launches ("
+                               + (f"{tot['kernel_launches'] // max(tot['apply_launches'], 1)} per sweep"
+                                  + (": inner fronts forward / backward, one slab step each"
+                                     if args.fronts_inner == 2 else "") + ")"),
                      "avg_launch_ms": round(kernel_avg_ms, 3),
                      "algorithmic_bytes_per_launch": kernel_bytes_per_launch,
                      "chains_sharing_factor_stream": R},
@@ -225,12 +254,14 @@ def main():
         "apply_launches_per_step": tot["apply_launches"] / args.steps,
         "matvec_gbs": round(mv_gbs, 1),
     }
-    tr = measured_traffic(args.workload, args.fronts)
+    tr = measured_traffic(args.workload, args.fronts, args.fronts_inner)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
-        result["roofline"]["traffic_gbs"] = round(tr["hbm_bytes_per_launch"] / (tr["apply_ms"] * 1e-3) / 1e9, 1)
-        result["roofline"]["traffic_note"] = ("HBM bytes of one 32-right-hand-side launch of the kernel "
-                                              "(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), "
+        ms = tr.get("kernel_ms_per_launch", tr.get("apply_ms"))
+        result["roofline"]["traffic_gbs"] = round(tr["hbm_bytes_per_launch"] / (ms * 1e-3) / 1e9, 1)
+        result["roofline"]["traffic_note"] = ("HBM bytes of one 32-right-hand-side launch of the kernel, "
+                                              "averaged over a sweep's launches (rocprofv3 FETCH_SIZE + "
+                                              "WRITE_SIZE, copy-calibrated), "
                                               + os.path.relpath(tr["_path"], ROOT))
     log(f"mixed: {sec_per_step:.3f} s/step, sweep {achieved:.0f} GB/s algorithmic")
 
@@ -238,13 +269,44 @@ def main():
         log("fp64 path: one step with complex128 sweeps")
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", args.fronts)
+        from paper_1502_07266_amd.binding import plan_bytes, HELM_C128, HelmError
+        fi64 = args.fronts_inner
+        try:
+            plan_bytes(n, wl["b"], wl["C"], wl["p"], wl["d"], HELM_C128, args.fronts, fi64)
+        except HelmError:
+            fi64 = 1
+        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", args.fronts, fi64)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        diff = lambda a, b: float(((a - b).reshape(R, -1).norm(dim=1) / b.reshape(R, -1).norm(dim=1)).max())
+        if args.ref_tol > 0:
+            # the same FP64 solve continued from its own iterate: a reference solution whose
+            # distance to each 1e-6 solution is that solution's error (up to ~ref_tol x cond)
+            u_ref, its_ref, rel_ref, rc_ref = H.solve(F, tol=args.ref_tol, restart=wl["restart"], maxit=400, x0=u64)
+            torch.cuda.synchronize()
+            result["fp64_reference"] = {"tol": args.ref_tol, "extra_iters_max": int(its_ref.max()),
+                                        "relres_max": float(rel_ref.max()), "status": int(rc_ref),
+                                        "rel_l2_mixed_vs_ref_max": diff(u_mix, u_ref),
+                                        "rel_l2_fp64_vs_ref_max": diff(u64, u_ref)}
+            log(f"fp64 reference to {args.ref_tol:g}: mixed error {diff(u_mix, u_ref):.2e}, "
+                f"fp64 error {diff(u64, u_ref):.2e}")
+            del u_ref
         H.close()
+        if fi64 != args.fronts_inner:
+            # the precision effect alone: the mixed solve in the FP64 leg's configuration
+            t4 = time.perf_counter()
+            Hm, u_same, its_same, rel_same, rc_same, _ = run_step(Helm, c, wl, F, "c64", args.fronts, fi64)
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            Hm.close()
+            result["precision_parity"] = {"fronts_inner": fi64, "mixed_s": round(t5 - t4, 3),
+                                          "mixed_iters": its_same.tolist(),
+                                          "rel_l2_mixed_vs_fp64_max": diff(u_same, u64)}
+            log(f"mixed with fronts_inner={fi64}: {t5 - t4:.3f} s, vs fp64 rel-L2 max {diff(u_same, u64):.2e}")
+            del u_same
         d = (u_mix - u64).reshape(R, -1).norm(dim=1) / u64.reshape(R, -1).norm(dim=1)
         a64 = st64["apply_bytes_per_rhs"] * st64["apply_rhs"] / max(st64["apply_ms"] * 1e-3, 1e-12) / 1e9
-        result["fp64_path"] = {"s_per_step": round(t3 - t2, 4), "iters": its64.tolist(),
+        result["fp64_path"] = {"s_per_step": round(t3 - t2, 4), "iters": its64.tolist(), "fronts_inner": fi64,
                                "relres_max": float(rel64.max()), "sweep_gbs_algorithmic": round(a64, 1),
                                "sweep_avg_launch_ms": round(st64["apply_ms"] / max(st64["apply_launches"], 1), 3)}
         result["rel_l2_mixed_vs_fp64_max"] = float(d.max())
@@ -252,7 +314,7 @@ def main():
         del u64
 
     if args.cpu_budget > 0:
-        est, sample = cpu_baseline(wl, its_mix, args.cpu_budget)
+        est, sample = cpu_baseline(wl, its_mix, args.cpu_budget, args.fronts, args.fronts_inner)
         result["cpu_baseline"] = {"value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
                                   "sample": sample}
         log(f"cpu oracle estimate {est:.0f} s/step")

@@ -51,7 +51,7 @@ size_t planned_bytes(const Plan& p, int prec) {
   const size_t N = (size_t)p.n * p.n * p.n;
   return ((size_t)p.total_elems + kFactorPad) * csize(prec) + N * sizeof(double) +
          (size_t)(2 * (p.n + 1) + 1 + 2 * p.p + 2 + 5 * (p.n + 2)) * sizeof(double2) +
-         (size_t)(p.Gz + p.Gy) * sizeof(GroupInfo) + (size_t)p.Gz * p.Gy * sizeof(long long);
+         (size_t)(p.Gz + p.Gy) * sizeof(GroupInfo) + (size_t)p.Gz * p.Gy * (sizeof(long long) + sizeof(int));
 }
 
 // algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
@@ -117,7 +117,7 @@ void release(helm_handle* h) {
   h->t_matvec.reset();
   h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
-                  h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
+                  h->d_setup_lines, h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -194,6 +194,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   ALLOC(h->diag, (size_t)(plan.n + 2) * sizeof(double2));
   ALLOC(h->d_groups, plan.groups.size() * sizeof(GroupInfo));
   ALLOC(h->d_line_off, plan.line_off.size() * sizeof(long long));
+  ALLOC(h->d_setup_lines, plan.line_off.size() * sizeof(int));
   // the sweep's row-major block walk may read up to 64 entries past the last block
   ALLOC(h->factors, ((size_t)plan.total_elems + kFactorPad) * csize(prec));
   ALLOC(h->d_err, 2 * sizeof(int));
@@ -205,6 +206,11 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(h->d_line_off, plan.line_off.data(), plan.line_off.size() * sizeof(long long),
                      hipMemcpyHostToDevice, s) != hipSuccess)
+    return bail(HELM_EHIP, "copying the plan failed");
+  const std::vector<int> setup_lines = setup_line_order(plan, nullptr);
+  if (hipMemcpyAsync(h->d_setup_lines, setup_lines.data(), setup_lines.size() * sizeof(int),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)   // the host vector goes out of scope
     return bail(HELM_EHIP, "copying the plan failed");
   h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
   h->kernel_bytes_per_rhs = kernel_bytes_per_rhs(plan, prec);

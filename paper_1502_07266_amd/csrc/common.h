@@ -222,6 +222,7 @@ struct helm_handle {
   double2* coef = nullptr;         // [4][n+2]: A[m,m-1], A[m,m+1], A^H[m,m-1], A^H[m,m+1]
   double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
   GroupInfo* d_groups = nullptr;   // [Gz + Gy]
+  int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_line_order
   long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128
   int* d_err = nullptr;            // [2]: error flag, first failing line
@@ -245,6 +246,9 @@ struct helm_handle {
 // ---------------------------------------------------------------------------------------
 hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables, hipStream_t s);
 hipError_t launch_setup(helm_handle* h, hipStream_t s);
+// the lines in the order the setup launches take them: the two-chain lines, then the lines
+// on a middle group (*n_small receives the count of the first kind)
+std::vector<int> setup_line_order(const Plan& P, int* n_small);
 // z = M^{-1} r (or M^{-H}) for `R` right-hand sides; r in complex128 or complex64, z likewise;
 // rhs_idx (device, may be null = identity) selects which vectors to process: workgroup a
 // reads r + idx[a]*r_stride and writes z + idx[a]*z_stride (strides in complex elements).

@@ -16,7 +16,9 @@
 // reuses it for the next Schur update.  The blocks are eliminated from both ends towards the
 // middle (see the order below), which halves the dependent chain of the line solve.  All
 // lines are independent (Sec. 6 notes that the setup is O(n^2) independent quasi-1D
-// problems), so one launch covers them all.
+// problems).  The LDS of a launch is sized by its largest block, so the lines on a middle
+// group (few, with blocks up to 128) get a launch of their own, on a second stream beside
+// the launch of all other lines, whose small LDS footprint lets many workgroups share a CU.
 #include "common.h"
 
 namespace {
@@ -30,6 +32,7 @@ struct SetupArgs {
   int n, Gz, Gy, p;
   int fronts, zmid, fronts_inner, ymid;
   int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
+  const int* lines;  // the lines of this launch (workgroup w takes line lines[w])
   double h;
   const GroupInfo* groups;
   const long long* line_off;
@@ -60,7 +63,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   __shared__ C pinv_s;
   __shared__ int piv_s, bad_s;
 
-  const int line = blockIdx.x;
+  const int line = a.lines[blockIdx.x];
   const int g = line / a.Gy, l = line % a.Gy;
   const GroupInfo gz = a.groups[g], gy = a.groups[a.Gz + l];
   const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
@@ -208,7 +211,44 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   }
 }
 
+// one launch over `count` lines listed at d_lines, LDS sized for blocks up to maxB
+hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, int count, int maxB,
+                        hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  a.lines = d_lines;
+  const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
+  // keep the previous factor in LDS when two B x B blocks fit, else re-read it from HBM
+  a.prev_in_lds = 2 * (size_t)maxB * maxB * csz <= kSetupLdsBytes;
+  const size_t sm = (a.prev_in_lds ? 2 : 1) * (size_t)maxB * maxB * csz;
+  if (h->prec == HELM_C64) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    k_line_setup<float><<<count, kSetupThreads, sm, s>>>(a);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    k_line_setup<double><<<count, kSetupThreads, sm, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+// The line list: the two-chain lines first, then the lines on a middle group.
+std::vector<int> setup_line_order(const Plan& P, int* n_small) {
+  std::vector<int> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int g = 0; g < P.Gz; ++g)
+      for (int l = 0; l < P.Gy; ++l)
+        if (P.one_chain(g, l) == (pass == 1)) {
+          if (pass == 1 && n_small && *n_small < 0) *n_small = (int)order.size();
+          order.push_back(g * P.Gy + l);
+        }
+  if (n_small && *n_small < 0) *n_small = (int)order.size();
+  return order;
+}
 
 hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   const Plan& P = h->plan;
@@ -229,21 +269,27 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   a.kappa = h->kappa;
   a.factors = h->factors;
   a.err = h->d_err;
-  const unsigned lines = (unsigned)(P.Gz * P.Gy);
-  const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
-  // keep the previous factor in LDS when two B x B blocks fit, else re-read it from HBM
-  a.prev_in_lds = 2 * (size_t)P.maxB * P.maxB * csz <= kSetupLdsBytes;
-  const size_t sm = (a.prev_in_lds ? 2 : 1) * (size_t)P.maxB * P.maxB * csz;
-  if (h->prec == HELM_C64) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    k_line_setup<float><<<lines, kSetupThreads, sm, s>>>(a);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    k_line_setup<double><<<lines, kSetupThreads, sm, s>>>(a);
-  }
-  return hipGetLastError();
+  a.lines = nullptr;
+  int n_small = -1;
+  const int total = (int)setup_line_order(P, &n_small).size();
+  const int n_big = total - n_small;
+  if (n_big == 0) return setup_launch(h, a, h->d_setup_lines, total, P.maxB_front, s);
+  // the lines on a middle group on a second stream, beside the others: s2 starts after the
+  // work already queued on s, and s continues only after s2 is done
+  hipStream_t s2 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s2, e0, 0);
+  if (e == hipSuccess) e = setup_launch(h, a, h->d_setup_lines + n_small, n_big, P.maxB_mid, s2);
+  if (e == hipSuccess) e = setup_launch(h, a, h->d_setup_lines, n_small, P.maxB_front, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, e1, 0);
+  // destroying a stream or event with work pending is allowed: it is released once done
+  if (e1) (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (s2) (void)hipStreamDestroy(s2);
+  return e;
 }

@@ -1,6 +1,7 @@
 """Driver for hardware-counter runs of the sweep: one plain copy of a known size, then one
-batched sweep (helm_apply) of a workload (one kernel dispatch with one front; with two
-fronts, two dispatches of the front kernel and one of the middle slab).
+batched sweep (helm_apply) of a workload (the launches of sweep_schedule: one dispatch with
+one front; with two fronts, two of the front kernel and one of the middle slab; with two
+inner fronts, three per slab step).
 
     python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024
 
@@ -26,6 +27,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--rhs", type=int, default=0, help="right-hand sides (0: all of the workload)")
     ap.add_argument("--fronts", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--fronts-inner", type=int, default=2, choices=[1, 2])
     args = ap.parse_args()
 
     wl = inputs.workload(args.workload)
@@ -49,7 +51,8 @@ def main():
 
     c = torch.from_numpy(wl["c"]).to(dev)
     F = torch.from_numpy(inputs.sources(n, nodes)).to(dev)
-    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec, fronts=args.fronts)
+    H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec, fronts=args.fronts,
+             fronts_inner=args.fronts_inner)
     H.reset_stats()
     t0 = time.perf_counter()
     H.apply(F)
@@ -58,6 +61,7 @@ def main():
     print(f"[profile] apply {args.prec} R={R}: {st['apply_ms']:.1f} ms "
           f"(host {1e3 * (time.perf_counter() - t0):.1f} ms)", flush=True)
     print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R, "fronts": args.fronts,
+                      "fronts_inner": args.fronts_inner,
                       "copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": copy_ms,
                       "apply_ms": st["apply_ms"],
                       "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R,
