@@ -78,7 +78,7 @@ def traffic_profile_name(fronts, fronts_inner):
             (2, 2): "k_sweep_fronts_both_axes"}[(fronts, fronts_inner)]
 
 
-def measured_traffic(workload, fronts, fronts_inner):
+def measured_traffic(workload, wl, fronts, fronts_inner):
     """HBM bytes per sweep launch from the committed counter run (FETCH_SIZE and WRITE_SIZE of
     one 32-right-hand-side launch, each scaled by what the counter reads for a plain copy of
     known size), or None when that run does not cover this workload or the sweep source has
@@ -92,6 +92,8 @@ def measured_traffic(workload, fronts, fronts_inner):
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("fronts", 1) != fronts or rec.get("fronts_inner", 1) != fronts_inner:
+        return None
+    if (rec.get("d"), rec.get("p")) != (wl["d"], wl["p"]):
         return None
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != rec.get("sweep_source_sha256"):
@@ -228,7 +230,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 sweep / f64 GMRES",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {n}^3, {R} point sources, b=p={wl['b']}, d={wl['d']}, "
+        "config": {"workload": f"{args.workload}: {n}^3, {R} point sources, b={wl['b']}, p={wl['p']}, d={wl['d']}, "
                                f"omega/2pi={wl['omega'] / (2 * np.pi):.0f}, GMRES({wl['restart']}) to {wl['tol']:g}, "
                                f"{args.fronts} front(s) in x3, {args.fronts_inner} in x2",
                    "fronts": args.fronts, "fronts_inner": args.fronts_inner,
@@ -254,7 +256,7 @@ def main():
         "apply_launches_per_step": tot["apply_launches"] / args.steps,
         "matvec_gbs": round(mv_gbs, 1),
     }
-    tr = measured_traffic(args.workload, args.fronts, args.fronts_inner)
+    tr = measured_traffic(args.workload, wl, args.fronts, args.fronts_inner)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
         ms = tr.get("kernel_ms_per_launch", tr.get("apply_ms"))
@@ -270,12 +272,17 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         from paper_1502_07266_amd.binding import plan_bytes, HELM_C128, HelmError
-        fi64 = args.fronts_inner
-        try:
-            plan_bytes(n, wl["b"], wl["C"], wl["p"], wl["d"], HELM_C128, args.fronts, fi64)
-        except HelmError:
-            fi64 = 1
-        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", args.fronts, fi64)
+        # the requested fronts if complex128 supports them (its line vectors of the blocks on
+        # a middle group must fit in LDS), else fewer
+        fr64, fi64 = 1, 1
+        for fr_, fi_ in [(args.fronts, args.fronts_inner), (args.fronts, 1), (1, 1)]:
+            try:
+                plan_bytes(n, wl["b"], wl["C"], wl["p"], wl["d"], HELM_C128, fr_, fi_)
+            except HelmError:
+                continue
+            fr64, fi64 = fr_, fi_
+            break
+        H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", fr64, fi64)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         diff = lambda a, b: float(((a - b).reshape(R, -1).norm(dim=1) / b.reshape(R, -1).norm(dim=1)).max())
@@ -292,21 +299,22 @@ def main():
                 f"fp64 error {diff(u64, u_ref):.2e}")
             del u_ref
         H.close()
-        if fi64 != args.fronts_inner:
+        if (fr64, fi64) != (args.fronts, args.fronts_inner):
             # the precision effect alone: the mixed solve in the FP64 leg's configuration
             t4 = time.perf_counter()
-            Hm, u_same, its_same, rel_same, rc_same, _ = run_step(Helm, c, wl, F, "c64", args.fronts, fi64)
+            Hm, u_same, its_same, rel_same, rc_same, _ = run_step(Helm, c, wl, F, "c64", fr64, fi64)
             torch.cuda.synchronize()
             t5 = time.perf_counter()
             Hm.close()
-            result["precision_parity"] = {"fronts_inner": fi64, "mixed_s": round(t5 - t4, 3),
+            result["precision_parity"] = {"fronts": fr64, "fronts_inner": fi64, "mixed_s": round(t5 - t4, 3),
                                           "mixed_iters": its_same.tolist(),
                                           "rel_l2_mixed_vs_fp64_max": diff(u_same, u64)}
             log(f"mixed with fronts_inner={fi64}: {t5 - t4:.3f} s, vs fp64 rel-L2 max {diff(u_same, u64):.2e}")
             del u_same
         d = (u_mix - u64).reshape(R, -1).norm(dim=1) / u64.reshape(R, -1).norm(dim=1)
         a64 = st64["apply_bytes_per_rhs"] * st64["apply_rhs"] / max(st64["apply_ms"] * 1e-3, 1e-12) / 1e9
-        result["fp64_path"] = {"s_per_step": round(t3 - t2, 4), "iters": its64.tolist(), "fronts_inner": fi64,
+        result["fp64_path"] = {"s_per_step": round(t3 - t2, 4), "iters": its64.tolist(), "fronts": fr64,
+                               "fronts_inner": fi64,
                                "relres_max": float(rel64.max()), "sweep_gbs_algorithmic": round(a64, 1),
                                "sweep_avg_launch_ms": round(st64["apply_ms"] / max(st64["apply_launches"], 1), 3)}
         result["rel_l2_mixed_vs_fp64_max"] = float(d.max())

@@ -517,12 +517,13 @@ struct Shape {
   int nc, cw;
 };
 
-Shape choose_shape(int maxB, int lanes) {
-  // default: 8 lanes per block row up to B = 40 (measured fastest for two chains at B = 36),
-  // 4 lanes beyond (8 x 7 columns leaves too few registers for the factor ring); 16 lanes
-  // only fit two chains in one workgroup up to B = 32.  CW is the smallest instantiated
-  // column count covering B.
-  const int nc = lanes ? lanes : (maxB <= 40 ? 8 : 4);
+Shape choose_shape(int maxB, int lanes, bool c64) {
+  // default: 8 lanes per block row (measured fastest for two chains at B = 36, 49 and 64 in
+  // complex64, although 8 x 7 and 8 x 8 columns leave registers for a ring of only 4 and 2
+  // blocks; in complex128 they leave none, so 4 lanes beyond B = 40); 16 lanes only fit two
+  // chains in one workgroup up to B = 32.  CW is the smallest instantiated column count
+  // covering B.
+  const int nc = lanes ? lanes : ((c64 || maxB <= 40) ? 8 : 4);
   const int need = (maxB + nc - 1) / nc;
   static const int cw4[] = {5, 7, 9, 13, 16}, cw8[] = {3, 4, 5, 7, 8}, cw16[] = {1, 2};
   const int* t = nc == 4 ? cw4 : (nc == 8 ? cw8 : cw16);
@@ -668,7 +669,8 @@ hipError_t sweep_launch(helm_handle* h, SweepArgs a, const SweepLaunch& L, int R
   a.ipass = L.ipass;
   a.ninner = L.ninner;
   a.maxB = L.maxB;
-  const Shape sh = L.chains == 2 ? choose_shape(L.maxB, h->lanes_override) : choose_shape_one(L.maxB);
+  const Shape sh = L.chains == 2 ? choose_shape(L.maxB, h->lanes_override, sizeof(R) == 4)
+                                 : choose_shape_one(L.maxB);
   if (sh.cw < 0 || !lds_fits(h->n, L.maxB, sh, L.chains)) return hipErrorInvalidValue;
   a.tpc = chain_threads(L.maxB, sh.nc);
   const size_t sm = LdsLayout(h->n, L.maxB, (int)sizeof(typename cx<R>::type)).bytes;
@@ -802,7 +804,7 @@ hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, d
   const int mb = one ? P.maxB_mid : P.maxB_front;
   a.maxB = mb;
   const size_t sm = LdsLayout(h->n, mb, (int)csz).bytes;
-  const Shape sh = one ? choose_shape_one(mb) : choose_shape(mb, h->lanes_override);
+  const Shape sh = one ? choose_shape_one(mb) : choose_shape(mb, h->lanes_override, c64);
   if (sh.cw < 0 || !lds_fits(h->n, mb, sh, one ? 1 : 2)) return hipErrorInvalidValue;
   a.tpc = chain_threads(mb, sh.nc);
   const int chains = one ? 1 : 2;

@@ -61,7 +61,7 @@ def main():
     print(f"[profile] apply {args.prec} R={R}: {st['apply_ms']:.1f} ms "
           f"(host {1e3 * (time.perf_counter() - t0):.1f} ms)", flush=True)
     print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R, "fronts": args.fronts,
-                      "fronts_inner": args.fronts_inner,
+                      "fronts_inner": args.fronts_inner, "b": wl["b"], "p": wl["p"], "d": wl["d"],
                       "copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": copy_ms,
                       "apply_ms": st["apply_ms"],
                       "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R,

@@ -43,7 +43,8 @@ def main():
     copy_bytes = run["copy_bytes_read"]
 
     out = {"workload": run["workload"], "rhs": run["rhs"], "fronts": run["fronts"],
-           "fronts_inner": run.get("fronts_inner", 1), "copy_bytes": copy_bytes}
+           "fronts_inner": run.get("fronts_inner", 1), "b": run.get("b"), "p": run.get("p"),
+           "d": run.get("d"), "copy_bytes": copy_bytes}
     hbm = 0.0
     for counter, path, moved in (("FETCH_SIZE", args.fetch, copy_bytes),
                                  ("WRITE_SIZE", args.write, run["copy_bytes_written"])):

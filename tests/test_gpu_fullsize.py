@@ -8,7 +8,7 @@ so sampled line factorisations are compared block by block with the oracle's, an
 checked through properties that hold at any size: the adjoint dot test
 <M^{-1} x, y> = <x, M^{-H} y>, linearity, and the distance between the complex64 and the
 complex128 sweeps.  Tolerances as in test_gpu_parity.py; the complex64 sweep composes
-(2G - 1)^2 = 60 025 line solves at 127^3 and is allowed 1e-3.
+(2G - 1)^2 line solves (6 889 at 127^3 with one front) and is allowed 1e-3.
 """
 import numpy as np
 import pytest
