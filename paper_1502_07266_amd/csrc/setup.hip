@@ -25,7 +25,8 @@ namespace {
 
 constexpr int kMaxW = 64;
 constexpr int kMaxB = 128;
-constexpr int kSetupThreads = 256;
+constexpr int kSetupThreads = 256;        // lines with two-chain blocks (B <= 64)
+constexpr int kSetupThreadsBig = 1024;    // lines on a middle group (B up to 128)
 constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may take (of 160 KiB)
 
 struct SetupArgs {
@@ -53,8 +54,10 @@ __device__ inline double2 window_s(const SetupArgs& a, const GroupInfo& gi, int 
   return a.sbd[t];
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
+// The B x B loops run rows across waves and columns across lanes (c and c + 64), so no
+// element index is divided by B.
+template <typename R, int NTB>
+__global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double2 syn[kMaxW], syh[kMaxW + 1], szn[kMaxW], szh[kMaxW + 1];
@@ -69,6 +72,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
   const int n = a.n;
   const int tid = threadIdx.x, NT = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
   C* S = reinterpret_cast<C*>(smem_raw);
   C* out = reinterpret_cast<C*>(a.factors) + a.line_off[line];
   const double ih2 = 1.0 / (a.h * a.h);
@@ -83,9 +87,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
   // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
   // middle block m last, whose Schur complement takes the update from both sides; m = n/2
   // (integer division), or m = n - 1 (the order of Sec. 3) for the lines on a middle group
-  // (x3 with two fronts, x2 with two inner fronts).  It is the block LDU of Sec. 3 with the blocks in that order (every block
-  // eliminated is an end of the remaining chain, so there is no fill); the sweep runs the two
-  // halves of each line solve as two concurrent chains.
+  // (x3 with two fronts, x2 with two inner fronts).  It is the block LDU of Sec. 3 with the
+  // blocks in that order (every block eliminated is an end of the remaining chain, so there
+  // is no fill); the sweep runs the two halves of each line solve as two concurrent chains.
   const bool one_chain = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
   const int mid = one_chain ? n - 1 : n / 2;
   // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
@@ -108,9 +112,11 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
     const C scA = (t < mid || is_mid) ? sc_below : sc_above;
     const C* TA = (is_mid && has_lower) ? T_mid_minus1 : Tprev;
     const bool use_b = is_mid && has_lower;
-    for (int e = tid; e < B * B; e += NT) {
-      const int r = e / B, c = e - r * B;
-      const int jr = r / Wz, kr = r - jr * Wz, jc = c / Wz, kc = c - jc * Wz;
+    for (int r = wv; r < B; r += nw) {
+      const int jr = r / Wz, kr = r - jr * Wz;
+      for (int c = lane; c < B; c += 64) {
+      const int e = r * B + c;
+      const int jc = c / Wz, kc = c - jc * Wz;
       double2 val = make_double2(0.0, 0.0);
       if (r == c) {
         const int k = gz.w0 + kr, j = gy.w0 + jr;
@@ -130,6 +136,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
       if (use_a) v = csub(v, cmul(scA, TA[e]));
       if (use_b) v = csub(v, cmul(sc_above, Tprev[e]));
       S[e] = v;
+      }
     }
     __syncthreads();
 
@@ -170,11 +177,14 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
       for (int r = tid; r < B; r += NT)
         if (r != k) fcol[r] = S[r * B + k];
       __syncthreads();
-      for (int e = tid; e < B * B; e += NT) {
-        const int r = e / B, c = e - r * B;
+      for (int r = wv; r < B; r += nw) {
         if (r == k) continue;
-        C old = (c == k) ? mk((R)0, (R)0) : S[e];
-        S[e] = csub(old, cmul(fcol[r], S[k * B + c]));
+        const C fr = fcol[r];
+        for (int c = lane; c < B; c += 64) {
+          const int e = r * B + c;
+          const C old = (c == k) ? mk((R)0, (R)0) : S[e];
+          S[e] = csub(old, cmul(fr, S[k * B + c]));
+        }
       }
       __syncthreads();
     }
@@ -190,17 +200,13 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
     __syncthreads();
     C* dst = out + (long long)i * B * B;
     if (a.prev_in_lds) {
-      for (int e = tid; e < B * B; e += NT) {
-        const int r = e / B, q = e - r * B;
-        Tlds[r * B + rho[q]] = S[e];
-      }
+      for (int r = wv; r < B; r += nw)
+        for (int q = lane; q < B; q += 64) Tlds[r * B + rho[q]] = S[r * B + q];
       __syncthreads();
       for (int e = tid; e < B * B; e += NT) dst[e] = Tlds[e];
     } else {
-      for (int e = tid; e < B * B; e += NT) {
-        const int r = e / B, q = e - r * B;
-        dst[r * B + rho[q]] = S[e];
-      }
+      for (int r = wv; r < B; r += nw)
+        for (int q = lane; q < B; q += 64) dst[r * B + rho[q]] = S[r * B + q];
       __syncthreads();   // the next block's Schur update reads dst (workgroup-scope fence)
       Tprev = dst;
     }
@@ -212,6 +218,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_line_setup(SetupArgs a) {
 }
 
 // one launch over `count` lines listed at d_lines, LDS sized for blocks up to maxB
+template <int NTB>
 hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, int count, int maxB,
                         hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -221,15 +228,15 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
   a.prev_in_lds = 2 * (size_t)maxB * maxB * csz <= kSetupLdsBytes;
   const size_t sm = (a.prev_in_lds ? 2 : 1) * (size_t)maxB * maxB * csz;
   if (h->prec == HELM_C64) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float, NTB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    k_line_setup<float><<<count, kSetupThreads, sm, s>>>(a);
+    k_line_setup<float, NTB><<<count, NTB, sm, s>>>(a);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double, NTB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    k_line_setup<double><<<count, kSetupThreads, sm, s>>>(a);
+    k_line_setup<double, NTB><<<count, NTB, sm, s>>>(a);
   }
   return hipGetLastError();
 }
@@ -273,7 +280,7 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   int n_small = -1;
   const int total = (int)setup_line_order(P, &n_small).size();
   const int n_big = total - n_small;
-  if (n_big == 0) return setup_launch(h, a, h->d_setup_lines, total, P.maxB_front, s);
+  if (n_big == 0) return setup_launch<kSetupThreads>(h, a, h->d_setup_lines, total, P.maxB_front, s);
   // the lines on a middle group on a second stream, beside the others: s2 starts after the
   // work already queued on s, and s continues only after s2 is done
   hipStream_t s2 = nullptr;
@@ -283,8 +290,9 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(e0, s);
   if (e == hipSuccess) e = hipStreamWaitEvent(s2, e0, 0);
-  if (e == hipSuccess) e = setup_launch(h, a, h->d_setup_lines + n_small, n_big, P.maxB_mid, s2);
-  if (e == hipSuccess) e = setup_launch(h, a, h->d_setup_lines, n_small, P.maxB_front, s);
+  if (e == hipSuccess)
+    e = setup_launch<kSetupThreadsBig>(h, a, h->d_setup_lines + n_small, n_big, P.maxB_mid, s2);
+  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, h->d_setup_lines, n_small, P.maxB_front, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s2);
   if (e == hipSuccess) e = hipStreamWaitEvent(s, e1, 0);
   // destroying a stream or event with work pending is allowed: it is released once done

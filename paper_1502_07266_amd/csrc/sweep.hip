@@ -256,13 +256,26 @@ struct LineSolver {
     lds_barrier();
   }
 
+  // D consecutive steps, one per ring slot, with no branch between them: the loop over such
+  // groups has a single path, so the wait before each slot's use covers exactly the loads
+  // issued D steps earlier (with early exits between the steps, the merged paths would make
+  // the first step of every group wait for the whole ring)
   template <int S = 0>
   __device__ __forceinline__ void group(int t0, C* sb, const C* zme, const C* zot, const int4* tab,
                                         const C* ctab) {
     if constexpr (S < D) {
+      step<S>(t0 + S, sb, zme, zot, tab, ctab);
+      group<S + 1>(t0, sb, zme, zot, tab, ctab);
+    }
+  }
+  // the last steps % D steps of a line
+  template <int S = 0>
+  __device__ __forceinline__ void tail(int t0, C* sb, const C* zme, const C* zot, const int4* tab,
+                                       const C* ctab) {
+    if constexpr (S < D) {
       if (t0 + S < steps) {
         step<S>(t0 + S, sb, zme, zot, tab, ctab);
-        group<S + 1>(t0, sb, zme, zot, tab, ctab);
+        tail<S + 1>(t0, sb, zme, zot, tab, ctab);
       }
     }
   }
@@ -330,8 +343,10 @@ struct LineSolver {
     Acur = sb[ecur.x + rowc];
     const C* zme = sb + zb + lower * 2 * ZS;
     const C* zot = sb + zb + (1 - lower) * 2 * ZS;
-    for (int t0 = 0; t0 < steps; t0 += D)
-      group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+    const int full = steps - steps % D;
+    int t0 = 0;
+    for (; t0 < full; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+    if (t0 < steps) tail(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
   }
 };
 
@@ -551,12 +566,13 @@ hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Arg
   X(4, 5, 16, 12) X(4, 7, 16, 12) X(4, 9, 8, 4) X(4, 13, 6, 2) X(4, 16, 4, 2)          \
   X(8, 3, 16, 12) X(8, 4, 16, 10) X(8, 5, 8, 4) X(8, 7, 4, 0) X(8, 8, 2, 0)            \
   X(16, 1, 16, 16) X(16, 2, 16, 8)
-// one chain spanning the workgroup (the two-front middle slab, blocks up to 128): 8 lanes
-// per row
-#define HELM_SHAPES_ONE(X) X(8, 3, 16, 12) X(8, 6, 8, 6) X(8, 9, 4, 2) X(8, 12, 2, 2) X(8, 16, 2, 0)
+// one chain spanning the workgroup (lines on a middle group, blocks up to 128): 8 lanes per
+// row
+#define HELM_SHAPES_ONE(X) \
+  X(8, 3, 16, 12) X(8, 6, 8, 6) X(8, 9, 4, 2) X(8, 10, 4, 2) X(8, 12, 2, 2) X(8, 16, 2, 0)
 
 Shape choose_shape_one(int maxB) {
-  static const int cw[] = {3, 6, 9, 12, 16};
+  static const int cw[] = {3, 6, 9, 10, 12, 16};
   for (int c : cw)
     if (8 * c >= maxB) return {8, c};
   return {8, -1};
