@@ -160,6 +160,23 @@ int helm_misfit(helm_handle* h, const void* u_dev, const void* d_dev, int R, int
 int helm_set_medium(helm_handle* h, const double* c_dev, void* stream);
 
 /*
+ * helm_update_medium -- local update of the setup after a change of the velocity (Sec. 6,
+ * future work: re-factor only the auxiliary problems a local change reaches).  c_dev (n^3
+ * float64 > 0) replaces the medium; it must differ from the medium of the current factors
+ * only inside box_host = {i0, i1, j0, j1, k0, k1} (host array, 1-based, inclusive,
+ * 1 <= lo <= hi <= n).  A line problem's matrix reads omega^2/c^2 on its own window only, so
+ * line (g, l) is re-factored iff its x3-window meets [k0, k1] and its x2-window meets
+ * [j0, j1] (every line spans all of x1); all other factors are kept and are those of the new
+ * medium already.  The result equals a fresh helm_setup on the new medium, bit for bit.
+ * helm_stats.setup_ms then reports the update's device time.
+ *   n_refactored : receives the number of lines re-factored (may be NULL).
+ * Errors: HELM_EINVAL (bad box, c not finite and > 0), HELM_ESINGULAR, HELM_EHIP.
+ * Synchronises `stream`.
+ */
+int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host, int* n_refactored,
+                       void* stream);
+
+/*
  * helm_info -- sizes of the setup: factor bytes, number of line problems, largest block.
  * Any output pointer may be NULL.
  */

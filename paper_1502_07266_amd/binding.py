@@ -48,6 +48,7 @@ _SIGS = {
     "helm_grad_c": (_I, [_P, _P, _P, _I, _P, _P]),
     "helm_misfit": (_I, [_P, _P, _P, _I, _I, ctypes.POINTER(_D), _P, _P]),
     "helm_set_medium": (_I, [_P, _P, _P]),
+    "helm_update_medium": (_I, [_P, _P, _P, _P, _P]),
     "helm_info": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "helm_plan_bytes": (_I, [ctypes.POINTER(helm_grid), ctypes.POINTER(helm_pml), _I, _I,
                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -212,6 +213,16 @@ class Helm:
     def set_medium(self, c):
         c = c.contiguous()
         _check(lib().helm_set_medium(self.handle, _ptr(c), _stream()), "helm_set_medium")
+
+    def update_medium(self, c, box):
+        """Local update after a change of c inside box = (i0, i1, j0, j1, k0, k1) (1-based,
+        inclusive): re-factors the lines whose windows meet the box; returns their count."""
+        c = c.contiguous()
+        b = (ctypes.c_int * 6)(*[int(v) for v in box])
+        nr = _I()
+        _check(lib().helm_update_medium(self.handle, _ptr(c), b, ctypes.byref(nr), _stream()),
+               "helm_update_medium")
+        return nr.value
 
     def info(self):
         fb, nl, mb = ctypes.c_size_t(), _I(), _I()

@@ -321,6 +321,52 @@ int helm_set_medium(helm_handle* h, const double* c_dev, void* stream) {
   return HELM_OK;
 }
 
+int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host, int* n_refactored,
+                       void* stream) {
+  if (n_refactored) *n_refactored = 0;
+  if (!h || !c_dev || !box_host) return fail(HELM_EINVAL, "handle, c_dev and box must not be NULL");
+  const int n = h->n;
+  const int i0 = box_host[0], i1 = box_host[1], j0 = box_host[2], j1 = box_host[3],
+            k0 = box_host[4], k1 = box_host[5];
+  if (i0 < 1 || i1 < i0 || i1 > n || j0 < 1 || j1 < j0 || j1 > n || k0 < 1 || k1 < k0 || k1 > n)
+    return fail(HELM_EINVAL, "box must satisfy 1 <= lo <= hi <= n on every axis");
+  hipStream_t s = S(stream);
+  HIP_TRY(launch_coefficients(h, c_dev, false, s));
+  int err[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err[0]) return fail(HELM_EINVAL, "c must be finite and > 0 at every node");
+  // a line's matrix reads omega^2/c^2 on its window only (x3-window x x2-window x all of x1)
+  const Plan& P = h->plan;
+  auto meets = [](const GroupInfo& gi, int lo, int hi) { return gi.w0 <= hi && gi.w0 + gi.W - 1 >= lo; };
+  std::vector<int> lines;
+  int n_small = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int g = 0; g < P.Gz; ++g) {
+      if (!meets(P.zg(g), k0, k1)) continue;
+      for (int l = 0; l < P.Gy; ++l)
+        if (meets(P.yg(l), j0, j1) && P.one_chain(g, l) == (pass == 1)) lines.push_back(g * P.Gy + l);
+    }
+  for (int line : lines)
+    if (!P.one_chain(line / P.Gy, line % P.Gy)) ++n_small;
+  if (lines.empty()) return HELM_OK;
+  // the setup's line list is free after helm_setup: it takes this list
+  HIP_TRY(hipMemcpyAsync(h->d_setup_lines, lines.data(), lines.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(h->d_err, 0, 2 * sizeof(int), s));
+  LaunchTimer t;
+  hipEvent_t ev = t.begin(s);
+  HIP_TRY(launch_setup_lines(h, h->d_setup_lines, n_small, (int)lines.size() - n_small, s));
+  t.end(ev, s, 1);
+  HIP_TRY(hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  t.flush();
+  h->setup_ms = t.ms;
+  if (n_refactored) *n_refactored = (int)lines.size();
+  if (err[0]) return fail(HELM_ESINGULAR, "singular block in line " + std::to_string(err[1]));
+  return HELM_OK;
+}
+
 int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max_block) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
   if (factor_bytes) *factor_bytes = (size_t)h->plan.total_elems * csize(h->prec);

@@ -249,6 +249,10 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s);
 // the lines in the order the setup launches take them: the two-chain lines, then the lines
 // on a middle group (*n_small receives the count of the first kind)
 std::vector<int> setup_line_order(const Plan& P, int* n_small);
+// the setup of a list of lines (device array: n_small two-chain lines, then n_big lines on a
+// middle group)
+hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, int n_big,
+                              hipStream_t s);
 // z = M^{-1} r (or M^{-H}) for `R` right-hand sides; r in complex128 or complex64, z likewise;
 // rhs_idx (device, may be null = identity) selects which vectors to process: workgroup a
 // reads r + idx[a]*r_stride and writes z + idx[a]*z_stride (strides in complex elements).

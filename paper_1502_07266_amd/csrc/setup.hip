@@ -258,6 +258,13 @@ std::vector<int> setup_line_order(const Plan& P, int* n_small) {
 }
 
 hipError_t launch_setup(helm_handle* h, hipStream_t s) {
+  int n_small = -1;
+  const int total = (int)setup_line_order(h->plan, &n_small).size();
+  return launch_setup_lines(h, h->d_setup_lines, n_small, total - n_small, s);
+}
+
+hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, int n_big,
+                              hipStream_t s) {
   const Plan& P = h->plan;
   SetupArgs a;
   a.n = h->n;
@@ -277,10 +284,7 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   a.factors = h->factors;
   a.err = h->d_err;
   a.lines = nullptr;
-  int n_small = -1;
-  const int total = (int)setup_line_order(P, &n_small).size();
-  const int n_big = total - n_small;
-  if (n_big == 0) return setup_launch<kSetupThreads>(h, a, h->d_setup_lines, total, P.maxB_front, s);
+  if (n_big == 0) return setup_launch<kSetupThreads>(h, a, d_lines, n_small, P.maxB_front, s);
   // the lines on a middle group on a second stream, beside the others: s2 starts after the
   // work already queued on s, and s continues only after s2 is done
   hipStream_t s2 = nullptr;
@@ -291,8 +295,8 @@ hipError_t launch_setup(helm_handle* h, hipStream_t s) {
   if (e == hipSuccess) e = hipEventRecord(e0, s);
   if (e == hipSuccess) e = hipStreamWaitEvent(s2, e0, 0);
   if (e == hipSuccess)
-    e = setup_launch<kSetupThreadsBig>(h, a, h->d_setup_lines + n_small, n_big, P.maxB_mid, s2);
-  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, h->d_setup_lines, n_small, P.maxB_front, s);
+    e = setup_launch<kSetupThreadsBig>(h, a, d_lines + n_small, n_big, P.maxB_mid, s2);
+  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, d_lines, n_small, P.maxB_front, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s2);
   if (e == hipSuccess) e = hipStreamWaitEvent(s, e1, 0);
   // destroying a stream or event with work pending is allowed: it is released once done

@@ -67,4 +67,5 @@ def test_null_handle_rejected():
     assert L.helm_apply(None, None, None, 1, None) == binding.HELM_EINVAL
     assert L.helm_solve(None, None, None, 1, 1e-6, 50, 10, 0, None, None, None) == binding.HELM_EINVAL
     assert L.helm_set_launch(None, 8) == binding.HELM_EINVAL
+    assert L.helm_update_medium(None, None, None, None, None) == binding.HELM_EINVAL
     L.helm_destroy(None)

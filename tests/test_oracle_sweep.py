@@ -303,3 +303,32 @@ def test_two_inner_fronts_linear_adjoint_and_effective():
     M1 = O.RecursiveSweep(_prob(n=11))
     _, its1, _ = O.fgmres(lambda v: M1.A @ v, lambda v: M1.apply(v)[:, 0], f, tol=1e-10, restart=40, maxit=80)
     assert its <= its1 + 3, (its, its1)
+
+
+@pytest.mark.parametrize("fronts,fronts_inner", [(1, 1), (2, 2)])
+def test_line_problem_depends_on_its_window_only(fronts, fronts_inner):
+    """Sec. 6 (local updates): a change of c inside a box changes the line problem (g, l)
+    exactly when the box meets its x3-window and its x2-window (a line spans all of x1).  This
+    is the selection rule of the library's local factor update."""
+    n, b, p, d = 13, 3, 3, 2
+    case = inputs.small_case(n=n, b=b, p=p, d=d)
+    c = case["c"]
+    box = (4, 9, 6, 7, 9, 10)                   # i0, i1, j0, j1, k0, k1 (1-based)
+    c2 = c.copy()
+    c2[box[4] - 1:box[5], box[2] - 1:box[3], box[0] - 1:box[1]] *= 1.07
+    kw = dict(n=n, omega=case["omega"], b=b, C=case["C"], p=p, d=d, fronts=fronts, fronts_inner=fronts_inner)
+    P1, P2 = O.Problem(c=c, **kw), O.Problem(c=c2, **kw)
+    Gz = O.groups_two_fronts(n, b, d) if fronts == 2 else O.groups(n, b, d)
+    Gy = O.groups_two_fronts(n, b, d) if fronts_inner == 2 else O.groups(n, b, d)
+    changed = 0
+    for g in range(len(Gz)):
+        zw0, zw1, _, _ = O.window_fronts(Gz, g, p, fronts)
+        for l in range(len(Gy)):
+            yw0, yw1, _, _ = O.window_fronts(Gy, l, p, fronts_inner)
+            K1 = O.LineFactors(P1, Gz, g, Gy, l).K
+            K2 = O.LineFactors(P2, Gz, g, Gy, l).K
+            meets = zw0 <= box[5] and zw1 >= box[4] and yw0 <= box[3] and yw1 >= box[2]
+            same = (K1 != K2).nnz == 0
+            assert same != meets, (g, l, meets)
+            changed += meets
+    assert 0 < changed < len(Gz) * len(Gy)
