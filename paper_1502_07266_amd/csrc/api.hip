@@ -12,8 +12,7 @@
 namespace {
 thread_local std::string g_last_error;
 
-constexpr int kBlockLimit = 64;          // largest block B of the two-chain sweep shapes
-constexpr int kBlockLimitOne = 128;      // ... of the one-chain shapes (lines on a middle group)
+constexpr int kBlockLimitOne = 128;      // largest block of the one-chain sweep shapes
 constexpr size_t kSetupLds = 144 * 1024; // dynamic LDS of the setup (one B x B block at least)
 constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
 constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
@@ -34,11 +33,10 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
   int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
-  if (plan.maxB_front > kBlockLimit)
-    return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 64");
   if (plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
-    return fail(HELM_EINVAL, "block size of a line on a middle group (two fronts) exceeds 128 "
-                             "(complex64) or 96 (complex128)");
+    return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 128 (complex64) "
+                             "or 96 (complex128) on a line solved by one chain (a middle group, or "
+                             "every line when some block exceeds 64)");
   if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
     return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
   for (int B : {plan.maxB_front, plan.maxB_mid})

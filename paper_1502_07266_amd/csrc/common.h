@@ -80,6 +80,9 @@ struct LdsLayout {
   }
 };
 
+// largest block of the two-chain sweep shapes (two chains of B rows x NC lanes per workgroup)
+constexpr int kTwoChainMaxB = 64;
+
 // ---------------------------------------------------------------------------------------
 // partition of an axis into groups and their auxiliary windows
 // ---------------------------------------------------------------------------------------
@@ -103,13 +106,15 @@ struct Plan {
   long long total_elems = 0;          // sum over lines of n * B^2
   int maxB = 0, maxW = 0;             // over all lines / windows
   int maxB_front = 0, maxB_mid = 0;   // largest block of the two-chain / one-chain lines
+  bool all_one = false;               // some line off the middle groups has a block above
+                                      // kTwoChainMaxB: every line is solved by one chain
   const GroupInfo& zg(int g) const { return groups[g]; }
   const GroupInfo& yg(int l) const { return groups[Gz + l]; }
   // lines on a middle group (x3 with two fronts, x2 with two inner fronts) have moving PML on
   // both sides of that group and blocks too large for two chains per workgroup: they are
   // eliminated in x1 order and solved by one chain spanning the workgroup (see the sweep)
   bool one_chain(int g, int l) const {
-    return (fronts == 2 && g == zmid) || (fronts_inner == 2 && l == ymid);
+    return all_one || (fronts == 2 && g == zmid) || (fronts_inner == 2 && l == ymid);
   }
   // middle block of line (g, l)'s elimination order: both ends towards n/2, or n - 1 (x1 order)
   int line_mid(int g, int l) const { return one_chain(g, l) ? n - 1 : n / 2; }

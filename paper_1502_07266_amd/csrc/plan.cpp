@@ -13,7 +13,9 @@
 // not padded.  x3 (outer sweep) and x2 (inner sweep) choose independently.
 //
 // Line problem (g, l) pairs x3-group g with x2-group l; its grid is x1 = 1..n times the two
-// windows, so its blocks have B = W_l * W_g unknowns.  Factors are stored line after line
+// windows, so its blocks have B = W_l * W_g unknowns.  Lines on a middle group are solved by
+// one chain; when a line off the middle groups has more than kTwoChainMaxB unknowns per block
+// (wide windows, e.g. the paper's own d = 4, p = 5, b = 9), every line is.  Factors are stored line after line
 // (g major, l minor), each line's n blocks contiguous, each block B*B row-major.
 #include "common.h"
 
@@ -98,6 +100,13 @@ int build_plan(int n, int b, int p, int d, int fronts, int fronts_inner, Plan& p
       plan.line_B[(size_t)g * plan.Gy + l] = B;
       off += (long long)n * B * B;
       if (B > plan.maxB) plan.maxB = B;
+      if (!plan.one_chain(g, l) && B > kTwoChainMaxB) plan.all_one = true;
+    }
+  }
+  // blocks of the two-chain lines and of the one-chain lines (all of them with all_one)
+  for (int g = 0; g < plan.Gz; ++g) {
+    for (int l = 0; l < plan.Gy; ++l) {
+      const int B = plan.line_B[(size_t)g * plan.Gy + l];
       if (plan.one_chain(g, l)) {
         if (B > plan.maxB_mid) plan.maxB_mid = B;
       } else if (B > plan.maxB_front) {

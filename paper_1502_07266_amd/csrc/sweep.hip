@@ -47,7 +47,7 @@ namespace {
 
 struct SweepArgs {
   int n, Gz, Gy, maxW, maxB;
-  int fronts, zmid, fronts_inner, ymid;
+  int fronts, zmid, fronts_inner, ymid, all_one;
   int pass;              // outer pass over the x3-groups (sweep_count / sweep_at)
   int nfront;            // outer fronts in this launch: workgroups per right-hand side (1, 2)
   int slab_lo, slab_hi;  // the range of the pass's slabs this launch handles
@@ -411,7 +411,8 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
         const GroupInfo gy = a.groups[Gz + l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
         const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
-        const bool one = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
+        const bool one =
+            a.all_one || (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
         // the host launches lines on a middle group with one chain and all others with two;
         // a mismatch would overrun the step table, so such a line is left alone
         if (one != (CH == 1)) continue;
@@ -508,7 +509,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_line_solve(Swee
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
   LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
-  const bool one = (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
+  const bool one = a.all_one || (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
   if (one != (CH == 1)) return;   // the host picks the chain count from the line
   ls.begin_line(T, B, n, one ? n - 1 : n / 2);
   ls.fill();
@@ -569,10 +570,11 @@ hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Arg
 // one chain spanning the workgroup (lines on a middle group, blocks up to 128): 8 lanes per
 // row
 #define HELM_SHAPES_ONE(X) \
-  X(8, 3, 16, 12) X(8, 6, 8, 6) X(8, 9, 4, 2) X(8, 10, 4, 2) X(8, 12, 2, 2) X(8, 16, 2, 0)
+  X(8, 3, 16, 12) X(8, 6, 8, 6) X(8, 9, 4, 2) X(8, 10, 4, 2) X(8, 11, 4, 2) X(8, 12, 2, 2)    \
+  X(8, 16, 2, 0)
 
 Shape choose_shape_one(int maxB) {
-  static const int cw[] = {3, 6, 9, 10, 12, 16};
+  static const int cw[] = {3, 6, 9, 10, 11, 12, 16};
   for (int c : cw)
     if (8 * c >= maxB) return {8, c};
   return {8, -1};
@@ -653,6 +655,7 @@ SweepArgs base_args(helm_handle* h) {
   a.zmid = P.zmid;
   a.fronts_inner = P.fronts_inner;
   a.ymid = P.ymid;
+  a.all_one = P.all_one;
   a.pass = 0;
   a.nfront = 1;
   a.slab_lo = 0;
@@ -723,7 +726,9 @@ hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStrea
 //   forward (two workgroups per outer front), the middle line (one chain), both inner fronts
 //   backward; the launch boundaries order them.  On the two-front middle slab every line has
 //   one chain.
-// Each launch's block bound is the largest block among the lines it solves.
+// Each launch's block bound is the largest block among the lines it solves.  The timed
+// (dominant) launches are those over the front slabs' lines off the middle x2-group: two
+// chains, or one with all_one.
 std::vector<SweepLaunch> sweep_schedule(const Plan& P) {
   std::vector<SweepLaunch> out;
   struct Outer {
@@ -736,7 +741,7 @@ std::vector<SweepLaunch> sweep_schedule(const Plan& P) {
   for (const Outer& o : outer) {
     const bool mid_slab = o.pass == 2;
     if (P.fronts_inner == 1) {
-      SweepLaunch L{o.pass, o.nfront, 0, 1 << 30, 0, 1, mid_slab ? 1 : 2, 0, !mid_slab};
+      SweepLaunch L{o.pass, o.nfront, 0, 1 << 30, 0, 1, (mid_slab || P.all_one) ? 1 : 2, 0, !mid_slab};
       int mb = 0;
       for (int g = 0; g < P.Gz; ++g)
         if ((P.fronts == 2 && g == P.zmid) == mid_slab)
@@ -758,8 +763,8 @@ std::vector<SweepLaunch> sweep_schedule(const Plan& P) {
             for (int k = 0; k < sweep_count(ip, P.Gy, P.ymid, inf); ++k)
               mb = std::max(mb, line_B(g, sweep_at(ip, P.Gy, P.ymid, inf, k).x));
         }
-        const int chains = (mid_slab || ip == 2) ? 1 : 2;
-        out.push_back(SweepLaunch{o.pass, o.nfront, si, si + 1, ip, ninner, chains, mb, chains == 2});
+        const int chains = (mid_slab || ip == 2 || P.all_one) ? 1 : 2;
+        out.push_back(SweepLaunch{o.pass, o.nfront, si, si + 1, ip, ninner, chains, mb, !mid_slab && ip != 2});
       }
     }
   }

@@ -34,11 +34,35 @@ def medium_constant(n, c0=1.0):
     return np.full((n, n, n), float(c0))
 
 
-def medium_lens(n):
-    """Gaussian low-velocity lens c = 1 - 0.4 exp(-|x - 0.5|^2 / 0.02) at the nodes."""
+def medium_lens(n, amplitude=-0.4):
+    """Gaussian lens c = 1 + amplitude exp(-|x - 0.5|^2 / 0.02) at the nodes (low-velocity
+    for amplitude < 0)."""
     X1, X2, X3 = _coords(n)
     r2 = (X1 - 0.5) ** 2 + (X2 - 0.5) ** 2 + (X3 - 0.5) ** 2
-    return 1.0 - 0.4 * np.exp(-r2 / 0.02)
+    return 1.0 + amplitude * np.exp(-r2 / 0.02)
+
+
+def medium_waveguide(n, amplitude=-0.4):
+    """Vertical Gaussian waveguide, constant along x3:
+    c = 1 + amplitude exp(-((x1 - 0.5)^2 + (x2 - 0.5)^2) / 0.02)."""
+    X1, X2, _ = _coords(n)
+    return 1.0 + amplitude * np.exp(-((X1 - 0.5) ** 2 + (X2 - 0.5) ** 2) / 0.02)
+
+
+def force_gaussian(n, center, sigma):
+    """Smooth point-like source exp(-|x - center|^2 / (2 sigma^2)) at the nodes (complex128)."""
+    X1, X2, X3 = _coords(n)
+    r2 = (X1 - center[0]) ** 2 + (X2 - center[1]) ** 2 + (X3 - center[2]) ** 2
+    return np.exp(-r2 / (2.0 * sigma ** 2)).astype(np.complex128)
+
+
+def force_wave_packet(n, center, direction, omega, sigma):
+    """Gaussian wave packet exp(-|x - center|^2 / (2 sigma^2)) exp(i omega direction . x):
+    a plane wave of wavelength 2 pi / omega (that of c = 1) travelling along `direction`."""
+    X1, X2, X3 = _coords(n)
+    r2 = (X1 - center[0]) ** 2 + (X2 - center[1]) ** 2 + (X3 - center[2]) ** 2
+    phase = omega * (direction[0] * X1 + direction[1] * X2 + direction[2] * X3)
+    return np.exp(-r2 / (2.0 * sigma ** 2)) * np.exp(1j * phase)
 
 
 def medium_grf(n, corr_len, lo, hi, seed=SEED_MEDIUM):

@@ -54,7 +54,7 @@ def test_plan_bytes_matches_factor_layout():
     (31, 6, 180.0, 7, 1),     # p > b
     (31, 6, 180.0, 6, 0),     # d < 1
     (31, 6, -1.0, 6, 1),      # C <= 0
-    (31, 6, 180.0, 6, 3),     # block (p+d)^2 = 81 > 64
+    (31, 6, 180.0, 6, 6),     # block (p+d)^2 = 144 > 128
 ])
 def test_invalid_parameters_rejected(args):
     with pytest.raises(binding.HelmError) as e:
@@ -69,3 +69,14 @@ def test_null_handle_rejected():
     assert L.helm_set_launch(None, 8) == binding.HELM_EINVAL
     assert L.helm_update_medium(None, None, None, None, None) == binding.HELM_EINVAL
     L.helm_destroy(None)
+
+
+def test_wide_windows_are_solved_by_one_chain():
+    """A block above 64 unknowns off the middle groups switches every line to one chain:
+    blocks up to 128 (complex64) or 96 (complex128) are accepted."""
+    _, nlines, maxb = binding.plan_bytes(31, 6, 180.0, 6, 3, binding.HELM_C64)
+    assert maxb == 81
+    _, _, maxb = binding.plan_bytes(31, 6, 180.0, 6, 3, binding.HELM_C128)
+    assert maxb == 81
+    with pytest.raises(binding.HelmError):
+        binding.plan_bytes(31, 6, 180.0, 6, 5, binding.HELM_C128)     # 11 x 11 = 121 > 96

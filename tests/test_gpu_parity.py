@@ -39,6 +39,10 @@ CASES = {
     "ragged_2f2i": dict(n=17, b=3, p=2, d=2, fronts=2, fronts_inner=2),
     "tiny3_2f2i": dict(n=3, b=1, p=1, d=1, fronts=2, fronts_inner=2),
     "tiny4_1f2i": dict(n=4, b=1, p=1, d=1, fronts=1, fronts_inner=2),
+    # wide windows (9 x 9 = 81 > 64 unknowns per block off the middle groups, as with the
+    # paper's own b = 9, p = 5, d = 4): every line in x1 order, solved by one chain
+    "wide_2f": dict(n=16, b=3, p=3, d=6, fronts=2),
+    "wide_1f": dict(n=16, b=3, p=3, d=6),
 }
 _cache = {}
 
@@ -62,9 +66,12 @@ def helm(name, prec):
 
 
 def on_middle_group(prob, M, g, l):
-    """Lines on a middle group are factored in x1 order, all others from both ends."""
-    return ((prob.fronts == 2 and g == len(M.Gz) // 2)
-            or (prob.fronts_inner == 2 and l == len(M.Gy) // 2))
+    """Lines on a middle group are factored in x1 order, all others from both ends, unless a
+    block off the middle groups exceeds 64 unknowns: then every line is in x1 order."""
+    mid = lambda g_, l_: ((prob.fronts == 2 and g_ == len(M.Gz) // 2)
+                          or (prob.fronts_inner == 2 and l_ == len(M.Gy) // 2))
+    wide = any(not mid(g_, l_) and ln.B > 64 for g_, l_, ln in M.lines())
+    return wide or mid(g, l)
 
 
 def rel(a, b):
