@@ -17,12 +17,14 @@ class HelmMisfit(torch.autograd.Function):
 
     c: float64 CUDA tensor (n, n, n); sources: complex128 (S, n, n, n); d_obs: complex128
     (S, n, n) data on the x3-layer plane_k (1-based).  Returns a float64 scalar tensor.
+    params may also hold fronts and fronts_inner (the preconditioner's sweep directions).
     """
 
     @staticmethod
     def forward(ctx, c, sources, d_obs, plane_k, params):
         H = Helm(c.detach(), params["omega"], params["b"], params["C"], params["p"],
-                 params.get("slab_layers", 1), prec=params.get("prec", "c64"))
+                 params.get("slab_layers", 1), prec=params.get("prec", "c64"),
+                 fronts=params.get("fronts", 1), fronts_inner=params.get("fronts_inner", 1))
         tol = params.get("tol", 1e-8)
         restart = params.get("restart", 50)
         maxit = params.get("maxit", 500)

@@ -212,3 +212,16 @@ def test_c3_two_fronts_both_axes():
     print(f"c3 2f2i complex64 sweep: dot test {dot_err:.2e}, linearity {lin_err:.2e}")
     assert dot_err <= 1e-4
     assert lin_err <= 1e-4
+
+
+def test_c4_gradient_against_central_differences():
+    """63^3 adjoint-gradient workload at full size: dJ/dc from one forward and one adjoint
+    solve against central differences (step 1e-4) of J at 3 of the seeded cells, every J
+    from FGMRES to 1e-12 (the full 20-cell check is python -m
+    paper_1502_07266_amd.gradient_check)."""
+    from paper_1502_07266_amd.gradient_check import run
+    summary, rows = run(cells=3, tol=1e-12)
+    for r in rows:
+        print(f"c4 cell {r['cell']}: adjoint {r['adjoint']:.6e}, central difference "
+              f"{r['central_difference']:.6e}, rel err {r['rel_err']:.2e}")
+    assert summary["max_rel_err"] <= 1e-4
