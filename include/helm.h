@@ -80,11 +80,11 @@ typedef struct {
  * shorter) and nodes n-b+1..n; with G of them the middle one is group G/2; groups below it
  * are padded below as above, groups above it padded above with the mirror image (plane p+1
  * spacings above the group), the middle group on both sides, and the first and last groups
- * not at all.  Line blocks have B = (x2 window) x (x3 window) unknowns.  Lines off the
- * middle groups are solved by two chains from the line's ends when every such block has
- * B <= 64; lines on a middle group, and every line when some block off the middle groups
- * exceeds 64, by one chain in x1 order (helm_line_factors).  One-chain blocks are limited to
- * B <= 128 (complex64) or 96 (complex128), and n*B line values must fit in LDS.
+ * not at all.  Line blocks have B = (x2 window) x (x3 window) unknowns.  The sweep solves
+ * the lines of one launch by two chains from the lines' ends when every block of the launch
+ * has B <= 64, else by one chain in x1 order
+ * (helm_line_factors).  One-chain blocks are limited to B <= 128 (complex64) or 96
+ * (complex128), and n*B line values must fit in LDS.
  * Errors: HELM_EINVAL, HELM_ENOMEM (factor bytes > free memory), HELM_ESINGULAR, HELM_EHIP.
  * Synchronises `stream`.
  */
@@ -201,15 +201,15 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
  * ends towards the middle block m (0-based): block i < m holds the inverse Schur complement
  * after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks i+1..n-1, and
  * block m the one after all others, which equals the (m, m) block of the line matrix's
- * inverse.  m = n/2 (integer division), except for the lines solved by one chain (on the
- * middle x3-group with two fronts or the middle x2-group with two inner fronts, or every
- * line when a block off the middle groups exceeds 64 unknowns), where m = n-1 (the x1 order
- * of Sec. 3).  The solve is exact for any such order.
+ * inverse.  m = n/2 (integer division), except for the lines the sweep solves with one
+ * chain, where m = n-1 (the x1 order of Sec. 3): the lines of every sweep launch that holds
+ * a block above 64 unknowns, e.g. the lines on the middle groups of two fronts at 127^3.  The solve is exact for any such order.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
- * *B_out receives B (may be NULL).  Pass dst_dev = NULL to query B only.
+ * *B_out receives B and *mid_out m (either may be NULL).  Pass dst_dev = NULL to query them
+ * only.
  */
 int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* B_out,
-                      void* stream);
+                      int* mid_out, void* stream);
 
 /*
  * helm_line_solve -- x = K^{-1} r (adjoint = 0) or K^{-H} r (adjoint = 1) for the line

@@ -52,7 +52,7 @@ _SIGS = {
     "helm_info": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "helm_plan_bytes": (_I, [ctypes.POINTER(helm_grid), ctypes.POINTER(helm_pml), _I, _I,
                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
-    "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), _P]),
+    "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
     "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
@@ -234,13 +234,21 @@ class Helm:
         """The block inverses T_1..T_n of line (zg, yg): tensor (n, B, B)."""
         import torch
         B = _I()
-        _check(lib().helm_line_factors(self.handle, zg, yg, None, ctypes.byref(B), _stream()),
+        _check(lib().helm_line_factors(self.handle, zg, yg, None, ctypes.byref(B), None, _stream()),
                "helm_line_factors")
         dt = torch.complex64 if self.prec == HELM_C64 else torch.complex128
         out = torch.empty((self.n, B.value, B.value), dtype=dt, device="cuda")
-        _check(lib().helm_line_factors(self.handle, zg, yg, _ptr(out), None, _stream()),
+        _check(lib().helm_line_factors(self.handle, zg, yg, _ptr(out), None, None, _stream()),
                "helm_line_factors")
         return out
+
+    def line_order(self, zg, yg):
+        """The oracle's name of line (zg, yg)'s elimination order: "two-sided" (both ends
+        towards block n/2) or "up" (x1 order, middle block n - 1)."""
+        m = _I()
+        _check(lib().helm_line_factors(self.handle, zg, yg, None, None, ctypes.byref(m), _stream()),
+               "helm_line_factors")
+        return "up" if m.value == self.n - 1 else "two-sided"
 
     def line_solve(self, zg, yg, r, adjoint=False):
         """x = K^{-1} r on the line grid; r: complex128 (R, Wz, Wy, n)."""

@@ -31,12 +31,12 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   std::string msg;
   const int fronts = pml->fronts == 0 ? 1 : pml->fronts;
   const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
-  int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, plan, msg);
+  int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, prec, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
   if (plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
     return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 128 (complex64) "
-                             "or 96 (complex128) on a line solved by one chain (a middle group, or "
-                             "every line when some block exceeds 64)");
+                             "or 96 (complex128) on a line solved by one chain (a line whose "
+                             "launch holds a block above 64)");
   if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
     return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
   for (int B : {plan.maxB_front, plan.maxB_mid})
@@ -49,7 +49,8 @@ size_t planned_bytes(const Plan& p, int prec) {
   const size_t N = (size_t)p.n * p.n * p.n;
   return ((size_t)p.total_elems + kFactorPad) * csize(prec) + N * sizeof(double) +
          (size_t)(2 * (p.n + 1) + 1 + 2 * p.p + 2 + 5 * (p.n + 2)) * sizeof(double2) +
-         (size_t)(p.Gz + p.Gy) * sizeof(GroupInfo) + (size_t)p.Gz * p.Gy * (sizeof(long long) + sizeof(int));
+         (size_t)(p.Gz + p.Gy) * sizeof(GroupInfo) +
+         (size_t)p.Gz * p.Gy * (sizeof(long long) + sizeof(int) + 1);
 }
 
 // algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
@@ -115,7 +116,8 @@ void release(helm_handle* h) {
   h->t_matvec.reset();
   h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
-                  h->d_setup_lines, h->factors, h->d_err, h->slab_scratch, h->d_rhs_idx};
+                  h->d_setup_lines, h->d_line_one, h->factors, h->d_err, h->slab_scratch,
+                  h->d_rhs_idx};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -193,6 +195,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   ALLOC(h->d_groups, plan.groups.size() * sizeof(GroupInfo));
   ALLOC(h->d_line_off, plan.line_off.size() * sizeof(long long));
   ALLOC(h->d_setup_lines, plan.line_off.size() * sizeof(int));
+  ALLOC(h->d_line_one, plan.one.size());
   // the sweep's row-major block walk may read up to 64 entries past the last block
   ALLOC(h->factors, ((size_t)plan.total_elems + kFactorPad) * csize(prec));
   ALLOC(h->d_err, 2 * sizeof(int));
@@ -208,6 +211,8 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   const std::vector<int> setup_lines = setup_line_order(plan, nullptr);
   if (hipMemcpyAsync(h->d_setup_lines, setup_lines.data(), setup_lines.size() * sizeof(int),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->d_line_one, h->plan.one.data(), h->plan.one.size(), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)   // the host vector goes out of scope
     return bail(HELM_EHIP, "copying the plan failed");
   h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
@@ -374,13 +379,14 @@ int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max
 }
 
 int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* B_out,
-                      void* stream) {
+                      int* mid_out, void* stream) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
   if (zg < 0 || zg >= h->plan.Gz || yg < 0 || yg >= h->plan.Gy)
     return fail(HELM_EINVAL, "group index out of range");
   const size_t line = (size_t)zg * h->plan.Gy + yg;
   const int B = h->plan.line_B[line];
   if (B_out) *B_out = B;
+  if (mid_out) *mid_out = h->plan.line_mid(zg, yg);
   if (!dst_dev) return HELM_OK;
   const size_t cs = csize(h->prec);
   HIP_TRY(hipMemcpyAsync(dst_dev, (const char*)h->factors + (size_t)h->plan.line_off[line] * cs,

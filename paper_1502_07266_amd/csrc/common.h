@@ -80,8 +80,12 @@ struct LdsLayout {
   }
 };
 
-// largest block of the two-chain sweep shapes (two chains of B rows x NC lanes per workgroup)
-constexpr int kTwoChainMaxB = 64;
+// largest block of the two-chain sweep shapes (two chains of B rows x NC lanes per workgroup):
+// 8 x 8 or 4 x 16.  (A 4 x 20 shape for blocks up to 80 was measured: at 640 threads it
+// spills registers and keeps a ring of only 2 blocks, and its lines took as long as one
+// chain over twice the steps.)
+constexpr int kTwoChainMaxB64 = 64;
+constexpr int kTwoChainMaxB128 = 64;
 
 // ---------------------------------------------------------------------------------------
 // partition of an axis into groups and their auxiliary windows
@@ -106,22 +110,19 @@ struct Plan {
   long long total_elems = 0;          // sum over lines of n * B^2
   int maxB = 0, maxW = 0;             // over all lines / windows
   int maxB_front = 0, maxB_mid = 0;   // largest block of the two-chain / one-chain lines
-  bool all_one = false;               // some line off the middle groups has a block above
-                                      // kTwoChainMaxB: every line is solved by one chain
+  int two_cap = 0;                    // largest block two chains per workgroup can solve
+  std::vector<unsigned char> one;     // [Gz*Gy] line solved by one chain (see build_plan)
   const GroupInfo& zg(int g) const { return groups[g]; }
   const GroupInfo& yg(int l) const { return groups[Gz + l]; }
-  // lines on a middle group (x3 with two fronts, x2 with two inner fronts) have moving PML on
-  // both sides of that group and blocks too large for two chains per workgroup: they are
-  // eliminated in x1 order and solved by one chain spanning the workgroup (see the sweep)
-  bool one_chain(int g, int l) const {
-    return all_one || (fronts == 2 && g == zmid) || (fronts_inner == 2 && l == ymid);
-  }
+  // lines whose launch holds a block too large for two chains per workgroup are eliminated
+  // in x1 order and solved by one chain spanning the workgroup (see build_plan)
+  bool one_chain(int g, int l) const { return one[(size_t)g * Gy + l] != 0; }
   // middle block of line (g, l)'s elimination order: both ends towards n/2, or n - 1 (x1 order)
   int line_mid(int g, int l) const { return one_chain(g, l) ? n - 1 : n / 2; }
 };
 
 // builds the plan; returns HELM_OK or HELM_EINVAL (with a message)
-int build_plan(int n, int b, int p, int d, int fronts, int fronts_inner, Plan& plan,
+int build_plan(int n, int b, int p, int d, int fronts, int fronts_inner, int prec, Plan& plan,
                std::string& msg);
 
 // what a workgroup does with one group (an x3-group of the outer sweep or an x2-group of the
@@ -227,6 +228,7 @@ struct helm_handle {
   double2* coef = nullptr;         // [4][n+2]: A[m,m-1], A[m,m+1], A^H[m,m-1], A^H[m,m+1]
   double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
   GroupInfo* d_groups = nullptr;   // [Gz + Gy]
+  unsigned char* d_line_one = nullptr;   // [Gz*Gy] Plan::one
   int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_line_order
   long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128

@@ -31,9 +31,10 @@ constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may tak
 
 struct SetupArgs {
   int n, Gz, Gy, p;
-  int fronts, zmid, fronts_inner, ymid, all_one;
+  int fronts, zmid, fronts_inner, ymid;
   int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
   const int* lines;  // the lines of this launch (workgroup w takes line lines[w])
+  const unsigned char* line_one;   // per line: solved by one chain (x1 order)
   double h;
   const GroupInfo* groups;
   const long long* line_off;
@@ -86,13 +87,11 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
 
   // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
   // middle block m last, whose Schur complement takes the update from both sides; m = n/2
-  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines on a middle group
-  // (x3 with two fronts, x2 with two inner fronts).  It is the block LDU of Sec. 3 with the
+  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines the sweep solves with
+  // one chain (blocks too large for two chains).  It is the block LDU of Sec. 3 with the
   // blocks in that order (every block eliminated is an end of the remaining chain, so there
   // is no fill); the sweep runs the two halves of each line solve as two concurrent chains.
-  const bool one_chain =
-      a.all_one || (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
-  const int mid = one_chain ? n - 1 : n / 2;
+  const int mid = a.line_one[line] ? n - 1 : n / 2;
   // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
   C* Tlds = S + B * B;
   const C* Tprev = Tlds;
@@ -276,7 +275,7 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, i
   a.zmid = P.zmid;
   a.fronts_inner = P.fronts_inner;
   a.ymid = P.ymid;
-  a.all_one = P.all_one;
+  a.line_one = h->d_line_one;
   a.h = h->h;
   a.groups = h->d_groups;
   a.line_off = h->d_line_off;

@@ -47,7 +47,7 @@ namespace {
 
 struct SweepArgs {
   int n, Gz, Gy, maxW, maxB;
-  int fronts, zmid, fronts_inner, ymid, all_one;
+  int fronts, zmid, fronts_inner, ymid;
   int pass;              // outer pass over the x3-groups (sweep_count / sweep_at)
   int nfront;            // outer fronts in this launch: workgroups per right-hand side (1, 2)
   int slab_lo, slab_hi;  // the range of the pass's slabs this launch handles
@@ -203,16 +203,29 @@ struct LineSolver {
     }
   }
 
-  // row sum of ring[S] . z over this thread's columns, reduced over the row's NC lanes (one
-  // accumulator: a wave issues an instruction only every few cycles, which already covers the
-  // FMA latency)
+  // row sum of ring[S] . z over this thread's columns, reduced over the row's NC lanes; even
+  // and odd columns go to two accumulators, which halves the dependent FMA chain of the wide
+  // shapes
+  template <int S> __device__ __forceinline__ C first(int cc, const C (&zr)[CW]) const {
+    return ADJ ? mk(ring[S][cc].x * zr[cc].x + ring[S][cc].y * zr[cc].y,
+                    ring[S][cc].x * zr[cc].y - ring[S][cc].y * zr[cc].x)
+               : cmul(ring[S][cc], zr[cc]);
+  }
   template <int S> __device__ __forceinline__ C dot(const C (&zr)[CW]) const {
-    C acc = ADJ ? mk(ring[S][0].x * zr[0].x + ring[S][0].y * zr[0].y,
-                     ring[S][0].x * zr[0].y - ring[S][0].y * zr[0].x)
-                : cmul(ring[S][0], zr[0]);
+    C acc = first<S>(0, zr);
+    if constexpr (CW >= 4) {
+      C acc1 = first<S>(1, zr);
 #pragma unroll
-    for (int cc = 1; cc < CW; ++cc)
-      acc = ADJ ? cfma_conj(acc, ring[S][cc], zr[cc]) : cfma(acc, ring[S][cc], zr[cc]);
+      for (int cc = 2; cc < CW; ++cc) {
+        C& a = (cc & 1) ? acc1 : acc;
+        a = ADJ ? cfma_conj(a, ring[S][cc], zr[cc]) : cfma(a, ring[S][cc], zr[cc]);
+      }
+      acc = cadd(acc, acc1);
+    } else {
+#pragma unroll
+      for (int cc = 1; cc < CW; ++cc)
+        acc = ADJ ? cfma_conj(acc, ring[S][cc], zr[cc]) : cfma(acc, ring[S][cc], zr[cc]);
+    }
     acc.x = lane_sum<NC>(acc.x);
     acc.y = lane_sum<NC>(acc.y);
     return acc;
@@ -411,12 +424,9 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
         const GroupInfo gy = a.groups[Gz + l];
         const int Wy = gy.W, B = Wy * Wz, j0 = gy.first, j1 = gy.last, yw0 = gy.w0;
         const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
-        const bool one =
-            a.all_one || (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
-        // the host launches lines on a middle group with one chain and all others with two;
-        // a mismatch would overrun the step table, so such a line is left alone
-        if (one != (CH == 1)) continue;
-        ls.begin_line(T, B, n, one ? n - 1 : n / 2);
+        // every line of a launch has the elimination order of the launch's chain count (the
+        // plan makes the lines of a launch agree): x1 order with one chain, two-sided with two
+        ls.begin_line(T, B, n, CH == 1 ? n - 1 : n / 2);
         ls.fill();   // in flight while the line input is gathered
         for (int e = tid; e < n * B; e += NT) {
           const int qq = e / n, i = e - qq * n;
@@ -509,9 +519,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_line_solve(Swee
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
   LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
-  const bool one = a.all_one || (a.fronts == 2 && g == a.zmid) || (a.fronts_inner == 2 && l == a.ymid);
-  if (one != (CH == 1)) return;   // the host picks the chain count from the line
-  ls.begin_line(T, B, n, one ? n - 1 : n / 2);
+  ls.begin_line(T, B, n, CH == 1 ? n - 1 : n / 2);   // the host picks CH from the line
   ls.fill();
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
     const int i = e % n, jj = (e / n) % Wy, kk = e / (n * Wy);
@@ -533,13 +541,37 @@ struct Shape {
   int nc, cw;
 };
 
+// the instantiated shapes: (NC, CW, ring depth for complex64, ring depth for complex128),
+// depths sized so that the ring fits the register budget of the shape's largest launch; depth
+// 0: not built (complex128 with 8 x 7 or 8 x 8 columns leaves no registers for a ring)
+#define HELM_SHAPES(X)                                                                  \
+  X(4, 5, 16, 12) X(4, 7, 16, 12) X(4, 9, 8, 4) X(4, 13, 6, 2) X(4, 16, 4, 2)          \
+  X(8, 3, 16, 12) X(8, 4, 16, 10) X(8, 5, 8, 4) X(8, 7, 4, 0) X(8, 8, 2, 0)            \
+  X(16, 1, 16, 16) X(16, 2, 16, 8)
+// the shape is instantiated for this precision
+bool shape_built(Shape sh, bool c64) {
+#define X(NC, CW, D64, D128) \
+  if (sh.nc == NC && sh.cw == CW) return (c64 ? D64 : D128) > 0;
+  HELM_SHAPES(X)
+#undef X
+  return false;
+}
+
 Shape choose_shape(int maxB, int lanes, bool c64) {
   // default: 8 lanes per block row (measured fastest for two chains at B = 36, 49 and 64 in
   // complex64, although 8 x 7 and 8 x 8 columns leave registers for a ring of only 4 and 2
   // blocks; in complex128 they leave none, so 4 lanes beyond B = 40); 16 lanes only fit two
   // chains in one workgroup up to B = 32.  CW is the smallest instantiated column count
   // covering B.
+  if (maxB > kTwoChainMaxB64) return Shape{4, -1};
   const int nc = lanes ? lanes : ((c64 || maxB <= 40) ? 8 : 4);
+  if (lanes) {   // an override without a shape for this block and precision: automatic
+    const Shape sh = choose_shape(maxB, 0, c64);
+    const int need = (maxB + nc - 1) / nc;
+    for (int cw = need; cw <= 20; ++cw)
+      if (shape_built(Shape{nc, cw}, c64)) return Shape{nc, cw};
+    return sh;
+  }
   const int need = (maxB + nc - 1) / nc;
   static const int cw4[] = {5, 7, 9, 13, 16}, cw8[] = {3, 4, 5, 7, 8}, cw16[] = {1, 2};
   const int* t = nc == 4 ? cw4 : (nc == 8 ? cw8 : cw16);
@@ -560,13 +592,6 @@ hipError_t launch_k(K kern, int grid, int threads, size_t sm, hipStream_t s, Arg
   return hipGetLastError();
 }
 
-// the instantiated shapes: (NC, CW, ring depth for complex64, ring depth for complex128),
-// depths sized so that the ring fits the register budget of the shape's largest launch; depth
-// 0: not built (complex128 with 8 x 7 or 8 x 8 columns leaves no registers for a ring)
-#define HELM_SHAPES(X)                                                                  \
-  X(4, 5, 16, 12) X(4, 7, 16, 12) X(4, 9, 8, 4) X(4, 13, 6, 2) X(4, 16, 4, 2)          \
-  X(8, 3, 16, 12) X(8, 4, 16, 10) X(8, 5, 8, 4) X(8, 7, 4, 0) X(8, 8, 2, 0)            \
-  X(16, 1, 16, 16) X(16, 2, 16, 8)
 // one chain spanning the workgroup (lines on a middle group, blocks up to 128): 8 lanes per
 // row
 #define HELM_SHAPES_ONE(X) \
@@ -655,7 +680,6 @@ SweepArgs base_args(helm_handle* h) {
   a.zmid = P.zmid;
   a.fronts_inner = P.fronts_inner;
   a.ymid = P.ymid;
-  a.all_one = P.all_one;
   a.pass = 0;
   a.nfront = 1;
   a.slab_lo = 0;
@@ -718,58 +742,6 @@ hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStrea
 
 }  // namespace
 
-// The launches of one sweep, in order.
-//   One inner front: one launch per outer pass, every workgroup sweeping its slabs and, in
-//   each, all lines (pass 0 with one front; passes 1, 2, 3 with two, the middle slab with one
-//   chain).
-//   Two inner fronts: per slab step of each outer pass, three launches: both inner fronts
-//   forward (two workgroups per outer front), the middle line (one chain), both inner fronts
-//   backward; the launch boundaries order them.  On the two-front middle slab every line has
-//   one chain.
-// Each launch's block bound is the largest block among the lines it solves.  The timed
-// (dominant) launches are those over the front slabs' lines off the middle x2-group: two
-// chains, or one with all_one.
-std::vector<SweepLaunch> sweep_schedule(const Plan& P) {
-  std::vector<SweepLaunch> out;
-  struct Outer {
-    int pass, nfront;
-  };
-  std::vector<Outer> outer;
-  if (P.fronts == 1) outer.push_back({0, 1});
-  else outer = {{1, 2}, {2, 1}, {3, 2}};
-  auto line_B = [&](int g, int l) { return P.line_B[(size_t)g * P.Gy + l]; };
-  for (const Outer& o : outer) {
-    const bool mid_slab = o.pass == 2;
-    if (P.fronts_inner == 1) {
-      SweepLaunch L{o.pass, o.nfront, 0, 1 << 30, 0, 1, (mid_slab || P.all_one) ? 1 : 2, 0, !mid_slab};
-      int mb = 0;
-      for (int g = 0; g < P.Gz; ++g)
-        if ((P.fronts == 2 && g == P.zmid) == mid_slab)
-          for (int l = 0; l < P.Gy; ++l) mb = std::max(mb, line_B(g, l));
-      L.maxB = mb;
-      out.push_back(L);
-      continue;
-    }
-    int steps = 0;
-    for (int fr = 0; fr < o.nfront; ++fr) steps = std::max(steps, sweep_count(o.pass, P.Gz, P.zmid, fr));
-    for (int si = 0; si < steps; ++si) {
-      for (int ip : {1, 2, 3}) {
-        const int ninner = ip == 2 ? 1 : 2;
-        int mb = 0;
-        for (int fr = 0; fr < o.nfront; ++fr) {
-          if (si >= sweep_count(o.pass, P.Gz, P.zmid, fr)) continue;
-          const int g = sweep_at(o.pass, P.Gz, P.zmid, fr, si).x;
-          for (int inf = 0; inf < ninner; ++inf)
-            for (int k = 0; k < sweep_count(ip, P.Gy, P.ymid, inf); ++k)
-              mb = std::max(mb, line_B(g, sweep_at(ip, P.Gy, P.ymid, inf, k).x));
-        }
-        const int chains = (mid_slab || ip == 2 || P.all_one) ? 1 : 2;
-        out.push_back(SweepLaunch{o.pass, o.nfront, si, si + 1, ip, ninner, chains, mb, !mid_slab && ip != 2});
-      }
-    }
-  }
-  return out;
-}
 
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,

@@ -180,7 +180,7 @@ def test_c3_sweep_dot_test_and_linearity(c3_handles):
 
 def test_c3_two_fronts_both_axes():
     """127^3, complex64, two fronts in x3 and in x2 (the launch configuration the benchmark
-    times): sampled line factors, including lines on the middle x2-group (blocks 11 x 6 = 66)
+    times): sampled line factors, including lines on the middle x2-group (blocks 11 x 7 = 77)
     and the middle-middle line (11 x 11 = 121), against the oracle's; the adjoint dot test
     and linearity of the whole sweep."""
     from paper_1502_07266_amd.binding import Helm
@@ -193,8 +193,8 @@ def test_c3_two_fronts_both_axes():
     H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64",
              fronts=2, fronts_inner=2)
     for (g, l) in [(0, 0), (mid - 1, mid), (mid, mid), (mid + 3, mid - 1), (len(Gt) - 1, mid + 1)]:
-        one = g == mid or l == mid
-        ln = O.LineFactors(prob, Gt, g, Gt, l, order="up" if one else "two-sided")
+        ln = O.LineFactors(prob, Gt, g, Gt, l, order=H.line_order(g, l))
+        assert (H.line_order(g, l) == "up") == (ln.B > 64), (g, l, ln.B)
         ref = np.stack(ln.block_T)
         T = H.line_factors(g, l).cpu().numpy()
         err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))

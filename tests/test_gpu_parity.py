@@ -43,6 +43,9 @@ CASES = {
     # paper's own b = 9, p = 5, d = 4): every line in x1 order, solved by one chain
     "wide_2f": dict(n=16, b=3, p=3, d=6, fronts=2),
     "wide_1f": dict(n=16, b=3, p=3, d=6),
+    # the middle slab's lines have 11 x 4 = 44 and 11 x 7 = 77 unknowns per block: the launch
+    # holds a block above two chains' capacity, so all of them take one chain
+    "mid77_2f": dict(n=19, b=4, p=4, d=3, fronts=2),
 }
 _cache = {}
 
@@ -65,13 +68,7 @@ def helm(name, prec):
                 fronts_inner=prob.fronts_inner)
 
 
-def on_middle_group(prob, M, g, l):
-    """Lines on a middle group are factored in x1 order, all others from both ends, unless a
-    block off the middle groups exceeds 64 unknowns: then every line is in x1 order."""
-    mid = lambda g_, l_: ((prob.fronts == 2 and g_ == len(M.Gz) // 2)
-                          or (prob.fronts_inner == 2 and l_ == len(M.Gy) // 2))
-    wide = any(not mid(g_, l_) and ln.B > 64 for g_, l_, ln in M.lines())
-    return wide or mid(g, l)
+TWO_CHAIN_CAP = {"c64": 64, "c128": 64}
 
 
 def rel(a, b):
@@ -109,10 +106,13 @@ def test_line_factors(name, prec, tol):
     worst = 0.0
     for g, l, ln in M.lines():
         T = H.line_factors(g, l).cpu().numpy()
-        # the library eliminates the x1-blocks from both ends towards the middle, except on a
-        # middle group (x1 order)
-        order = "up" if on_middle_group(prob, M, g, l) else "two-sided"
+        # the library eliminates the x1-blocks from both ends towards the middle, or in x1 order
+        # on the lines it solves with one chain (always those with blocks above two chains'
+        # capacity)
+        order = H.line_order(g, l)
         ln = O.LineFactors(prob, M.Gz, g, M.Gy, l, order=order)
+        if ln.B > TWO_CHAIN_CAP[prec]:
+            assert order == "up", (g, l, ln.B)
         ref = np.stack(ln.block_T)
         assert T.shape == ref.shape
         e = max(rel(T[i], ref[i]) for i in range(prob.n))
