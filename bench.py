@@ -41,7 +41,7 @@ def log(msg):
 def run_step(Helm, c, wl, F, prec, fronts, fronts_inner):
     import torch
     H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts,
-             fronts_inner=fronts_inner)
+             fronts_inner=fronts_inner, C_moving=wl.get("C_moving", 0.0))
     u, its, rel, rc = H.solve(F, tol=wl["tol"], restart=wl["restart"], maxit=wl.get("maxit", 400))
     torch.cuda.synchronize()
     st = H.stats()
@@ -93,7 +93,7 @@ def measured_traffic(workload, wl, fronts, fronts_inner):
         rec = json.load(fh)
     if rec.get("fronts", 1) != fronts or rec.get("fronts_inner", 1) != fronts_inner:
         return None
-    if (rec.get("d"), rec.get("p")) != (wl["d"], wl["p"]):
+    if (rec.get("d"), rec.get("p"), rec.get("C_moving", 0.0)) != (wl["d"], wl["p"], wl.get("C_moving", 0.0)):
         return None
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != rec.get("sweep_source_sha256"):
@@ -115,7 +115,8 @@ def cpu_baseline(wl, iters, budget_s, fronts=1, fronts_inner=1):
     from oracle.partition import groups
 
     with threadpool_limits(limits=1):
-        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"])
+        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                         C_moving=wl.get("C_moving", 0.0))
         Gz = groups(wl["n"], wl["b"], wl["d"])
         G = len(Gz)
         t0 = time.perf_counter()
@@ -231,10 +232,12 @@ def main():
         "dtype": "c64 sweep / f64 GMRES",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n}^3, {R} point sources, b={wl['b']}, p={wl['p']}, d={wl['d']}, "
+                               f"C_moving/C={(wl.get('C_moving', 0.0) or wl['C']) / wl['C']:g}, "
                                f"omega/2pi={wl['omega'] / (2 * np.pi):.0f}, GMRES({wl['restart']}) to {wl['tol']:g}, "
                                f"{args.fronts} front(s) in x3, {args.fronts_inner} in x2",
                    "fronts": args.fronts, "fronts_inner": args.fronts_inner,
                    "n": n, "rhs": R, "b": wl["b"], "p": wl["p"], "slab_layers": wl["d"],
+                   "C": wl["C"], "C_moving": wl.get("C_moving", 0.0) or wl["C"],
                    "factor_bytes": info["factor_bytes"], "lines": info["n_lines"], "max_block": info["max_block"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -277,7 +280,7 @@ def main():
         fr64, fi64 = 1, 1
         for fr_, fi_ in [(args.fronts, args.fronts_inner), (args.fronts, 1), (1, 1)]:
             try:
-                plan_bytes(n, wl["b"], wl["C"], wl["p"], wl["d"], HELM_C128, fr_, fi_)
+                plan_bytes(n, wl["b"], wl["C"], wl["p"], wl["d"], HELM_C128, fr_, fi_)   # C_moving: no effect on sizes
             except HelmError:
                 continue
             fr64, fi64 = fr_, fi_

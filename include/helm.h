@@ -58,6 +58,8 @@ typedef struct {
   int fronts_inner;         /* the same choice for the inner sweep over x2 (Algorithm 4):  */
                             /* 1 (or 0) from x2 = 0 only; 2 from both faces, meeting in a  */
                             /* middle x2-group                                              */
+  double C_moving;          /* the constant C of the auxiliary problems' moving PML (Sec. 3,*/
+                            /* 4.2); 0: the same as C.  Changes the preconditioner only.  */
 } helm_pml;
 
 /*
@@ -129,7 +131,10 @@ int helm_matvec(helm_handle* h, const void* u_dev, void* y_dev, int R, int adjoi
  *   adjoint      : 0 solves A u = f with M^{-1}; 1 solves A^H u = f with M^{-H}.
  *   iters_host   : [R] iterations used per right-hand side (may be NULL).
  *   relres_host  : [R] final true relative residuals (may be NULL).
- * Returns HELM_ENOTCONV if some right-hand side did not reach tol within maxit.
+ * Returns HELM_ENOTCONV if some right-hand side did not reach tol within maxit, or if its
+ * true residual became non-finite (then relres_host holds NaN or inf for it; e.g. a
+ * preconditioner whose complex64 values overflow), and HELM_EINVAL for a right-hand side
+ * that is not finite.
  * Synchronises `stream`.
  */
 int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol, int restart,

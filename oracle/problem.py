@@ -80,11 +80,13 @@ class AxisProfile:
     half: np.ndarray
 
 
-def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0, last_phys=None):
+def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0, last_phys=None, C_mv=None):
     """Profile of a window.  With ``first_phys`` set, positions strictly below that node use
     the moving PML (the auxiliary profile replaces the original one there, Sec. 3 and 4.1);
     with ``last_phys`` set, positions strictly above that node use the mirrored moving PML;
-    all other positions keep the boundary profile, including the far-face PML."""
+    all other positions keep the boundary profile, including the far-face PML.  The moving
+    PML takes the constant C_mv (default C)."""
+    Cm = C if C_mv is None else C_mv
     m = np.arange(w0, w1 + 1)
     t_node = 2 * m
     t_half = 2 * np.arange(w0, w1 + 2) - 1
@@ -93,13 +95,13 @@ def axis_profile(w0, w1, n, b, C, omega, first_phys=None, p=0, last_phys=None):
     if first_phys is not None:
         below_n = t_node < 2 * first_phys
         below_h = t_half < 2 * first_phys
-        node = np.where(below_n, moving_profile(t_node, first_phys, p, n, C, omega), node)
-        half = np.where(below_h, moving_profile(t_half, first_phys, p, n, C, omega), half)
+        node = np.where(below_n, moving_profile(t_node, first_phys, p, n, Cm, omega), node)
+        half = np.where(below_h, moving_profile(t_half, first_phys, p, n, Cm, omega), half)
     if last_phys is not None:
         above_n = t_node > 2 * last_phys
         above_h = t_half > 2 * last_phys
-        node = np.where(above_n, moving_profile_above(t_node, last_phys, p, n, C, omega), node)
-        half = np.where(above_h, moving_profile_above(t_half, last_phys, p, n, C, omega), half)
+        node = np.where(above_n, moving_profile_above(t_node, last_phys, p, n, Cm, omega), node)
+        half = np.where(above_h, moving_profile_above(t_half, last_phys, p, n, Cm, omega), half)
     return AxisProfile(w0, w1, node, half)
 
 
@@ -152,7 +154,9 @@ class Problem:
     values only serve the degenerate-partition pins); fronts: 1 for the single-front outer
     sweep of Algorithm 6, 2 for the outer sweep from both x3-faces meeting in a middle slab
     (the configuration of the paper's experiments, Sec. 4.2 note 3 and Sec. 5); fronts_inner:
-    the same choice for the inner sweep over x2 (Algorithm 4).
+    the same choice for the inner sweep over x2 (Algorithm 4); C_moving: the constant of the
+    auxiliary problems' moving PML (0: C).  The paper fixes neither constant; only C enters
+    eq. (3) itself.
     """
     n: int
     c: np.ndarray
@@ -165,6 +169,7 @@ class Problem:
     first_z: Optional[int] = None
     fronts: int = 1
     fronts_inner: int = 1
+    C_moving: float = 0.0
     h: float = field(init=False)
 
     def __post_init__(self):
@@ -175,6 +180,10 @@ class Problem:
             self.first_y = self.b
         if self.first_z is None:
             self.first_z = self.b
+
+    @property
+    def C_mv(self):
+        return self.C_moving if self.C_moving > 0 else self.C
 
     @property
     def kappa(self):

@@ -84,8 +84,8 @@ class LineFactors:
         zw0, zw1, zfirst, zlast = window_fronts(Gz, zg, prob.p, prob.fronts)
         yw0, yw1, yfirst, ylast = window_fronts(Gy, yg, prob.p, prob.fronts_inner)
         px = prob.boundary_axis()
-        py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p, ylast)
-        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast)
+        py = axis_profile(yw0, yw1, n, prob.b, prob.C, prob.omega, yfirst, prob.p, ylast, prob.C_mv)
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast, prob.C_mv)
         K = assemble_box(prob.kappa[zw0 - 1:zw1, yw0 - 1:yw1, :], px, py, pz, h)
         self.Wy, self.Wz = yw1 - yw0 + 1, zw1 - zw0 + 1
         self.n, self.B = n, self.Wy * self.Wz
@@ -158,7 +158,7 @@ class SlabSweep:
         n = prob.n
         zw0, zw1, zfirst, zlast = window_fronts(Gz, zg, prob.p, prob.fronts)
         ax = prob.boundary_axis()
-        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast)
+        pz = axis_profile(zw0, zw1, n, prob.b, prob.C, prob.omega, zfirst, prob.p, zlast, prob.C_mv)
         self.H = assemble_box(prob.kappa[zw0 - 1:zw1], ax, ax, pz, prob.h)
         self.HH = self.H.conj().T.tocsr()
         self.Wz = zw1 - zw0 + 1

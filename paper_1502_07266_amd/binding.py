@@ -22,7 +22,7 @@ class helm_grid(ctypes.Structure):
 
 class helm_pml(ctypes.Structure):
     _fields_ = [("b", ctypes.c_int), ("C", ctypes.c_double), ("p", ctypes.c_int), ("fronts", ctypes.c_int),
-                ("fronts_inner", ctypes.c_int)]
+                ("fronts_inner", ctypes.c_int), ("C_moving", ctypes.c_double)]
 
 
 class helm_stats(ctypes.Structure):
@@ -121,10 +121,12 @@ class Helm:
     c: float64 CUDA tensor of shape (n, n, n), indexed [k, j, i] (x1 fastest).  All vector
     arguments are complex128 CUDA tensors of shape (R, n, n, n) or (n, n, n).  fronts: 1 for
     the outer sweep from x3 = 0 (Algorithm 6), 2 for two fronts meeting in a middle slab;
-    fronts_inner: the same for the inner sweep over x2 (Algorithm 4).
+    fronts_inner: the same for the inner sweep over x2 (Algorithm 4); C_moving: the constant
+    of the auxiliary problems' moving PML (0: C).
     """
 
-    def __init__(self, c, omega, b, C, p, slab_layers=1, prec="c64", fronts=1, fronts_inner=1):
+    def __init__(self, c, omega, b, C, p, slab_layers=1, prec="c64", fronts=1, fronts_inner=1,
+                 C_moving=0.0):
         import torch
         if not (isinstance(c, torch.Tensor) and c.is_cuda and c.dtype == torch.float64):
             raise TypeError("c must be a float64 CUDA tensor")
@@ -137,7 +139,8 @@ class Helm:
         self.prec = HELM_C64 if prec in ("c64", HELM_C64) else HELM_C128
         h = ctypes.c_void_p()
         _check(lib().helm_setup(ctypes.byref(helm_grid(n)), _ptr(c), self.omega,
-                                ctypes.byref(helm_pml(b, self.C, p, fronts, fronts_inner)), slab_layers, self.prec,
+                                ctypes.byref(helm_pml(b, self.C, p, fronts, fronts_inner, float(C_moving))),
+                                slab_layers, self.prec,
                                 _stream(), ctypes.byref(h)), "helm_setup")
         self._h = h
 

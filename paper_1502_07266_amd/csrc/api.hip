@@ -28,6 +28,8 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   if (!grid || !pml) return fail(HELM_EINVAL, "grid and pml must not be NULL");
   if (prec != HELM_C64 && prec != HELM_C128) return fail(HELM_EINVAL, "prec must be HELM_C64 or HELM_C128");
   if (!(pml->C > 0.0) || !std::isfinite(pml->C)) return fail(HELM_EINVAL, "PML constant C must be finite and > 0");
+  if (!(pml->C_moving >= 0.0) || !std::isfinite(pml->C_moving))
+    return fail(HELM_EINVAL, "moving-PML constant C_moving must be finite and >= 0");
   std::string msg;
   const int fronts = pml->fronts == 0 ? 1 : pml->fronts;
   const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
@@ -134,7 +136,7 @@ const char* helm_last_error(void) { return g_last_error.c_str(); }
 const char* helm_error_string(int code) {
   switch (code) {
     case HELM_OK: return "HELM_OK";
-    case HELM_ENOTCONV: return "HELM_ENOTCONV: GMRES reached maxit before tol";
+    case HELM_ENOTCONV: return "HELM_ENOTCONV: GMRES reached maxit before tol, or a residual was not finite";
     case HELM_EINVAL: return "HELM_EINVAL: invalid argument";
     case HELM_ENOMEM: return "HELM_ENOMEM: not enough device memory";
     case HELM_ESINGULAR: return "HELM_ESINGULAR: singular block in the line factorisation";
@@ -176,6 +178,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   h->omega = omega;
   h->h = 1.0 / (plan.n + 1);
   h->C = pml->C;
+  h->C_mv = pml->C_moving > 0.0 ? pml->C_moving : pml->C;
   (void)hipGetDevice(&h->device);
   const size_t N = (size_t)plan.n * plan.n * plan.n;
   hipStream_t s = S(stream);
@@ -281,6 +284,7 @@ int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol
   rc = fgmres_solve(h, (const double2*)f_dev, (double2*)u_dev, R, tol, restart, maxit, adjoint != 0,
                     iters_host, relres_host, S(stream), msg);
   if (rc < 0) return fail(rc, msg);
+  if (rc != HELM_OK && !msg.empty()) g_last_error = msg;
   return rc;
 }
 

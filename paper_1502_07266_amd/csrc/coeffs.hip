@@ -30,7 +30,7 @@ __global__ void k_kappa(const double* __restrict__ c, double* __restrict__ kappa
   kappa[e] = omega2 / (v * v);
 }
 
-__global__ void k_tables(int n, int b, int p, double C, double omega, double2* __restrict__ sbd,
+__global__ void k_tables(int n, int b, int p, double C, double C_mv, double omega, double2* __restrict__ sbd,
                          double2* __restrict__ smv, double2* __restrict__ coef,
                          double2* __restrict__ diag) {
   const double h = 1.0 / (n + 1);
@@ -42,7 +42,7 @@ __global__ void k_tables(int n, int b, int p, double C, double omega, double2* _
     sbd[e] = stretch(sigma(x_lo, eta, C) + sigma(x_hi, eta, C), omega);
   }
   if (e < 2 * p + 2) {  // moving profile, measured from its own Dirichlet plane
-    smv[e] = stretch(sigma(0.5 * e * h, eta_mv, C), omega);
+    smv[e] = stretch(sigma(0.5 * e * h, eta_mv, C_mv), omega);
   }
 }
 
@@ -76,7 +76,7 @@ hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (tables) {
     const int T = 2 * (n + 1) + 1;
-    k_tables<<<(T + 255) / 256, 256, 0, s>>>(n, h->plan.b, h->plan.p, h->C, h->omega, h->sbd,
+    k_tables<<<(T + 255) / 256, 256, 0, s>>>(n, h->plan.b, h->plan.p, h->C, h->C_mv, h->omega, h->sbd,
                                              h->smv, h->coef, h->diag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_coupling<<<(n + 2 + 255) / 256, 256, 0, s>>>(n, h->sbd, h->coef, h->diag);

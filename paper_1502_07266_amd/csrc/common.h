@@ -218,7 +218,7 @@ struct LaunchTimer {
 struct helm_handle {
   Plan plan;
   int n = 0, prec = HELM_C64, device = 0;
-  double omega = 0, h = 0, C = 0;
+  double omega = 0, h = 0, C = 0, C_mv = 0;
   int lanes_override = 0;
 
   // device data

@@ -80,7 +80,8 @@ __global__ void k_dots_final(const double2* __restrict__ partial, int K, int nch
     double2 s = make_double2(0.0, 0.0);
     const double2* p = partial + ((long long)a * K + k) * nchunk;
     for (int c = 0; c < nchunk; ++c) s = cadd(s, p[c]);
-    if (mode == 1) s = make_double2(sqrt(fmax(s.x, 0.0)), 0.0);
+    // a norm keeps NaN (fmax would turn it into 0 and a broken vector would look converged)
+    if (mode == 1) s = make_double2(s.x > 0.0 ? sqrt(s.x) : (s.x == s.x ? 0.0 : s.x), 0.0);
     out[(long long)q * ostride + k] = s;
   }
 }
@@ -292,7 +293,13 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
   std::vector<double2> tmp(R);
   HIP_MSG(hipMemcpyAsync(tmp.data(), ws.fnrm, R * sizeof(double2), hipMemcpyDeviceToHost, s));
   HIP_MSG(hipStreamSynchronize(s));
-  for (int q = 0; q < R; ++q) fn[q] = tmp[q].x;
+  for (int q = 0; q < R; ++q) {
+    fn[q] = tmp[q].x;
+    if (!std::isfinite(fn[q])) {
+      msg = "right-hand side " + std::to_string(q) + " is not finite";
+      return HELM_EINVAL;
+    }
+  }
 
   const long long Vr = (long long)(m + 1) * N, Zr = (long long)m * N;
   int status = HELM_OK;
@@ -312,7 +319,14 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
     for (int q : cyc) {
       beta[q] = tmp[q].x;
       res[q] = fn[q] > 0 ? beta[q] / fn[q] : 0.0;
-      if (beta[q] <= tol * fn[q]) {
+      if (!std::isfinite(beta[q])) {
+        // the residual overflowed or became NaN (a preconditioner out of range): give up on
+        // this right-hand side and report it
+        done[q] = 1;
+        res[q] = beta[q];
+        status = HELM_ENOTCONV;
+        msg = "right-hand side " + std::to_string(q) + ": residual not finite";
+      } else if (beta[q] <= tol * fn[q]) {
         done[q] = 1;
       } else if (its[q] >= maxit) {
         done[q] = 1;
@@ -368,6 +382,7 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
         kq[q] = j + 1;
         res[q] = fn[q] > 0 ? rr[q] / fn[q] : 0.0;
         worst = std::max(worst, res[q]);
+        // (a NaN estimate leaves the cycle; the true residual after it decides)
         if (rr[q] > tol * fn[q] && its[q] < maxit) keep.push_back(q);
       }
       if (verbose)

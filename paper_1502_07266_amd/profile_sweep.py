@@ -52,7 +52,7 @@ def main():
     c = torch.from_numpy(wl["c"]).to(dev)
     F = torch.from_numpy(inputs.sources(n, nodes)).to(dev)
     H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec, fronts=args.fronts,
-             fronts_inner=args.fronts_inner)
+             fronts_inner=args.fronts_inner, C_moving=wl.get("C_moving", 0.0))
     H.reset_stats()
     t0 = time.perf_counter()
     H.apply(F)
@@ -62,6 +62,7 @@ def main():
           f"(host {1e3 * (time.perf_counter() - t0):.1f} ms)", flush=True)
     print(json.dumps({"workload": args.workload, "prec": args.prec, "rhs": R, "fronts": args.fronts,
                       "fronts_inner": args.fronts_inner, "b": wl["b"], "p": wl["p"], "d": wl["d"],
+                      "C_moving": wl.get("C_moving", 0.0),
                       "copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copy_ms": copy_ms,
                       "apply_ms": st["apply_ms"],
                       "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R,

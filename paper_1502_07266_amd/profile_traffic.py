@@ -44,7 +44,7 @@ def main():
 
     out = {"workload": run["workload"], "rhs": run["rhs"], "fronts": run["fronts"],
            "fronts_inner": run.get("fronts_inner", 1), "b": run.get("b"), "p": run.get("p"),
-           "d": run.get("d"), "copy_bytes": copy_bytes}
+           "d": run.get("d"), "C_moving": run.get("C_moving", 0.0), "copy_bytes": copy_bytes}
     hbm = 0.0
     for counter, path, moved in (("FETCH_SIZE", args.fetch, copy_bytes),
                                  ("WRITE_SIZE", args.write, run["copy_bytes_written"])):

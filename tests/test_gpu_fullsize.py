@@ -8,7 +8,7 @@ so sampled line factorisations are compared block by block with the oracle's, an
 checked through properties that hold at any size: the adjoint dot test
 <M^{-1} x, y> = <x, M^{-H} y>, linearity, and the distance between the complex64 and the
 complex128 sweeps.  Tolerances as in test_gpu_parity.py; the complex64 sweep composes
-(2G - 1)^2 line solves (6 889 at 127^3 with one front) and is allowed 1e-3.
+(2G - 1)^2 line solves (thousands at 127^3 with one front) and is allowed 1e-3.
 """
 import numpy as np
 import pytest
@@ -27,7 +27,7 @@ _cache = {}
 def workload(name):
     if name not in _cache:
         wl = inputs.workload(name)
-        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"])
+        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], C_moving=wl.get("C_moving", 0.0))
         _cache[name] = (wl, prob)
     return _cache[name]
 
@@ -35,7 +35,7 @@ def workload(name):
 def helm(wl, prec):
     from paper_1502_07266_amd.binding import Helm
     c = torch.from_numpy(wl["c"]).cuda()
-    return Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec)
+    return Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, C_moving=wl.get("C_moving", 0.0))
 
 
 def rel(a, b):
@@ -69,7 +69,7 @@ def test_c1_apply_matches_oracle(c1_oracle, prec, tol):
 @pytest.fixture(scope="module")
 def c1_two_front_oracle():
     wl, _ = workload("c1")
-    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], fronts=2)
+    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], C_moving=wl.get("C_moving", 0.0), fronts=2)
     return wl, O.RecursiveSweep(prob)
 
 
@@ -81,7 +81,7 @@ def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
     n = wl["n"]
     x = inputs.random_rhs(n, 2, seed=22)
     from paper_1502_07266_amd.binding import Helm
-    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=2)
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, C_moving=wl.get("C_moving", 0.0), fronts=2)
     z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
     H.close()
     ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
@@ -93,7 +93,7 @@ def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
 @pytest.fixture(scope="module")
 def c1_two_inner_front_oracle():
     wl, _ = workload("c1")
-    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], C_moving=wl.get("C_moving", 0.0),
                      fronts=1, fronts_inner=2)
     return wl, O.RecursiveSweep(prob)
 
@@ -106,7 +106,7 @@ def test_c1_two_inner_front_apply_matches_oracle(c1_two_inner_front_oracle, prec
     n = wl["n"]
     x = inputs.random_rhs(n, 2, seed=24)
     from paper_1502_07266_amd.binding import Helm
-    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec,
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, C_moving=wl.get("C_moving", 0.0),
              fronts=1, fronts_inner=2)
     z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
     H.close()
@@ -180,17 +180,17 @@ def test_c3_sweep_dot_test_and_linearity(c3_handles):
 
 def test_c3_two_fronts_both_axes():
     """127^3, complex64, two fronts in x3 and in x2 (the launch configuration the benchmark
-    times): sampled line factors, including lines on the middle x2-group (blocks 11 x 7 = 77)
-    and the middle-middle line (11 x 11 = 121), against the oracle's; the adjoint dot test
-    and linearity of the whole sweep."""
+    times): sampled line factors, including lines on the middle x2-group (two chains up to 64
+    unknowns per block) and the middle-middle line (one chain), against the oracle's; the
+    adjoint dot test and linearity of the whole sweep."""
     from paper_1502_07266_amd.binding import Helm
     wl, _ = workload("c3")
     n = wl["n"]
-    prob = O.Problem(n=n, c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+    prob = O.Problem(n=n, c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"], C_moving=wl.get("C_moving", 0.0),
                      fronts=2, fronts_inner=2)
     Gt = O.groups_two_fronts(n, wl["b"], wl["d"])
     mid = len(Gt) // 2
-    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64",
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64", C_moving=wl.get("C_moving", 0.0),
              fronts=2, fronts_inner=2)
     for (g, l) in [(0, 0), (mid - 1, mid), (mid, mid), (mid + 3, mid - 1), (len(Gt) - 1, mid + 1)]:
         ln = O.LineFactors(prob, Gt, g, Gt, l, order=H.line_order(g, l))

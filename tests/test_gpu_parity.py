@@ -46,6 +46,8 @@ CASES = {
     # the middle slab's lines have 11 x 4 = 44 and 11 x 7 = 77 unknowns per block: the launch
     # holds a block above two chains' capacity, so all of them take one chain
     "mid77_2f": dict(n=19, b=4, p=4, d=3, fronts=2),
+    # a moving PML stronger than the boundary one (the auxiliary constant on its own)
+    "b4p4_2f2i_cm": dict(n=15, b=4, p=4, d=1, fronts=2, fronts_inner=2, C_moving_scale=2.0),
 }
 _cache = {}
 
@@ -55,7 +57,8 @@ def case(name):
         cfg = CASES[name]
         sc = inputs.small_case(n=cfg["n"], b=cfg["b"], p=cfg["p"], d=cfg["d"])
         prob = O.Problem(n=cfg["n"], c=sc["c"], omega=sc["omega"], b=cfg["b"], C=sc["C"], p=cfg["p"], d=cfg["d"],
-                         fronts=cfg.get("fronts", 1), fronts_inner=cfg.get("fronts_inner", 1))
+                         fronts=cfg.get("fronts", 1), fronts_inner=cfg.get("fronts_inner", 1),
+                         C_moving=cfg.get("C_moving_scale", 0.0) * sc["C"])
         _cache[name] = (sc, prob, O.RecursiveSweep(prob))
     return _cache[name]
 
@@ -65,7 +68,7 @@ def helm(name, prec):
     sc, prob, _ = case(name)
     c = torch.from_numpy(sc["c"]).cuda()
     return Helm(c, sc["omega"], prob.b, prob.C, prob.p, prob.d, prec=prec, fronts=prob.fronts,
-                fronts_inner=prob.fronts_inner)
+                fronts_inner=prob.fronts_inner, C_moving=prob.C_moving)
 
 
 TWO_CHAIN_CAP = {"c64": 64, "c128": 64}
@@ -230,3 +233,21 @@ def test_update_medium_equals_fresh_setup(name, prec):
     assert nref == expect and 0 < nref < len(M.Gz) * len(M.Gy)
     x = to_gpu(rhs(n, 2, seed=17))
     assert torch.equal(H.apply(x), H2.apply(x))
+
+
+def test_solve_never_reports_a_non_finite_residual_as_converged():
+    """A NaN in the initial guess makes the first true residual NaN: the solve must report
+    non-convergence with a NaN residual, not a zero one (a norm through fmax(., 0) once
+    turned NaN into 0); a NaN right-hand side is rejected."""
+    from paper_1502_07266_amd.binding import HelmError
+    sc, prob, M = case("b4p4")
+    f = to_gpu(rhs(prob.n, 2, seed=13))
+    H = helm("b4p4", "c64")
+    x0 = torch.zeros_like(f)
+    x0[1, 3, 4, 5] = float("nan")
+    u, its, relres, rc = H.solve(f, tol=1e-8, restart=10, maxit=20, x0=x0)
+    assert rc != 0 and np.isnan(relres[1]) and relres[0] <= 1e-8
+    bad = f.clone()
+    bad[0, 1, 1, 1] = float("nan")
+    with pytest.raises(HelmError):
+        H.solve(bad, tol=1e-8)

@@ -332,3 +332,18 @@ def test_line_problem_depends_on_its_window_only(fronts, fronts_inner):
             assert same != meets, (g, l, meets)
             changed += meets
     assert 0 < changed < len(Gz) * len(Gy)
+
+
+def test_moving_pml_constant_changes_the_preconditioner_only():
+    """C_moving enters the auxiliary problems' moving PML, not eq. (3): A is unchanged, the
+    sweep changes, and C_moving = C is the default."""
+    case = inputs.small_case(n=11, b=3, p=3, d=1)
+    kw = dict(n=11, c=case["c"], omega=case["omega"], b=3, C=case["C"], p=3, d=1, fronts=2, fronts_inner=2)
+    M0 = O.RecursiveSweep(O.Problem(**kw))
+    M1 = O.RecursiveSweep(O.Problem(C_moving=case["C"], **kw))
+    M2 = O.RecursiveSweep(O.Problem(C_moving=2.0 * case["C"], **kw))
+    assert (M0.A != M2.A).nnz == 0
+    f = inputs.random_rhs(11, 1, seed=5).reshape(-1)
+    z0, z1, z2 = M0.apply(f), M1.apply(f), M2.apply(f)
+    assert np.array_equal(z0, z1)
+    assert _rel(z2, z0) > 1e-3
