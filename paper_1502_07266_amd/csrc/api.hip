@@ -211,7 +211,7 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
       hipMemcpyAsync(h->d_line_off, plan.line_off.data(), plan.line_off.size() * sizeof(long long),
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return bail(HELM_EHIP, "copying the plan failed");
-  const std::vector<int> setup_lines = setup_line_order(plan, nullptr);
+  const std::vector<int> setup_lines = setup_classes(plan, (int)csize(prec), nullptr).order;
   if (hipMemcpyAsync(h->d_setup_lines, setup_lines.data(), setup_lines.size() * sizeof(int),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(h->d_line_one, h->plan.one.data(), h->plan.one.size(), hipMemcpyHostToDevice,
@@ -347,23 +347,20 @@ int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host,
   const Plan& P = h->plan;
   auto meets = [](const GroupInfo& gi, int lo, int hi) { return gi.w0 <= hi && gi.w0 + gi.W - 1 >= lo; };
   std::vector<int> lines;
-  int n_small = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int g = 0; g < P.Gz; ++g) {
-      if (!meets(P.zg(g), k0, k1)) continue;
-      for (int l = 0; l < P.Gy; ++l)
-        if (meets(P.yg(l), j0, j1) && P.one_chain(g, l) == (pass == 1)) lines.push_back(g * P.Gy + l);
-    }
-  for (int line : lines)
-    if (!P.one_chain(line / P.Gy, line % P.Gy)) ++n_small;
+  for (int g = 0; g < P.Gz; ++g) {
+    if (!meets(P.zg(g), k0, k1)) continue;
+    for (int l = 0; l < P.Gy; ++l)
+      if (meets(P.yg(l), j0, j1)) lines.push_back(g * P.Gy + l);
+  }
   if (lines.empty()) return HELM_OK;
+  const SetupClasses cls = setup_classes(P, (int)csize(h->prec), &lines);
   // the setup's line list is free after helm_setup: it takes this list
-  HIP_TRY(hipMemcpyAsync(h->d_setup_lines, lines.data(), lines.size() * sizeof(int),
+  HIP_TRY(hipMemcpyAsync(h->d_setup_lines, cls.order.data(), cls.order.size() * sizeof(int),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(h->d_err, 0, 2 * sizeof(int), s));
   LaunchTimer t;
   hipEvent_t ev = t.begin(s);
-  HIP_TRY(launch_setup_lines(h, h->d_setup_lines, n_small, (int)lines.size() - n_small, s));
+  HIP_TRY(launch_setup_lines(h, h->d_setup_lines, cls, s));
   t.end(ev, s, 1);
   HIP_TRY(hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -229,7 +229,7 @@ struct helm_handle {
   double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
   GroupInfo* d_groups = nullptr;   // [Gz + Gy]
   unsigned char* d_line_one = nullptr;   // [Gz*Gy] Plan::one
-  int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_line_order
+  int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_classes order
   long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128
   int* d_err = nullptr;            // [2]: error flag, first failing line
@@ -253,12 +253,16 @@ struct helm_handle {
 // ---------------------------------------------------------------------------------------
 hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables, hipStream_t s);
 hipError_t launch_setup(helm_handle* h, hipStream_t s);
-// the lines in the order the setup launches take them: the two-chain lines, then the lines
-// on a middle group (*n_small receives the count of the first kind)
-std::vector<int> setup_line_order(const Plan& P, int* n_small);
-// the setup of a list of lines (device array: n_small two-chain lines, then n_big lines on a
-// middle group)
-hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, int n_big,
+// the setup's launches: lines in class order (small two-chain blocks, other two-chain
+// blocks, one-chain lines), the count and largest block of each class
+struct SetupClasses {
+  std::vector<int> order;
+  int count[3];
+  int maxB[3];
+};
+SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subset);
+// the setup of the lines listed at d_lines (device copy of c.order)
+hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupClasses& c,
                               hipStream_t s);
 // z = M^{-1} r (or M^{-H}) for `R` right-hand sides; r in complex128 or complex64, z likewise;
 // rhs_idx (device, may be null = identity) selects which vectors to process: workgroup a

@@ -17,8 +17,11 @@
 // middle (see the order below), which halves the dependent chain of the line solve.  All
 // lines are independent (Sec. 6 notes that the setup is O(n^2) independent quasi-1D
 // problems).  The LDS of a launch is sized by its largest block, so the lines on a middle
-// group (few, with blocks up to 128) get a launch of their own, on a second stream beside
-// the launch of all other lines, whose small LDS footprint lets many workgroups share a CU.
+// group (few, with blocks up to 128) get a launch of their own, on a side stream beside the
+// launches of the other lines (split again by block size, so that the many small ones share
+// CUs four at a time).
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -28,6 +31,7 @@ constexpr int kMaxB = 128;
 constexpr int kSetupThreads = 256;        // lines with two-chain blocks (B <= 64)
 constexpr int kSetupThreadsBig = 1024;    // lines on a middle group (B up to 128)
 constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may take (of 160 KiB)
+constexpr size_t kSmallLds = 40 * 1024;         // two blocks within this: four workgroups per CU
 
 struct SetupArgs {
   int n, Gz, Gy, p;
@@ -243,27 +247,38 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
 
 }  // namespace
 
-// The line list: the two-chain lines first, then the lines on a middle group.
-std::vector<int> setup_line_order(const Plan& P, int* n_small) {
-  std::vector<int> order;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int g = 0; g < P.Gz; ++g)
-      for (int l = 0; l < P.Gy; ++l)
-        if (P.one_chain(g, l) == (pass == 1)) {
-          if (pass == 1 && n_small && *n_small < 0) *n_small = (int)order.size();
-          order.push_back(g * P.Gy + l);
-        }
-  if (n_small && *n_small < 0) *n_small = (int)order.size();
-  return order;
+// The setup's line classes, each one launch with LDS for its own largest block: two-chain
+// lines whose two B x B blocks take at most kSmallLds (several workgroups share a CU), the
+// other two-chain lines, and the one-chain lines (1024 threads each).
+SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subset) {
+  SetupClasses c;
+  std::vector<int> all;
+  if (!subset) {
+    for (int line = 0; line < P.Gz * P.Gy; ++line) all.push_back(line);
+    subset = &all;
+  }
+  for (int k = 0; k < 3; ++k) {
+    c.count[k] = 0;
+    c.maxB[k] = 0;
+  }
+  for (int k = 0; k < 3; ++k)
+    for (int line : *subset) {
+      const int B = P.line_B[line];
+      const int cls = P.one[line] ? 2 : (2 * (size_t)B * B * csz <= kSmallLds ? 0 : 1);
+      if (cls != k) continue;
+      c.order.push_back(line);
+      c.count[k] += 1;
+      c.maxB[k] = std::max(c.maxB[k], B);
+    }
+  return c;
 }
 
 hipError_t launch_setup(helm_handle* h, hipStream_t s) {
-  int n_small = -1;
-  const int total = (int)setup_line_order(h->plan, &n_small).size();
-  return launch_setup_lines(h, h->d_setup_lines, n_small, total - n_small, s);
+  const int csz = h->prec == HELM_C64 ? (int)sizeof(float2) : (int)sizeof(double2);
+  return launch_setup_lines(h, h->d_setup_lines, setup_classes(h->plan, csz, nullptr), s);
 }
 
-hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, int n_big,
+hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupClasses& c,
                               hipStream_t s) {
   const Plan& P = h->plan;
   SetupArgs a;
@@ -285,24 +300,36 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, int n_small, i
   a.factors = h->factors;
   a.err = h->d_err;
   a.lines = nullptr;
-  if (n_big == 0) return setup_launch<kSetupThreads>(h, a, d_lines, n_small, P.maxB_front, s);
-  // the lines on a middle group on a second stream, beside the others: s2 starts after the
-  // work already queued on s, and s continues only after s2 is done
-  hipStream_t s2 = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(e0, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s2, e0, 0);
-  if (e == hipSuccess)
-    e = setup_launch<kSetupThreadsBig>(h, a, d_lines + n_small, n_big, P.maxB_mid, s2);
-  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, d_lines, n_small, P.maxB_front, s);
-  if (e == hipSuccess) e = hipEventRecord(e1, s2);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s, e1, 0);
+  // class 0 on s, classes 1 and 2 on side streams that start after the work already queued
+  // on s; s continues only after both are done
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t start = nullptr, done[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  const bool need_side = c.count[1] > 0 || c.count[2] > 0;
+  if (need_side) {
+    e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(start, s);
+  }
+  int first = c.count[0];
+  for (int k = 1; k < 3 && e == hipSuccess; ++k) {
+    if (c.count[k] == 0) continue;
+    e = hipStreamCreateWithFlags(&side[k - 1], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done[k - 1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side[k - 1], start, 0);
+    if (e == hipSuccess)
+      e = k == 2 ? setup_launch<kSetupThreadsBig>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1])
+                 : setup_launch<kSetupThreads>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1]);
+    if (e == hipSuccess) e = hipEventRecord(done[k - 1], side[k - 1]);
+    first += c.count[k];
+  }
+  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, d_lines, c.count[0], c.maxB[0], s);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    if (done[k]) e = hipStreamWaitEvent(s, done[k], 0);
   // destroying a stream or event with work pending is allowed: it is released once done
-  if (e1) (void)hipEventDestroy(e1);
-  if (e0) (void)hipEventDestroy(e0);
-  if (s2) (void)hipStreamDestroy(s2);
+  for (int k = 0; k < 2; ++k) {
+    if (done[k]) (void)hipEventDestroy(done[k]);
+    if (side[k]) (void)hipStreamDestroy(side[k]);
+  }
+  if (start) (void)hipEventDestroy(start);
   return e;
 }
