@@ -155,6 +155,8 @@ def main():
                          "configuration of the paper's experiments) or from x3 = 0 only (1)")
     ap.add_argument("--fronts-inner", type=int, default=2, choices=[1, 2],
                     help="the same for the inner sweep over x2")
+    ap.add_argument("--c-moving-scale", type=float, default=0.0,
+                    help="moving-PML constant as a multiple of the boundary one (0: the workload's)")
     ap.add_argument("--ref-tol", type=float, default=1e-10,
                     help="after the FP64 solve, continue it to this residual for a reference "
                          "solution the two 1e-6 solves are measured against (0: skip)")
@@ -174,6 +176,8 @@ def main():
     from paper_1502_07266_amd.binding import Helm
 
     wl = inputs.workload(args.workload)
+    if args.c_moving_scale > 0:
+        wl["C_moving"] = args.c_moving_scale * wl["C"]
     n, R = wl["n"], len(wl["nodes"])
     dev = torch.device("cuda:0")
     c = torch.from_numpy(wl["c"]).to(dev)
