@@ -55,6 +55,7 @@ _SIGS = {
     "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
+    "helm_set_split": (_I, [_P, _I]),
     "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
     "helm_autotune": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "helm_reset_stats": (_I, [_P]),
@@ -281,6 +282,10 @@ class Helm:
 
     def set_launch(self, lanes_per_row):
         _check(lib().helm_set_launch(self.handle, int(lanes_per_row)), "helm_set_launch")
+
+    def set_split(self, on):
+        """Run each two-sided line solve's chains on a workgroup pair (True) or one workgroup."""
+        _check(lib().helm_set_split(self.handle, 1 if on else 0), "helm_set_split")
 
     def close(self):
         if self._h is not None:

@@ -119,7 +119,7 @@ void release(helm_handle* h) {
   h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
                   h->d_setup_lines, h->d_line_one, h->factors, h->d_err, h->slab_scratch,
-                  h->d_rhs_idx};
+                  h->d_rhs_idx, h->xbuf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -284,6 +284,9 @@ int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol
   rc = fgmres_solve(h, (const double2*)f_dev, (double2*)u_dev, R, tol, restart, maxit, adjoint != 0,
                     iters_host, relres_host, S(stream), msg);
   if (rc < 0) return fail(rc, msg);
+  int bad = 0;
+  HIP_TRY(take_exchange_error(h, &bad));
+  if (bad) return fail(HELM_EHIP, "a paired line solve of the sweep timed out waiting for its partner");
   if (rc != HELM_OK && !msg.empty()) g_last_error = msg;
   return rc;
 }
@@ -403,6 +406,13 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
     return fail(HELM_EINVAL, "group index out of range");
   HIP_TRY(launch_line_solve(h, zg, yg, (const double2*)r_dev, (double2*)x_dev, R, adjoint != 0,
                             S(stream)));
+  return HELM_OK;
+}
+
+int helm_set_split(helm_handle* h, int on) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (on != 0 && on != 1) return fail(HELM_EINVAL, "on must be 0 or 1");
+  h->split = on;
   return HELM_OK;
 }
 

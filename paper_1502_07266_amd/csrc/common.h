@@ -244,9 +244,22 @@ struct helm_handle {
   // apply workspace (grown on demand)
   void* slab_scratch = nullptr;
   size_t slab_scratch_bytes = 0;
+  // paired two-chain launches (helm_set_split): error word and exchange slots for xpairs
+  // workgroup pairs; xseq numbers the lines across launches
+  int split = 1;
+  void* xbuf = nullptr;
+  size_t xpairs = 0;
+  unsigned long long xseq = 0;
   int* d_rhs_idx = nullptr;
   int rhs_idx_cap = 0;
 };
+
+// layout of helm_handle::xbuf: an error word (padded), then per pair, chain and line parity a
+// slot of kZMax values of up to four 32-bit pieces, one tagged 64-bit word each
+constexpr size_t kXHead = 256;
+constexpr size_t kXSlot = (size_t)kZMax * 4;
+// nonzero if a paired line solve gave up waiting for its partner since the last call (clears it)
+hipError_t take_exchange_error(helm_handle* h, int* bad);
 
 // ---------------------------------------------------------------------------------------
 // internal launchers (all asynchronous on `stream`)

@@ -4,7 +4,10 @@
 // One workgroup runs the whole sweep for one right-hand side; a launch covers a batch of
 // right-hand sides ("persistent": the workgroup loops over every slab and line itself, so the
 // sweep's long chain of dependent block steps never returns to the host).  Workgroups of
-// different right-hand sides are independent and read the same factor stream.
+// different right-hand sides are independent and read the same factor stream.  In the
+// two-chain launches a workgroup pair (one per chain of the two-sided line solves) takes the
+// place of that workgroup: each member holds the grid points of its half of every line in x1,
+// and the two meet once per line solve, at the middle block (SPLIT below).
 //
 // Data flow for one right-hand side (one front; the two-front outer sweep is below):
 //   outer forward  g = 0..G-1 : slab input  f on the group's layers, minus A[k0,k0-1] u[k0-1]
@@ -35,7 +38,7 @@
 // (input f minus both couplings).  (3) The fronts run backwards: the lower one groups
 // mid-1..0 (input A[k1,k1+1] u[k1+1], subtracted), the upper one groups mid+1..G-1 (input
 // A[k0,k0-1] u[k0-1]).  The launch boundaries order the fronts and the middle slab; inside a
-// launch no workgroup waits for another.  The middle slab's line problems have moving PML on
+// launch only the members of a workgroup pair wait for each other.  The middle slab's line problems have moving PML on
 // both sides in x3 and larger blocks; their factors are in x1 order and each is solved by one
 // chain spanning the whole workgroup.
 #include <algorithm>
@@ -63,7 +66,28 @@ struct SweepArgs {
   void* out;
   const int* rhs_idx;
   void* scratch;
+  // paired workgroups (the SPLIT kernels): workgroups b and b + 8 (xcd_pair, the same XCD under
+  // the dispatcher's round-robin) or 2p and 2p + 1 form a pair; per pair and chain an exchange
+  // slot of two vectors (by line parity) of kZMax x kXWords tagged words; err is set when a
+  // wait times out
+  int xcd_pair;
+  unsigned long long seq0, seq_span;   // line k of the launch has sequence number seq0 + k + 1
+  unsigned long long* xdata;
+  int* xerr;
 };
+
+// middle-block exchange of a paired line solve: this chain's slot, the other chain's, the
+// line's sequence number
+struct Xchg {
+  unsigned long long* mine;
+  const unsigned long long* other;
+  unsigned long long seq;
+  int* err;
+};
+
+// polls of the partner's flag before a paired line solve gives up (about 0.1 s): the pair is
+// co-resident (cooperative launch), so only a fault elsewhere can exhaust it
+constexpr unsigned kSpinLimit = 1u << 20;
 
 // sum over groups of NC adjacent lanes (NC in {4, 8, 16}), result in every lane of the group
 template <int CTRL> __device__ __forceinline__ float dpp_mov(float x) {
@@ -117,8 +141,9 @@ __device__ __forceinline__ void lds_barrier() {
 // for each chain and step, the LDS rows to read and write and the factor block to prefetch,
 // and every lane of a block row writes the row's (identical) result, so no lane masking is
 // needed.  Steps without a destination write to a junk row.
-template <typename R, int NC, int CW, int D, bool ADJ, int CH>
+template <typename R, int NC, int CW, int D, bool ADJ, int CH, bool SPLIT = false>
 struct LineSolver {
+  static_assert(!SPLIT || CH == 2, "only two-chain line solves are split over a workgroup pair");
   using C = typename cx<R>::type;
   static constexpr int ZS = NC * CW;   // stride of one published vector (>= B, zero-padded)
   static_assert(D % 2 == 0, "the ring depth must be even (published-vector parity per slot)");
@@ -137,10 +162,11 @@ struct LineSolver {
   int4 ecur, enext;
   C Acur, ccur;
 
-  // tpc: threads per chain, a multiple of the wavefront size
-  __device__ __forceinline__ explicit LineSolver(int tpc) {
-    lower = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= tpc ? 1 : 0);
-    const int lt = (int)threadIdx.x - lower * tpc;
+  // tpc: threads per chain, a multiple of the wavefront size; half: the chain of a paired
+  // workgroup (SPLIT: the workgroup is that one chain)
+  __device__ __forceinline__ LineSolver(int tpc, int half) {
+    lower = SPLIT ? half : __builtin_amdgcn_readfirstlane((int)threadIdx.x >= tpc ? 1 : 0);
+    const int lt = SPLIT ? (int)threadIdx.x : (int)threadIdx.x - lower * tpc;
     row = lt / NC;
     c0 = (lt - row * NC) * CW;
   }
@@ -281,16 +307,66 @@ struct LineSolver {
       group<S + 1>(t0, sb, zme, zot, tab, ctab);
     }
   }
-  // the last steps % D steps of a line
+  // steps t0 + S .. end - 1 of a group that ends early (end - t0 < D)
   template <int S = 0>
-  __device__ __forceinline__ void tail(int t0, C* sb, const C* zme, const C* zot, const int4* tab,
-                                       const C* ctab) {
+  __device__ __forceinline__ void tail(int t0, int end, C* sb, const C* zme, const C* zot,
+                                       const int4* tab, const C* ctab) {
     if constexpr (S < D) {
-      if (t0 + S < steps) {
+      if (t0 + S < end) {
         step<S>(t0 + S, sb, zme, zot, tab, ctab);
-        tail<S + 1>(t0, sb, zme, zot, tab, ctab);
+        tail<S + 1>(t0, end, sb, zme, zot, tab, ctab);
       }
     }
+  }
+  // steps t0 + s0 .. min(t0 + D, end) - 1 of a group entered at slot s0 (after the exchange)
+  template <int S = 0>
+  __device__ __forceinline__ void head(int t0, int s0, int end, C* sb, const C* zme,
+                                       const C* zot, const int4* tab, const C* ctab) {
+    if constexpr (S < D) {
+      if (S >= s0) {
+        if (t0 + S >= end) return;
+        step<S>(t0 + S, sb, zme, zot, tab, ctab);
+      }
+      head<S + 1>(t0, s0, end, sb, zme, zot, tab, ctab);
+    }
+  }
+
+  // Paired line solve, before the middle step: publish this chain's partial right-hand side of
+  // the middle block (its published vector of step mid) to the partner and take the partner's
+  // into the LDS slot the middle step reads.  Each 32-bit piece of a value travels in one
+  // 64-bit word together with the line's sequence number (a relaxed device-scope atomic store
+  // and load), so a word read with the expected tag holds this line's piece and no fence is
+  // needed (a device-scope fence would write back and invalidate the L2 that the right-hand
+  // sides' workgroups share the factor stream through).  A piece whose tag never arrives (a
+  // fault elsewhere) is replaced by NaN, so the solution is NaN rather than silently wrong,
+  // and err is raised.
+  __device__ __forceinline__ void exchange(C* sb, int zb, const Xchg& x) {
+    using W = unsigned long long;
+    constexpr int np = sizeof(C) / 4;                  // 32-bit pieces per value
+    const int par = (mid & 1) * ZS;
+    const C* mine = sb + zb + lower * 2 * ZS + par;
+    C* other = sb + zb + (1 - lower) * 2 * ZS + par;
+    const W tag = (x.seq & 0xffffffffull) << 32;
+    for (int e = threadIdx.x; e < B_ * np; e += blockDim.x) {
+      const unsigned* src = reinterpret_cast<const unsigned*>(mine);
+      __hip_atomic_store(x.mine + e, tag | src[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned* dst = reinterpret_cast<unsigned*>(other);
+    for (int e = threadIdx.x; e < B_ * np; e += blockDim.x) {
+      unsigned spins = 0;
+      W w = __hip_atomic_load(x.other + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while ((w & 0xffffffff00000000ull) != tag) {
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(x.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          w = 0x7fc00000u;   // a quiet NaN in either half of a value
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        w = __hip_atomic_load(x.other + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      dst[e] = (unsigned)w;
+    }
+    lds_barrier();
   }
 
   // Solve on the right-hand side in ybuf[i*B + q]; begin_line and fill must have run, and
@@ -300,7 +376,8 @@ struct LineSolver {
   // return ybuf holds the solution (visible to the whole workgroup).  No global memory is
   // touched besides the factor stream, so the wait before each ring slot is exact.
   __device__ __forceinline__ void run(C* sb, int ybuf, int zb, int zeros, int junk, C* ctab,
-                                      int4* tab, const C* cf, const C* cb) {
+                                      int4* tab, const C* cf, const C* cb,
+                                      const Xchg* xc = nullptr) {
     const C zero = mk((R)0, (R)0);
     const int B = B_, ts = steps + 2;   // table entries per chain (CH * ts <= 2 (n + 3))
     for (int e = threadIdx.x; e < 4 * ZS; e += blockDim.x)
@@ -356,18 +433,39 @@ struct LineSolver {
     Acur = sb[ecur.x + rowc];
     const C* zme = sb + zb + lower * 2 * ZS;
     const C* zot = sb + zb + (1 - lower) * 2 * ZS;
-    const int full = steps - steps % D;
-    int t0 = 0;
-    for (; t0 < full; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
-    if (t0 < steps) tail(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+    if constexpr (!SPLIT) {
+      const int full = steps - steps % D;
+      int t0 = 0;
+      for (; t0 < full; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+      if (t0 < steps) tail(__builtin_amdgcn_readfirstlane(t0), steps, sb, zme, zot, tb, ct);
+    } else {
+      // forward steps 0 .. mid - 1, the exchange, then mid .. steps - 1 continuing the ring
+      // slots where the forward steps left them (step t always uses slot t % D)
+      int t0 = 0;
+      for (; t0 + D <= mid; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+      if (t0 < mid) tail(__builtin_amdgcn_readfirstlane(t0), mid, sb, zme, zot, tb, ct);
+      exchange(sb, zb, *xc);
+      t0 = mid - mid % D;
+      if (t0 < mid) {
+        head(__builtin_amdgcn_readfirstlane(t0), mid - t0, steps, sb, zme, zot, tb, ct);
+        t0 += D;
+      }
+      for (; t0 + D <= steps; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tb, ct);
+      if (t0 < steps) tail(__builtin_amdgcn_readfirstlane(t0), steps, sb, zme, zot, tb, ct);
+    }
   }
 };
 
 // threads of a launch: CH chains (2, or 1 spanning the workgroup) of round-up-to-64(B * NC)
 template <int NC, int CW, int CH> constexpr int max_threads() { return CH * ((NC * NC * CW + 63) / 64 * 64); }
 
-template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ, int CH>
-__global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs a) {
+// SPLIT: each line's two chains run in a pair of workgroups, one chain each, on the grid
+// points of their own half of the line in x1 (blocks 0..mid and mid+1..n-1); the pair
+// exchanges one B-vector per line solve (the middle block's partial right-hand sides) and is
+// otherwise independent, since every coupling outside a line solve joins points of the same x1
+template <typename R, typename TI, typename TO, int NC, int CW, int D, bool ADJ, int CH,
+          bool SPLIT = false>
+__global__ void __launch_bounds__((max_threads<NC, CW, SPLIT ? 1 : CH>())) k_sweep(SweepArgs a) {
   using C = typename cx<R>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, Gz = a.Gz, Gy = a.Gy;
@@ -382,7 +480,16 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
   const int tid = threadIdx.x, NT = blockDim.x;
   // workgroup = (right-hand side, outer front, inner front); the inner fronts of one outer
   // front share its slab iterate and write disjoint rows of it
-  const int fw = (int)blockIdx.x / a.ninner, ifront = (int)blockIdx.x - fw * a.ninner;
+  int half = 0, bid = (int)blockIdx.x;
+  if constexpr (SPLIT) {
+    const int b = (int)blockIdx.x;
+    half = a.xcd_pair ? (b >> 3) & 1 : b & 1;
+    bid = a.xcd_pair ? ((b >> 4) << 3) | (b & 7) : b >> 1;
+  }
+  const int fw = bid / a.ninner, ifront = bid - fw * a.ninner;
+  // the x1 range of this workgroup's grid points: the whole line, or its chain's half
+  const int ilo = SPLIT && half ? n / 2 + 1 : 0;
+  const int ni = SPLIT ? (half ? n - (n / 2 + 1) : n / 2 + 1) : n;
   const int slot = fw / a.nfront, front = fw - slot * a.nfront;
   const int q = a.rhs_idx ? a.rhs_idx[slot] : slot;
   const TI* __restrict__ f = reinterpret_cast<const TI*>(a.in) + (long long)q * a.in_stride;
@@ -398,7 +505,14 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
   auto gidx = [&](int i, int j, int k) -> long long {  // i 0-based, j, k 1-based
     return ((long long)(k - 1) * n + (j - 1)) * n + i;
   };
-  LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
+  LineSolver<R, NC, CW, D, ADJ, CH, SPLIT> ls(a.tpc, half);
+  Xchg xc{};
+  if constexpr (SPLIT) {
+    xc.err = a.xerr;
+    xc.mine = a.xdata + (size_t)(2 * bid + half) * 2 * kXSlot;
+    xc.other = a.xdata + (size_t)(2 * bid + 1 - half) * 2 * kXSlot;
+  }
+  unsigned long long lcount = 0;   // lines solved so far in this launch
 
   const int nslab = min(a.slab_hi, sweep_count(a.pass, Gz, a.zmid, front));
   const int nline = sweep_count(a.ipass, Gy, a.ymid, ifront);
@@ -428,8 +542,8 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
         // plan makes the lines of a launch agree): x1 order with one chain, two-sided with two
         ls.begin_line(T, B, n, CH == 1 ? n - 1 : n / 2);
         ls.fill();   // in flight while the line input is gathered
-        for (int e = tid; e < n * B; e += NT) {
-          const int qq = e / n, i = e - qq * n;
+        for (int e = tid; e < ni * B; e += NT) {
+          const int qq = e / ni, i = ilo + e - qq * ni;
           const int jj = qq / Wz, kk = qq - jj * Wz;
           const int j = yw0 + jj, k = zw0 + kk;
           C val = zero;
@@ -457,11 +571,24 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
           ybuf[i * B + qq] = val;
         }
         __syncthreads();
-        ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb);
+        if constexpr (SPLIT) {
+          Xchg x = xc;
+          const int par = (int)(lcount & 1);
+          x.mine += par * kXSlot;
+          x.other += par * kXSlot;
+          x.seq = a.seq0 + lcount + 1;
+          // (a launch past its span would meet flags of the next launch: reported, not waited)
+          if (lcount + 1 > a.seq_span && tid == 0)
+            __hip_atomic_store(a.xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb, &x);
+        } else {
+          ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb);
+        }
+        ++lcount;
         // ---- line output on the group's rows: v = x (inner forward) or v -= x (backward) ----
         const int npy = j1 - j0 + 1;
-        for (int e = tid; e < n * Wz * npy; e += NT) {
-          const int i = e % n, kk = (e / n) % Wz, jp = e / (n * Wz);
+        for (int e = tid; e < ni * Wz * npy; e += NT) {
+          const int i = ilo + e % ni, kk = (e / ni) % Wz, jp = e / (ni * Wz);
           const int qq = (j0 - yw0 + jp) * Wz + kk;
           C* p = v + ((long long)kk * n + (j0 + jp - 1)) * n + i;
           *p = ifwd ? ybuf[i * B + qq] : csub(*p, ybuf[i * B + qq]);
@@ -482,8 +609,8 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_sweep(SweepArgs
         else r0 = a.groups[Gz + a.ymid + 1].first;
       }
       const int nph = k1 - k0 + 1, nr = r1 - r0 + 1;
-      for (int e = tid; e < n * nr * nph; e += NT) {
-        const int i = e % n, jm = r0 - 1 + (e / n) % nr, kp = e / (n * nr);
+      for (int e = tid; e < ni * nr * nph; e += NT) {
+        const int i = ilo + e % ni, jm = r0 - 1 + (e / ni) % nr, kp = e / (ni * nr);
         const int kk = k0 - zw0 + kp;
         const C val = v[((long long)kk * n + jm) * n + i];
         const long long id = gidx(i, jm + 1, k0 + kp);
@@ -518,7 +645,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW, CH>())) k_line_solve(Swee
   const double2* r = reinterpret_cast<const double2*>(a.in) + (long long)blockIdx.x * n * B;
   double2* x = reinterpret_cast<double2*>(a.out) + (long long)blockIdx.x * n * B;
   const C* T = reinterpret_cast<const C*>(a.factors) + a.line_off[(size_t)g * Gy + l];
-  LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc);
+  LineSolver<R, NC, CW, D, ADJ, CH> ls(a.tpc, 0);
   ls.begin_line(T, B, n, CH == 1 ? n - 1 : n / 2);   // the host picks CH from the line
   ls.fill();
   for (int e = tid; e < n * B; e += NT) {   // line grid: x1 fastest, then window row, then layer
@@ -605,15 +732,45 @@ Shape choose_shape_one(int maxB) {
   return {8, -1};
 }
 
+// A two-chain launch of `grid` line-solving workgroups.  With exchange buffers (a.xdata) and
+// room for every pair to be resident at once, the SPLIT kernel runs on 2 grid workgroups of
+// one chain each, launched cooperatively (the runtime refuses a cooperative grid that cannot
+// be co-resident, so no workgroup waits for a partner that is not running); otherwise one
+// workgroup runs both chains of a line.
+template <typename K1, typename K2>
+hipError_t launch_two(K1 pair_kern, K2 kern, int grid, int tpc, size_t sm, hipStream_t s,
+                      SweepArgs a) {
+  if (a.xdata) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)pair_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)pair_kern, tpc, sm);
+    if (e != hipSuccess) return e;
+    if (coop && (long long)per_cu * cus >= 2LL * grid) {
+      a.xcd_pair = grid % 8 == 0;
+      void* args[] = {&a};
+      e = hipLaunchCooperativeKernel((const void*)pair_kern, dim3(2 * grid), dim3(tpc), args,
+                                     (unsigned)sm, s);
+      return e != hipSuccess ? e : hipGetLastError();
+    }
+  }
+  return launch_k(kern, grid, 2 * tpc, sm, s, a);
+}
+
 template <typename R, typename TI, typename TO, bool ADJ>
 hipError_t dispatch_sweep(Shape sh, int chains, int grid, size_t sm, hipStream_t s, SweepArgs a) {
   constexpr bool c64 = sizeof(R) == 4;
   if (chains == 2) {
-    const int t = 2 * a.tpc;
 #define X(NC, CW, D64, D128)                                                              \
     if (sh.nc == NC && sh.cw == CW) {                                                     \
       if constexpr ((c64 ? D64 : D128) > 0)                                               \
-        return launch_k(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ, 2>, grid, t, sm, s, a); \
+        return launch_two(k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ, 2, true>,    \
+                          k_sweep<R, TI, TO, NC, CW, (c64 ? D64 : D128), ADJ, 2, false>,   \
+                          grid, a.tpc, sm, s, a);                                         \
       return hipErrorInvalidValue;                                                        \
     }
     HELM_SHAPES(X)
@@ -697,6 +854,11 @@ SweepArgs base_args(helm_handle* h) {
   a.out = nullptr;
   a.rhs_idx = nullptr;
   a.scratch = nullptr;
+  a.xcd_pair = 0;
+  a.seq0 = 0;
+  a.seq_span = 0;
+  a.xdata = nullptr;
+  a.xerr = nullptr;
   return a;
 }
 
@@ -718,6 +880,17 @@ hipError_t sweep_launch(helm_handle* h, SweepArgs a, const SweepLaunch& L, int R
   a.tpc = chain_threads(L.maxB, sh.nc);
   const size_t sm = LdsLayout(h->n, L.maxB, (int)sizeof(typename cx<R>::type)).bytes;
   const int grid = R_ * L.nfront * L.ninner;
+  a.xdata = nullptr;
+  if (L.chains == 2 && h->split && h->xbuf && (size_t)grid <= h->xpairs) {
+    char* base = static_cast<char*>(h->xbuf);
+    a.xerr = reinterpret_cast<int*>(base);
+    a.xdata = reinterpret_cast<unsigned long long*>(base + kXHead);
+    // every line solve of the launch takes the next sequence number: a workgroup solves at
+    // most (2 Gz - 1) (2 Gy - 1) lines (both passes of both loops)
+    a.seq0 = h->xseq;
+    a.seq_span = (unsigned long long)(2 * h->plan.Gz) * (2 * h->plan.Gy);
+    h->xseq += a.seq_span;
+  }
   return adjoint ? dispatch_sweep<R, TI, TO, true>(sh, L.chains, grid, sm, s, a)
                  : dispatch_sweep<R, TI, TO, false>(sh, L.chains, grid, sm, s, a);
 }
@@ -763,6 +936,23 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
     if (e != hipSuccess) return e;
     h->slab_scratch_bytes = need;
   }
+  // exchange buffers of the paired two-chain launches: one pair per workgroup of a launch
+  const size_t pairs = (size_t)R * h->plan.fronts * h->plan.fronts_inner;
+  if (h->split && pairs > h->xpairs) {
+    if (h->xbuf) {
+      hipError_t e = hipFree(h->xbuf);
+      if (e != hipSuccess) return e;
+      h->xbuf = nullptr;
+      h->xpairs = 0;
+    }
+    // (cleared whole: tags left in reused memory by another handle must not match)
+    const size_t bytes = kXHead + pairs * 2 * 2 * kXSlot * sizeof(unsigned long long);
+    hipError_t e = hipMalloc(&h->xbuf, bytes);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(h->xbuf, 0, bytes, s);
+    if (e != hipSuccess) return e;
+    h->xpairs = pairs;
+  }
   SweepArgs a = base_args(h);
   a.in = r;
   a.out = z;
@@ -781,6 +971,14 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   else
     e = sweep_all<float, double2, float2>(h, a, R, adjoint, s);
   h->t_apply.end(ev, s, R);
+  return e;
+}
+
+hipError_t take_exchange_error(helm_handle* h, int* bad) {
+  *bad = 0;
+  if (!h->xbuf) return hipSuccess;
+  hipError_t e = hipMemcpy(bad, h->xbuf, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && *bad) e = hipMemset(h->xbuf, 0, sizeof(int));
   return e;
 }
 

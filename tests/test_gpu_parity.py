@@ -172,6 +172,31 @@ def test_apply_launch_shape_invariant(lanes, name):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_apply_paired_chains_match_one_workgroup(name, prec, adjoint):
+    """The two chains of each two-sided line solve on a workgroup pair (the default) agree with
+    both chains in one workgroup to rounding (the same operations in the same order; the two
+    kernels are compiled for different workgroup sizes, which may contract multiply-adds
+    differently: observed differences are a few units in the last place): with 3 right-hand
+    sides the launches pair workgroups 2p, 2p + 1, with 8 they pair b, b + 8; the calls in a
+    row regrow the exchange buffers and continue the line numbering."""
+    sc, prob, M = case(name)
+    Hp = helm(name, prec)
+    H1 = helm(name, prec)
+    H1.set_split(False)
+    tol = 1e-13 if prec == "c128" else 1e-5
+    for R in (3, 8, 3):
+        x = to_gpu(rhs(prob.n, R, seed=20 + R))
+        zp = Hp.apply(x, adjoint=adjoint).cpu().numpy()
+        z1 = H1.apply(x, adjoint=adjoint).cpu().numpy()
+        err = max(rel(zp[q], z1[q]) for q in range(R))
+        assert err <= tol, f"R={R}: {err:.3e}"
+    ref = M.apply(x.cpu().numpy().reshape(3, -1).T, adjoint=adjoint).T.reshape(x.shape)
+    assert rel(zp, ref) <= (1e-10 if prec == "c128" else 2e-4)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_solve(name, prec):
     """FGMRES to 1e-8 against a sparse direct solve of eq. (3); the error bound 1e-6 allows the
     conditioning of A to amplify the residual (the reported numbers are ~1e-8)."""
