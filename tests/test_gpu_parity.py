@@ -195,6 +195,25 @@ def test_apply_paired_chains_match_one_workgroup(name, prec, adjoint):
     assert rel(zp, ref) <= (1e-10 if prec == "c128" else 2e-4)
 
 
+def test_apply_unpaired_when_pairs_cannot_be_resident():
+    """With more workgroup pairs than the GPU can hold at once the paired launch is refused
+    and the launch runs unpaired: same results as a handle set to unpaired, and the oracle's
+    on a sample of the right-hand sides."""
+    name = "tiny3_2f2i"
+    sc, prob, M = case(name)
+    R = 1500   # 6000 pairs of line-solving workgroups per launch: beyond any co-residency
+    x = rhs(prob.n, R, seed=31)
+    Hp = helm(name, "c128")
+    H1 = helm(name, "c128")
+    H1.set_split(False)
+    zp = Hp.apply(to_gpu(x)).cpu().numpy()
+    z1 = H1.apply(to_gpu(x)).cpu().numpy()
+    assert rel(zp, z1) <= 1e-13
+    pick = [0, 1, 777, R - 1]
+    ref = M.apply(x[pick].reshape(len(pick), -1).T).T.reshape((len(pick),) + x.shape[1:])
+    assert rel(zp[pick], ref) <= 1e-10
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_solve(name, prec):
