@@ -229,14 +229,15 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
  * helm_set_split -- where the two elimination chains of a two-sided line solve run (the
  * two-sided block LDU of Sec. 3, eliminated from both ends towards the middle block): on = 1
  * (default) gives each chain a workgroup of its own, a pair per line solve holding the grid
- * points of its half of the line in x1, which meet once per line solve to exchange the middle
- * block's partial right-hand sides through device memory; on = 0 runs both chains in one
- * workgroup.  The operations and their order are the same either way; results agree to
- * rounding (the two kernels may contract multiply-adds differently).  Pairs are used only when every pair of a
- * launch can be resident at once (a cooperative launch; otherwise that launch runs unpaired);
- * they take (R * fronts * fronts_inner) x 16 KiB of device memory beside the slab scratch.  A
- * pair whose partner never arrives gives up after about 0.1 s, writes NaN into its line
- * solution and makes the next helm_solve on the handle return HELM_EHIP.
+ * points of its half of the line in x1, which meet once per line solve to exchange the
+ * middle block's partial right-hand sides through device memory; on = 0 runs both chains in
+ * one workgroup.  The operations and their order are the same either way; results agree to
+ * rounding (the two kernels may contract multiply-adds differently).  Pairs are used only
+ * when every pair of a launch can be resident at once (a cooperative launch; otherwise that
+ * launch runs unpaired); they take (R * fronts * fronts_inner) x 16 KiB of device memory
+ * beside the slab scratch.  A member whose partner never arrives gives up after 2^20 polls
+ * (on the order of a second), writes NaN into its line solution and makes the next
+ * helm_solve on the handle return HELM_EHIP.
  * Errors: HELM_EINVAL (h NULL, on not 0 or 1).
  */
 int helm_set_split(helm_handle* h, int on);

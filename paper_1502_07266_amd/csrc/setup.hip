@@ -37,6 +37,9 @@ struct SetupArgs {
   int n, Gz, Gy, p;
   int fronts, zmid, fronts_inner, ymid;
   int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
+  int part;          // 0: whole lines; 1: the two halves of two-sided lines, one workgroup
+                     // each (workgroup 2w + h takes half h of line lines[w]); 2: their middle
+                     // blocks, after part 1
   const int* lines;  // the lines of this launch (workgroup w takes line lines[w])
   const unsigned char* line_one;   // per line: solved by one chain (x1 order)
   double h;
@@ -71,7 +74,9 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   __shared__ C pinv_s;
   __shared__ int piv_s, bad_s;
 
-  const int line = a.lines[blockIdx.x];
+  const int w = a.part == 1 ? (int)blockIdx.x >> 1 : (int)blockIdx.x;
+  const int half = a.part == 1 ? (int)blockIdx.x & 1 : 0;
+  const int line = a.lines[w];
   const int g = line / a.Gy, l = line % a.Gy;
   const GroupInfo gz = a.groups[g], gy = a.groups[a.Gz + l];
   const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
@@ -101,7 +106,18 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   const C* Tprev = Tlds;
   const bool has_lower = mid + 1 <= n - 1;
   const C* T_mid_minus1 = out + (long long)(mid - 1) * B * B;   // T_{m-1}, stored at t = m - 1
-  for (int t = 0; t < n; ++t) {
+  // steps t0..t1-1 of the order: all, one half (the halves do not meet before the middle
+  // block, so they run in two workgroups), or the middle block alone, which then reads both
+  // neighbours' factors from HBM
+  int t0 = 0, t1 = n;
+  if (a.part == 1) {
+    t0 = half ? mid : 0;
+    t1 = half ? n - 1 : mid;
+  } else if (a.part == 2) {
+    t0 = n - 1;
+    Tprev = has_lower ? out + (long long)(mid + 1) * B * B : T_mid_minus1;
+  }
+  for (int t = t0; t < t1; ++t) {
     const int i = t < mid ? t : (t < n - 1 ? n - 1 - (t - mid) : mid);
     const int m = i + 1;  // global x1 node of block i
     const double2 sxn = a.sbd[2 * m], sxd = a.sbd[2 * m - 1], sxu = a.sbd[2 * m + 1];
@@ -221,11 +237,19 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   }
 }
 
-// one launch over `count` lines listed at d_lines, LDS sized for blocks up to maxB
+// one launch over `count` lines listed at d_lines, LDS sized for blocks up to maxB; two-sided
+// lines take two launches, their halves on two workgroups each, then their middle blocks
 template <int NTB>
 hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, int count, int maxB,
-                        hipStream_t s) {
+                        hipStream_t s, bool two_sided) {
   if (count <= 0) return hipSuccess;
+  if (two_sided) {
+    a.part = 1;
+    hipError_t e = setup_launch<NTB>(h, a, d_lines, 2 * count, maxB, s, false);
+    if (e != hipSuccess) return e;
+    a.part = 2;
+    return setup_launch<NTB>(h, a, d_lines, count, maxB, s, false);
+  }
   a.lines = d_lines;
   const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
   // keep the previous factor in LDS when two B x B blocks fit, else re-read it from HBM
@@ -300,6 +324,7 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
   a.factors = h->factors;
   a.err = h->d_err;
   a.lines = nullptr;
+  a.part = 0;
   // class 0 on s, classes 1 and 2 on side streams that start after the work already queued
   // on s; s continues only after both are done
   hipStream_t side[2] = {nullptr, nullptr};
@@ -317,12 +342,12 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
     if (e == hipSuccess) e = hipEventCreateWithFlags(&done[k - 1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamWaitEvent(side[k - 1], start, 0);
     if (e == hipSuccess)
-      e = k == 2 ? setup_launch<kSetupThreadsBig>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1])
-                 : setup_launch<kSetupThreads>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1]);
+      e = k == 2 ? setup_launch<kSetupThreadsBig>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1], false)
+                 : setup_launch<kSetupThreads>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1], true);
     if (e == hipSuccess) e = hipEventRecord(done[k - 1], side[k - 1]);
     first += c.count[k];
   }
-  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, d_lines, c.count[0], c.maxB[0], s);
+  if (e == hipSuccess) e = setup_launch<kSetupThreads>(h, a, d_lines, c.count[0], c.maxB[0], s, true);
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     if (done[k]) e = hipStreamWaitEvent(s, done[k], 0);
   // destroying a stream or event with work pending is allowed: it is released once done

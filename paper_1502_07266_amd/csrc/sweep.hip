@@ -85,8 +85,9 @@ struct Xchg {
   int* err;
 };
 
-// polls of the partner's flag before a paired line solve gives up (about 0.1 s): the pair is
-// co-resident (cooperative launch), so only a fault elsewhere can exhaust it
+// polls of a partner's word before a paired line solve gives up (each poll a device-memory
+// round trip and a short sleep: on the order of a second): the pair is co-resident
+// (cooperative launch), so only a fault elsewhere can exhaust it
 constexpr unsigned kSpinLimit = 1u << 20;
 
 // sum over groups of NC adjacent lanes (NC in {4, 8, 16}), result in every lane of the group
@@ -755,7 +756,8 @@ hipError_t launch_two(K1 pair_kern, K2 kern, int grid, int tpc, size_t sm, hipSt
       void* args[] = {&a};
       e = hipLaunchCooperativeKernel((const void*)pair_kern, dim3(2 * grid), dim3(tpc), args,
                                      (unsigned)sm, s);
-      return e != hipSuccess ? e : hipGetLastError();
+      if (e != hipErrorCooperativeLaunchTooLarge) return e != hipSuccess ? e : hipGetLastError();
+      (void)hipGetLastError();   // refused (not all resident): run unpaired
     }
   }
   return launch_k(kern, grid, 2 * tpc, sm, s, a);
