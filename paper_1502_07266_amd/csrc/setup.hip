@@ -11,10 +11,12 @@
 // the only dense work is inverting S_i.
 // D_i is the 5-point (x2, x3) operator of the window plus the x1 diagonal and kappa.
 //
-// One workgroup owns one line: it forms S_i in LDS, inverts it by Gauss-Jordan elimination
-// with partial pivoting (row interchanges inside the block only), stores T_i = S_i^{-1} and
-// reuses it for the next Schur update.  The blocks are eliminated from both ends towards the
-// middle (see the order below), which halves the dependent chain of the line solve.  All
+// One workgroup owns a line, or one half of a two-sided line: it forms S_i in LDS, inverts it
+// by Gauss-Jordan elimination with partial pivoting (row interchanges inside the block only),
+// stores T_i = S_i^{-1} and reuses it for the next Schur update.  The blocks are eliminated
+// from both ends towards the middle (see the order below), which halves the dependent chain
+// of the line solve; the two halves do not meet before the middle block, so they are factored
+// by two workgroups and the middle blocks by a launch of their own.  All
 // lines are independent (Sec. 6 notes that the setup is O(n^2) independent quasi-1D
 // problems).  The LDS of a launch is sized by its largest block, so the lines on a middle
 // group (few, with blocks up to 128) get a launch of their own, on a side stream beside the
