@@ -173,7 +173,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the sweep for one "
               "right-hand side is a single dependent chain; multi-GPU sharding by right-hand "
-              "side is described in DESIGN.md and not run here.", file=sys.stderr)
+              "side is a design only and not run here.", file=sys.stderr)
         sys.exit(2)
 
     # per-iteration progress lines from the solver (stderr), so long solves are never silent
