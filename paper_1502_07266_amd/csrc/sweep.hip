@@ -578,7 +578,7 @@ __global__ void __launch_bounds__((max_threads<NC, CW, SPLIT ? 1 : CH>())) k_swe
           x.mine += par * kXSlot;
           x.other += par * kXSlot;
           x.seq = a.seq0 + lcount + 1;
-          // (a launch past its span would meet flags of the next launch: reported, not waited)
+          // (a launch past its span would share tags with the next launch: reported)
           if (lcount + 1 > a.seq_span && tid == 0)
             __hip_atomic_store(a.xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ls.run(sb, L.ybuf, L.zb, L.zeros, L.junk, ctab, tab, cf, cb, &x);
