@@ -17,6 +17,8 @@ precision).  Each function cites the section, equation or algorithm it follows:
                    auxiliary PML): groups, windows, moving-PML profiles.
 * ``sweep``     -- Sec. 4: quasi-1D block LDU (Sec. 4.1), Algorithms 3/4 (inner sweep)
                    and 5/6 (outer sweep), and the adjoint of Algorithm 6.
+* ``nested``    -- Sec. 6: 1D nested dissection of the line problems (the parallel
+                   alternative to the block LDU; oracle only so far).
 * ``krylov``    -- Sec. 5: GMRES as the outer solver (flexible, right preconditioned).
 * ``gradient``  -- the adjoint-state misfit gradient (not in the paper; derived from
                    eq. (3), whose only dependence on c is the diagonal omega^2/c^2).
@@ -31,11 +33,12 @@ from .problem import (Problem, sigma, stretch, boundary_profile, axis_profile,
                       assemble_box, helmholtz_matrix)
 from .partition import groups, groups_two_fronts, window, window_fronts
 from .sweep import LineFactors, SlabSweep, RecursiveSweep, elimination_order
+from .nested import NestedDissection
 from .krylov import fgmres
 from .gradient import misfit_and_gradient
 
 __all__ = [
     "Problem", "sigma", "stretch", "boundary_profile", "axis_profile", "assemble_box",
     "helmholtz_matrix", "groups", "groups_two_fronts", "window", "window_fronts", "LineFactors", "SlabSweep", "RecursiveSweep", "elimination_order",
-    "fgmres", "misfit_and_gradient",
+    "NestedDissection", "fgmres", "misfit_and_gradient",
 ]
