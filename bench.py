@@ -58,16 +58,32 @@ def group_count(n, b, d, fronts):
     return 1 + -(-(n - b) // d) if fronts == 1 else 2 + -(-(n - 2 * b) // d)
 
 
-def dependent_steps(n, b, d, fronts, fronts_inner):
+def dependent_steps(n, b, d, fronts, fronts_inner, line_steps=None):
     """Dependent block steps of one sweep (the longest chain through its launches) and of one
     launch of the dominant kernel.  A two-sided line solve takes 2 (n/2) + 1 steps, a
-    one-chain solve (lines on a middle group) 2n - 1."""
+    one-chain solve 2n - 1; line_steps(g, l) gives them per line (default: the lines on a
+    middle group one chain, the others two-sided).  With two fronts the chain runs through
+    the front with more groups."""
     S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
     Gz, Gy = group_count(n, b, d, fronts), group_count(n, b, d, fronts_inner)
-    Fz = max(Gz // 2, Gz - 1 - Gz // 2) if fronts == 2 else 0
-    Fy = max(Gy // 2, Gy - 1 - Gy // 2) if fronts_inner == 2 else 0
-    slab = (lambda S: (2 * Gy - 1) * S) if fronts_inner == 1 else (lambda S: 2 * Fy * S + S1)
-    sweep = (2 * Gz - 1) * slab(S2) if fronts == 1 else 2 * Fz * slab(S2) + slab(S1)
+    zmid, ymid = Gz // 2, Gy // 2
+    if line_steps is None:
+        line_steps = lambda g, l: S1 if (fronts == 2 and g == zmid) or (fronts_inner == 2 and l == ymid) else S2
+
+    def longer_front(G, mid):
+        lo, hi = list(range(mid)), list(range(mid + 1, G))
+        return lo if len(lo) >= len(hi) else hi
+
+    def slab(g):
+        if fronts_inner == 1:
+            return sum(line_steps(g, l) for l in range(Gy)) + sum(line_steps(g, l) for l in range(Gy - 1))
+        return 2 * sum(line_steps(g, l) for l in longer_front(Gy, ymid)) + line_steps(g, ymid)
+
+    if fronts == 1:
+        sweep = sum(slab(g) for g in range(Gz)) + sum(slab(g) for g in range(Gz - 1))
+    else:
+        sweep = 2 * sum(slab(g) for g in longer_front(Gz, zmid)) + slab(zmid)
+    Fz, Fy = len(longer_front(Gz, zmid)), len(longer_front(Gy, ymid))
     if fronts_inner == 2:
         kernel = Fy * S2                       # one inner front's lines of one slab step
     elif fronts == 1:
@@ -225,7 +241,16 @@ def main():
     # the dominant kernel (its two-chain launches)
     kernel_avg_ms = tot["kernel_ms"] / max(tot["kernel_launches"], 1)
     kernel_bytes_per_launch = kbr * tot["kernel_rhs"] / max(tot["kernel_launches"], 1)
-    steps_per_sweep, steps_per_kernel = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner)
+    # each line's chain count as a handle of this configuration factors it (two-sided or x1
+    # order), from a handle made after the timed region
+    S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
+    Hq = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64", fronts=args.fronts,
+              fronts_inner=args.fronts_inner, C_moving=wl.get("C_moving", 0.0))
+    chains = {}
+    line_steps = lambda g, l: chains.setdefault((g, l), S2 if Hq.line_order(g, l) == "two-sided" else S1)
+    steps_per_sweep, steps_per_kernel = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner,
+                                                        line_steps)
+    Hq.close()
     apply_bytes_per_launch = bpr * tot["apply_rhs"] / max(tot["apply_launches"], 1)
     achieved = kernel_bytes_per_launch / (kernel_avg_ms * 1e-3) / 1e9
     mv_gbs = mvb * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
