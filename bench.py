@@ -7,18 +7,19 @@ applied in complex64 and GMRES, matvec and residuals in FP64.  The outer sweep r
 fronts (from both x3-faces, as in the paper's experiments) unless --fronts 1, and so does the
 inner sweep over x2 unless --fronts-inner 1.  Inputs are resident on the GPU before the timed
 region.  Default workload: 127^3 interior points, 5-cell PML (C = 30 b),
-moving PML 5 cells, one layer per auxiliary problem, a Gaussian random field in [1, 2]
-(correlation length 0.1), omega = 2 pi 16, 32 point sources at seeded interior nodes,
-GMRES(50) to relative residual 1e-6.
+2-cell moving PML of constant C/8, five layers per auxiliary problem, a Gaussian random field
+in [1, 2] (correlation length 0.1), omega = 2 pi 16, 32 point sources at seeded interior
+nodes, GMRES(50) to relative residual 1e-6.
 
 Printed: one JSON line.  `value` is seconds per step (lower is better).  `roofline` is the
-sweep kernel (the dominant kernel: its two-chain launches): algorithmic bytes per launch
-divided by its average launch duration, both taken from HIP events recorded on the launch
-stream inside the timed steps.  The FP64 path (complex128 sweep) is run once after the timed
-steps and reported beside, with the same fronts where complex128 allows them (the line
-vector of a block larger than 96 does not fit in LDS in complex128: then one inner front).
-`cpu_baseline` is the oracle timed on a bounded sample of the same workload and scaled to
-one step.
+sweep kernel (the dominant kernel: its two-chain launches): algorithmic bytes per launch (the
+launch's factor blocks once per visit, which its right-hand sides share, plus every
+right-hand side's input and output) divided by its average launch duration, both taken from
+HIP events recorded on the launch stream inside the timed steps.  The FP64 path (complex128
+sweep) is run once after the timed steps and reported beside, with the same fronts where
+complex128 allows them.  `oracle_reference` compares the mixed solution with the oracle's
+reference solutions stored under tests/golden.  `cpu_baseline` is the oracle timed on the
+host's cores on a bounded sample of the same workload and scaled to one step.
 """
 import argparse
 import json
@@ -122,52 +123,114 @@ def measured_traffic(workload, wl, fronts, fronts_inner):
     return rec
 
 
-def cpu_baseline(wl, iters, budget_s, fronts=1, fronts_inner=1):
-    """Oracle (numpy/scipy complex128, BLAS limited to one thread) on a bounded sample: the
-    full factorisation of a few interior line problems and repeated single-right-hand-side
-    line solves, scaled to one step = all Gz Gy lines factored + (2Gz-1)(2Gy-1) line solves
-    per sweep (every group is visited twice but one, with one front or two) and one sweep per
-    GMRES iteration per right-hand side (the sweep dominates the oracle's time; matvecs and
-    orthogonalisation are left out, so the estimate is a lower bound)."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-    import oracle as O
-    from oracle.partition import groups
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    with threadpool_limits(limits=1):
-        prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
-                         C_moving=wl.get("C_moving", 0.0))
-        Gz = groups(wl["n"], wl["b"], wl["d"])
-        G = len(Gz)
-        t0 = time.perf_counter()
-        lines = []
-        g = G // 2
-        while time.perf_counter() - t0 < 0.5 * budget_s and len(lines) < 8:
-            lines.append(O.LineFactors(prob, Gz, g, Gz, g + len(lines) - 4))
-        t_fac = (time.perf_counter() - t0) / len(lines)
-        ln = lines[0]
-        rng = np.random.default_rng(0)
-        r = rng.standard_normal(ln.K.shape[0]) + 1j * rng.standard_normal(ln.K.shape[0])
+
+def cpu_baseline(wl, iters, fronts=2, fronts_inner=2):
+    """The oracle (numpy/scipy complex128, BLAS on every host core) timed on a bounded sample
+    of this workload and scaled to one step.  Sample: the assembly of A (eq. (3)); the setup
+    (Algorithm 3: every line factorisation) of three x3-slabs, a boundary slab, an interior
+    front slab and the middle slab, and one inner sweep (Algorithm 4) of each on one
+    right-hand side; one matvec; one Gram-Schmidt dot product + update.  Scaled: setup = the
+    assembly + every slab's setup (the boundary slabs, the interior ones and the middle one by
+    their samples); per GMRES iteration and right-hand side one sweep (each slab applied twice,
+    the middle slab once: Algorithm 6 with two fronts; Algorithm 6 as printed applies the last
+    slab once), one matvec and j + 1 modified Gram-Schmidt dots and updates at iteration j;
+    two true-residual matvecs per right-hand side.  `iters` are the GPU solve's iteration
+    counts (the oracle's FGMRES takes the same within one or two)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import oracle as O
+    from oracle.partition import groups, groups_two_fronts
+
+    n = wl["n"]
+    prob = O.Problem(n=n, c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                     C_moving=wl.get("C_moving", 0.0), fronts=fronts, fronts_inner=fronts_inner)
+    Gz = groups_two_fronts(n, wl["b"], wl["d"]) if fronts == 2 else groups(n, wl["b"], wl["d"])
+    Gy = groups_two_fronts(n, wl["b"], wl["d"]) if fronts_inner == 2 else groups(n, wl["b"], wl["d"])
+    G = len(Gz)
+    mid = G // 2 if fronts == 2 else G - 1
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    A = O.helmholtz_matrix(prob)
+    t_asm = time.perf_counter() - t0
+    samples = {}
+    for tag, g in (("boundary", 0), ("interior", mid - 1), ("middle", mid)):
         t1 = time.perf_counter()
-        ns = 0
-        while time.perf_counter() - t1 < 0.4 * budget_s:
-            ln.solve(r)
-            ns += 1
-        t_sol = (time.perf_counter() - t1) / ns
-    Gz_, Gy_ = (group_count(wl["n"], wl["b"], wl["d"], fr) for fr in (fronts, fronts_inner))
-    solves_per_sweep = (2 * Gz_ - 1) * (2 * Gy_ - 1)
-    est = Gz_ * Gy_ * t_fac + float(np.sum(iters)) * solves_per_sweep * t_sol
-    sample = (f"{len(lines)} interior line factorisations ({t_fac:.3f} s each) and {ns} line solves "
-              f"({t_sol * 1e3:.2f} ms each) of this workload, scaled to {Gz_ * Gy_} factorisations + "
-              f"{int(np.sum(iters))} sweeps x {solves_per_sweep} line solves")
-    return est, sample
+        slab = O.SlabSweep(prob, Gz, g, Gy)
+        t_set = time.perf_counter() - t1
+        gv = rng.standard_normal(slab.H.shape[0]) + 1j * rng.standard_normal(slab.H.shape[0])
+        t2 = time.perf_counter()
+        slab.apply(gv)
+        samples[tag] = (t_set, time.perf_counter() - t2)
+    N = n ** 3
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    t3 = time.perf_counter()
+    A @ x
+    t_mv = time.perf_counter() - t3
+    y = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    t4 = time.perf_counter()
+    for _ in range(4):
+        hij = np.vdot(x, y)
+        y = y - hij * x
+    t_orth = (time.perf_counter() - t4) / 4
+    nb = 2 if fronts == 2 else 1                  # boundary slabs (one front: slab 0 only)
+    n_int = G - nb - 1
+    setup = t_asm + nb * samples["boundary"][0] + n_int * samples["interior"][0] + samples["middle"][0]
+    # applies per sweep: every slab twice but the middle (two fronts) or the last (one front)
+    sweep = 2 * nb * samples["boundary"][1] + 2 * n_int * samples["interior"][1] + samples["middle"][1]
+    if fronts == 1:
+        sweep -= samples["middle"][1] - samples["interior"][1]   # slab G-1 is an interior one
+    solve = 0.0
+    for it in np.asarray(iters).tolist():
+        solve += it * (sweep + t_mv) + sum(j + 1 for j in range(int(it))) * t_orth + 2 * t_mv
+    est = setup + solve
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    sample = (f"oracle on {threads} BLAS threads ({_cpu_model()}, {os.cpu_count()} logical CPUs): "
+              f"assembly of A {t_asm:.2f} s; setup of a boundary / interior / middle x3-slab "
+              f"{samples['boundary'][0]:.2f} / {samples['interior'][0]:.2f} / {samples['middle'][0]:.2f} s "
+              f"and one inner sweep of each {samples['boundary'][1]:.3f} / {samples['interior'][1]:.3f} / "
+              f"{samples['middle'][1]:.3f} s; matvec {t_mv:.3f} s; Gram-Schmidt dot + update "
+              f"{t_orth * 1e3:.1f} ms; scaled to {G} slabs (setup {setup:.1f} s), one sweep "
+              f"{sweep:.2f} s per iteration and right-hand side, {int(np.sum(iters))} iterations "
+              f"over {len(iters)} right-hand sides")
+    parts = {"setup_s": round(setup, 2), "sweep_s_per_rhs": round(sweep, 3), "matvec_s_per_rhs": round(t_mv, 4),
+             "solve_s": round(solve, 1)}
+    return est, threads, sample, parts
+
+
+def oracle_reference(workload, u_mix, fronts, fronts_inner):
+    """Relative L2 error of the mixed solution against the oracle's reference solutions (FGMRES
+    to 1e-10, written by tests/golden/make_reference_solutions.py), on the stored subsample of
+    every right-hand side the reference covers; None if there is none for this workload."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_reference.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    s = int(ref["stride"])
+    m = ref["sub"].shape[0]
+    sub = u_mix[:m, ::s, ::s, ::s].cpu().numpy()
+    err = np.linalg.norm((sub - ref["sub"]).reshape(m, -1), axis=1) / np.linalg.norm(ref["sub"].reshape(m, -1), axis=1)
+    return {"rhs": m, "subsample_stride": s, "oracle_tol": 1e-10,
+            "rel_l2_mixed_vs_oracle": [float(e) for e in err],
+            "rel_l2_mixed_vs_oracle_max": float(err.max()),
+            "file": os.path.relpath(path, ROOT)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
     ap.add_argument("--no-pair", action="store_true",
@@ -182,7 +245,7 @@ def main():
     ap.add_argument("--ref-tol", type=float, default=1e-10,
                     help="after the FP64 solve, continue it to this residual for a reference "
                          "solution the two 1e-6 solves are measured against (0: skip)")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     args = ap.parse_args()
     global PAIRED
     PAIRED = not args.no_pair
@@ -197,7 +260,7 @@ def main():
     import numpy as np
     import torch
     from paper_1502_07266_amd import inputs
-    from paper_1502_07266_amd.binding import Helm
+    from paper_1502_07266_amd.binding import Helm, pool_stats
 
     wl = inputs.workload(args.workload)
     if args.c_moving_scale > 0:
@@ -209,8 +272,12 @@ def main():
     torch.cuda.synchronize()
     log(f"workload {args.workload}: n={n} R={R} b={wl['b']} p={wl['p']} d={wl['d']} omega={wl['omega']:.4f}")
 
+    first_step_s = None
     for w in range(args.warmup):
+        tw = time.perf_counter()
         H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
+        if first_step_s is None:
+            first_step_s = time.perf_counter() - tw
         log(f"warmup {w}: iters {its.tolist()} setup {st['setup_ms']:.1f} ms apply {st['apply_ms']:.0f} ms")
         H.close()
         del u
@@ -221,13 +288,16 @@ def main():
            "matvec_ms": 0.0, "matvec_launches": 0, "matvec_rhs": 0,
            "kernel_ms": 0.0, "kernel_launches": 0, "kernel_rhs": 0}
     u_mix = None
+    step_s = []
     for k in range(args.steps):
+        ts = time.perf_counter()
         H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
+        step_s.append(time.perf_counter() - ts)
         for key in tot:
             tot[key] += st[key]
-        bpr, mvb, kbr = st["apply_bytes_per_rhs"], st["matvec_bytes_per_rhs"], st["kernel_bytes_per_rhs"]
+        kst = st
         info = H.info()
-        log(f"step {k}: iters {its.tolist()} relres max {rel.max():.2e} status {rc}")
+        log(f"step {k}: {step_s[-1]:.3f} s, iters {its.tolist()} relres max {rel.max():.2e} status {rc}")
         H.close()
         if k == args.steps - 1:
             u_mix, its_mix, rel_mix, rc_mix = u, its, rel, rc
@@ -236,11 +306,18 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec_per_step = (t1 - t0) / args.steps
+    if first_step_s is None:
+        first_step_s = step_s[0]
 
     apply_avg_ms = tot["apply_ms"] / max(tot["apply_launches"], 1)
-    # the dominant kernel (its two-chain launches)
-    kernel_avg_ms = tot["kernel_ms"] / max(tot["kernel_launches"], 1)
-    kernel_bytes_per_launch = kbr * tot["kernel_rhs"] / max(tot["kernel_launches"], 1)
+    # the dominant kernel (its two-chain launches), per launch
+    kl = max(tot["kernel_launches"], 1)
+    kernel_avg_ms = tot["kernel_ms"] / kl
+    rhs_per_launch = tot["kernel_rhs"] / kl
+    unique_bytes = kst["kernel_factor_bytes"] + kst["kernel_vector_bytes_per_rhs"] * rhs_per_launch
+    effective_bytes = kst["kernel_bytes_per_rhs"] * rhs_per_launch
+    flops = kst["kernel_flops_per_rhs"] * rhs_per_launch
+    achieved = unique_bytes / (kernel_avg_ms * 1e-3) / 1e9
     # each line's chain count as a handle of this configuration factors it (two-sided or x1
     # order), from a handle made after the timed region
     S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
@@ -251,9 +328,10 @@ def main():
     steps_per_sweep, steps_per_kernel = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner,
                                                         line_steps)
     Hq.close()
-    apply_bytes_per_launch = bpr * tot["apply_rhs"] / max(tot["apply_launches"], 1)
-    achieved = kernel_bytes_per_launch / (kernel_avg_ms * 1e-3) / 1e9
-    mv_gbs = mvb * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
+    mv_gbs = kst["matvec_bytes_per_rhs"] * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
+    # device time of the step's kernels, from the library's own event pairs (sweeps and
+    # matvecs) plus the setup; the rest is Krylov kernels and host work
+    kernels_ms = (tot["apply_ms"] + tot["matvec_ms"] + tot["setup_ms"]) / args.steps
 
     result = {
         "metric": METRIC,
@@ -282,33 +360,49 @@ def main():
                                + (f"{tot['kernel_launches'] // max(tot['apply_launches'], 1)} per sweep"
                                   + (": inner fronts forward / backward, one slab step each"
                                      if args.fronts_inner == 2 else "") + ")"),
-                     "avg_launch_ms": round(kernel_avg_ms, 3),
-                     "algorithmic_bytes_per_launch": kernel_bytes_per_launch,
-                     "chains_sharing_factor_stream": R,
-                     "frac_note": "achieved counts every right-hand side's factor reads; the right-hand "
-                                  "sides share one factor stream through L2, so it can exceed the HBM "
-                                  "peak (the HBM bytes actually moved are in traffic)"},
+                     "avg_launch_ms": round(kernel_avg_ms, 4),
+                     "algorithmic_bytes_per_launch": unique_bytes,
+                     "algorithmic_bytes_note": "the launch's factor blocks once per visit (its right-hand "
+                                               "sides share them) plus every right-hand side's input "
+                                               "read and output written",
+                     "effective_bytes_per_launch": effective_bytes,
+                     "effective_gbs": round(effective_bytes / (kernel_avg_ms * 1e-3) / 1e9, 1),
+                     "effective_note": "the factor stream counted once per right-hand side, as if "
+                                       "each chain streamed its own copy",
+                     "fp32_flops_per_launch": flops,
+                     "fp32_tflops": round(flops / (kernel_avg_ms * 1e-3) / 1e12, 2),
+                     "fp32_frac": round(flops / (kernel_avg_ms * 1e-3) / 157.3e12, 4),
+                     "rhs_per_launch": rhs_per_launch},
         "sweep_ms_per_apply": round(apply_avg_ms, 3),
-        "sweep_algorithmic_gbs_per_apply": round(apply_bytes_per_launch / (apply_avg_ms * 1e-3) / 1e9, 1),
         "ns_per_dependent_step": round(kernel_avg_ms * 1e6 / steps_per_kernel, 1),
         "dependent_steps_per_sweep": steps_per_sweep,
         "iters": its_mix.tolist(),
         "relres_max": float(rel_mix.max()),
+        "first_step_s": round(first_step_s, 4),
+        "step_s_min_max": [round(min(step_s), 4), round(max(step_s), 4)],
         "setup_ms": round(tot["setup_ms"] / args.steps, 2),
         "apply_ms_total_per_step": round(tot["apply_ms"] / args.steps, 1),
+        "matvec_ms_total_per_step": round(tot["matvec_ms"] / args.steps, 2),
+        "timed_kernels_frac_of_step": round(kernels_ms / (sec_per_step * 1e3), 3),
         "apply_launches_per_step": tot["apply_launches"] / args.steps,
         "matvec_gbs": round(mv_gbs, 1),
+        "device_pool_bytes": dict(zip(("cached", "live"), pool_stats())),
     }
     tr = measured_traffic(args.workload, wl, args.fronts, args.fronts_inner)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
-        # HBM bytes per launch (counters) over this run's average launch duration
+        result["roofline"]["traffic_ratio"] = round(tr["hbm_bytes_per_launch"] / unique_bytes, 3)
         result["roofline"]["traffic_gbs"] = round(tr["hbm_bytes_per_launch"] / (kernel_avg_ms * 1e-3) / 1e9, 1)
-        result["roofline"]["traffic_note"] = ("HBM bytes of one 32-right-hand-side launch of the kernel, "
-                                              "averaged over a sweep's launches (rocprofv3 FETCH_SIZE + "
-                                              "WRITE_SIZE, copy-calibrated), "
-                                              + os.path.relpath(tr["_path"], ROOT))
-    log(f"mixed: {sec_per_step:.3f} s/step, sweep {achieved:.0f} GB/s algorithmic")
+        result["roofline"]["traffic_note"] = ("HBM bytes of one launch of the kernel, averaged over a "
+                                              "sweep's launches (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                              "copy-calibrated); traffic_ratio = traffic / algorithmic "
+                                              "bytes, " + os.path.relpath(tr["_path"], ROOT))
+    ref = oracle_reference(args.workload, u_mix, args.fronts, args.fronts_inner)
+    if ref is not None:
+        result["oracle_reference"] = ref
+        log(f"mixed vs oracle reference (subsample): {ref['rel_l2_mixed_vs_oracle_max']:.2e}")
+    log(f"mixed: {sec_per_step:.3f} s/step (first {first_step_s:.3f} s), dominant kernel "
+        f"{achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.3f} of HBM peak)")
 
     if not args.no_fp64:
         log("fp64 path: one step with complex128 sweeps")
@@ -358,16 +452,17 @@ def main():
         a64 = st64["apply_bytes_per_rhs"] * st64["apply_rhs"] / max(st64["apply_ms"] * 1e-3, 1e-12) / 1e9
         result["fp64_path"] = {"s_per_step": round(t3 - t2, 4), "iters": its64.tolist(), "fronts": fr64,
                                "fronts_inner": fi64,
-                               "relres_max": float(rel64.max()), "sweep_gbs_algorithmic": round(a64, 1),
+                               "relres_max": float(rel64.max()), "sweep_gbs_effective": round(a64, 1),
                                "sweep_avg_launch_ms": round(st64["apply_ms"] / max(st64["apply_launches"], 1), 3)}
         result["rel_l2_mixed_vs_fp64_max"] = float(d.max())
         log(f"fp64: {t3 - t2:.3f} s/step; mixed vs fp64 rel-L2 max {float(d.max()):.2e}")
         del u64
 
-    if args.cpu_budget > 0:
-        est, sample = cpu_baseline(wl, its_mix, args.cpu_budget, args.fronts, args.fronts_inner)
-        result["cpu_baseline"] = {"value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
-                                  "sample": sample}
+    if not args.no_cpu:
+        log("cpu baseline: the oracle on a sample of the workload")
+        est, threads, sample, parts = cpu_baseline(wl, its_mix, args.fronts, args.fronts_inner)
+        result["cpu_baseline"] = {"value": round(est, 1), "unit": "s", "cores": threads, "kind": "oracle",
+                                  "sample": sample, "parts": parts}
         log(f"cpu oracle estimate {est:.0f} s/step")
     print(json.dumps(result), flush=True)
 

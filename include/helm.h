@@ -87,7 +87,9 @@ typedef struct {
  * has B <= 64, else by one chain in x1 order
  * (helm_line_factors).  One-chain blocks are limited to B <= 128 (complex64) or 96
  * (complex128), and n*B line values must fit in LDS.
- * Errors: HELM_EINVAL, HELM_ENOMEM (factor bytes > free memory), HELM_ESINGULAR, HELM_EHIP.
+ * Errors: HELM_EINVAL, HELM_ENOMEM (the planned bytes of helm_plan_bytes exceed the free
+ * device memory plus the pool's cached blocks; checked before anything is allocated),
+ * HELM_ESINGULAR, HELM_EHIP.
  * Synchronises `stream`.
  */
 int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const helm_pml* pml,
@@ -105,6 +107,8 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
  * middle line, inner fronts backward).
  *   r_dev, z_dev : R*n^3 complex128 each (may not alias).  In HELM_C64 mode r is rounded to
  *                  complex64 on entry and z is widened on exit.
+ * When paired line solves ran (helm_set_split), the call synchronises `stream` to read their
+ * error word and returns HELM_EHIP if one of them timed out (z then holds NaN there).
  */
 int helm_apply(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream);
 
@@ -135,6 +139,13 @@ int helm_matvec(helm_handle* h, const void* u_dev, void* y_dev, int R, int adjoi
  * true residual became non-finite (then relres_host holds NaN or inf for it; e.g. a
  * preconditioner whose complex64 values overflow), and HELM_EINVAL for a right-hand side
  * that is not finite.
+ * Memory: the Krylov bases (V complex128, Z complex64 in HELM_C64 mode, complex128
+ * otherwise) grow with the iterations, up to min(restart, maxit) vectors per right-hand side;
+ * their largest size (helm_workspace_bytes) is checked against the free device memory before
+ * anything is allocated and gives HELM_ENOMEM if it does not fit.  The workspace comes from
+ * the library's memory pool and returns to it (helm_pool_trim).
+ * Errors also: HELM_EHIP when a paired line solve of the sweep timed out (a fault elsewhere;
+ * see helm_set_split).
  * Synchronises `stream`.
  */
 int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol, int restart,
@@ -189,6 +200,30 @@ int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host,
  * Any output pointer may be NULL.
  */
 int helm_info(const helm_handle* h, size_t* factor_bytes, int* n_lines, int* max_block);
+
+/*
+ * helm_workspace_bytes -- device memory beyond the handle's own (helm_info) that calls on it
+ * may take, computed on the host: *apply_bytes for helm_apply / helm_apply_adjoint of R
+ * right-hand sides (slab iterates of the sweep and the exchange slots of paired line solves),
+ * *solve_bytes for helm_solve(R, restart, maxit) at most (those plus the Krylov bases of
+ * min(restart, maxit) iterations and the Arnoldi scalars).  Either pointer may be NULL.
+ * Errors: HELM_EINVAL (h NULL, R < 1, restart outside [1, 200], maxit < 0).
+ */
+int helm_workspace_bytes(const helm_handle* h, int R, int restart, int maxit, size_t* solve_bytes,
+                         size_t* apply_bytes);
+
+/*
+ * Device memory pool.  Every device buffer of the library (handles' factors and
+ * coefficients, sweep scratch, Krylov bases) is taken from a process-wide pool and returned
+ * to it when freed, so repeated setups and solves of similar sizes reuse memory instead of
+ * asking the HIP runtime each time.  A block returned on one stream and reused on another
+ * waits for the first stream's work.  When the runtime cannot satisfy a request, the cached
+ * blocks of that device are released and the request retried.
+ * helm_pool_trim -- release every cached (unused) block to the HIP runtime.
+ * helm_pool_stats -- bytes cached (free, held by the pool) and in use; NULL pointers skipped.
+ */
+void helm_pool_trim(void);
+void helm_pool_stats(size_t* cached_bytes, size_t* live_bytes);
 
 /*
  * helm_plan_bytes -- device bytes helm_setup would allocate for these parameters (factors +
@@ -283,10 +318,16 @@ typedef struct {
   long long kernel_launches;
   long long kernel_rhs;
   double kernel_ms;
-  double kernel_bytes_per_rhs; /* algorithmic bytes of one such launch per right-hand side,   */
-                               /* averaged over a sweep's launches: factor bytes of its line  */
-                               /* solves plus 16 bytes per grid point it reads as input and   */
-                               /* 16 per point it writes as output                            */
+  double kernel_bytes_per_rhs; /* effective bytes of one such launch per right-hand side,     */
+                               /* averaged over a sweep's launches: the factor bytes of its   */
+                               /* line solves plus 16 bytes per grid point it reads as input  */
+                               /* and 16 per point it writes as output; counts the factor     */
+                               /* stream once per right-hand side                             */
+  double kernel_factor_bytes;  /* factor bytes of one such launch, counted once (the          */
+                               /* right-hand sides of a launch share one factor stream)       */
+  double kernel_vector_bytes_per_rhs; /* its input and output bytes per right-hand side       */
+  double kernel_flops_per_rhs; /* useful real flops of one such launch per right-hand side:   */
+                               /* 8 per factor entry visited (one complex multiply-add)       */
 } helm_stats;
 
 /* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */

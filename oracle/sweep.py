@@ -226,7 +226,9 @@ class RecursiveSweep:
     by the auxiliary problem padded on its eliminated side(s) (``partition.window_fronts``);
     forward, the two fronts carry f - A u from their eliminated neighbour and the middle group
     takes both; backward, each front subtracts the correction from the neighbour nearer the
-    middle.  The inner sweep is the single-front Algorithm 4 either way."""
+    middle.  The inner sweep is Algorithm 4 from the x2 = 0 face, or with
+    ``prob.fronts_inner == 2`` from both x2-faces in the same block order one level down
+    (``SlabSweep.apply``), independently of the outer choice."""
 
     def __init__(self, prob):
         self.prob = prob

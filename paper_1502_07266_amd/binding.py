@@ -32,7 +32,8 @@ class helm_stats(ctypes.Structure):
                 ("matvec_rhs", ctypes.c_longlong), ("matvec_ms", ctypes.c_double),
                 ("matvec_bytes_per_rhs", ctypes.c_double), ("kernel_launches", ctypes.c_longlong),
                 ("kernel_rhs", ctypes.c_longlong), ("kernel_ms", ctypes.c_double),
-                ("kernel_bytes_per_rhs", ctypes.c_double)]
+                ("kernel_bytes_per_rhs", ctypes.c_double), ("kernel_factor_bytes", ctypes.c_double),
+                ("kernel_vector_bytes_per_rhs", ctypes.c_double), ("kernel_flops_per_rhs", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -50,6 +51,10 @@ _SIGS = {
     "helm_set_medium": (_I, [_P, _P, _P]),
     "helm_update_medium": (_I, [_P, _P, _P, _P, _P]),
     "helm_info": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "helm_workspace_bytes": (_I, [_P, _I, _I, _I, ctypes.POINTER(ctypes.c_size_t),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "helm_pool_trim": (None, []),
+    "helm_pool_stats": (None, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "helm_plan_bytes": (_I, [ctypes.POINTER(helm_grid), ctypes.POINTER(helm_pml), _I, _I,
                              ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
@@ -114,6 +119,18 @@ def plan_bytes(n, b, C, p, slab_layers=1, prec=HELM_C64, fronts=1, fronts_inner=
                                  slab_layers, prec, ctypes.byref(nb), ctypes.byref(nl),
                                  ctypes.byref(mb)), "helm_plan_bytes")
     return nb.value, nl.value, mb.value
+
+
+def pool_stats():
+    """(bytes cached by the library's device memory pool, bytes in use)."""
+    c, l = ctypes.c_size_t(), ctypes.c_size_t()
+    lib().helm_pool_stats(ctypes.byref(c), ctypes.byref(l))
+    return c.value, l.value
+
+
+def pool_trim():
+    """Release the pool's cached device memory to the HIP runtime."""
+    lib().helm_pool_trim()
 
 
 class Helm:
@@ -233,6 +250,13 @@ class Helm:
         _check(lib().helm_info(self.handle, ctypes.byref(fb), ctypes.byref(nl), ctypes.byref(mb)),
                "helm_info")
         return {"factor_bytes": fb.value, "n_lines": nl.value, "max_block": mb.value}
+
+    def workspace_bytes(self, R, restart=50, maxit=500):
+        """{"solve": bytes a solve may take at most, "apply": bytes of an apply's scratch}."""
+        sb, ab = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().helm_workspace_bytes(self.handle, int(R), int(restart), int(maxit), ctypes.byref(sb),
+                                          ctypes.byref(ab)), "helm_workspace_bytes")
+        return {"solve": sb.value, "apply": ab.value}
 
     def line_factors(self, zg, yg):
         """The block inverses T_1..T_n of line (zg, yg): tensor (n, B, B)."""

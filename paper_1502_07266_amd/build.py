@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhelm.so")
 
-SOURCES = ["api.hip", "plan.cpp", "coeffs.hip", "setup.hip", "sweep.hip", "stencil.hip", "krylov.hip"]
+SOURCES = ["api.hip", "plan.cpp", "pool.cpp", "coeffs.hip", "setup.hip", "sweep.hip", "stencil.hip",
+           "krylov.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -76,18 +76,24 @@ double sweep_bytes_per_rhs(const Plan& p, int prec) {
 }
 
 // the same for one launch of the dominant kernel (the two-chain launches of sweep_schedule),
-// averaged over its launches in one sweep: the factor bytes of the line solves of a launch,
-// plus 16 bytes per grid point of its slabs' rows for reading the input and 16 for writing
-// the output, each counted in the launch that does it (an inner-front forward launch reads
-// the input on its lines' rows, the backward one writes the output there; a launch that runs
-// whole inner sweeps does both on every row)
-double kernel_bytes_per_rhs(const Plan& p, int prec) {
-  double total = 0.0;
+// averaged over its launches in one sweep: the factor bytes of the line solves of a launch
+// (every block visit reads B*B entries), and per right-hand side 16 bytes per grid point of
+// its slabs' rows for reading the input and 16 for writing the output, each counted in the
+// launch that does it (an inner-front forward launch reads the input on its lines' rows, the
+// backward one writes the output there; a launch that runs whole inner sweeps does both on
+// every row).  factor: the factor bytes once per launch (the right-hand sides of a launch
+// share one factor stream); vec: the vector bytes of one right-hand side; entries: factor
+// entries visited (one complex multiply-add, 8 real flops, per entry and right-hand side).
+struct KernelWork {
+  double factor = 0.0, vec = 0.0, entries = 0.0;
+};
+KernelWork kernel_work(const Plan& p, int prec) {
+  KernelWork w;
   int launches = 0;
   for (const SweepLaunch& L : sweep_schedule(p)) {
     if (!L.timed) continue;
     ++launches;
-    double fac = 0.0, pts = 0.0;
+    double ent = 0.0, pts = 0.0;
     const int io = L.ipass == 0 ? 32 : 16;
     for (int fr = 0; fr < L.nfront; ++fr) {
       const int cnt = std::min(L.slab_hi, sweep_count(L.pass, p.Gz, p.zmid, fr));
@@ -100,7 +106,7 @@ double kernel_bytes_per_rhs(const Plan& p, int prec) {
           for (int k = 0; k < lc; ++k) {
             const int l = sweep_at(L.ipass, p.Gy, p.ymid, inf, k).x;
             const double B = p.line_B[(size_t)g * p.Gy + l];
-            fac += 2.0 * p.n * B * B;
+            ent += 2.0 * p.n * B * B;
             if (L.ipass != 0) rows += p.yg(l).last - p.yg(l).first + 1;
           }
         }
@@ -108,9 +114,16 @@ double kernel_bytes_per_rhs(const Plan& p, int prec) {
         pts += (double)p.n * rows * nph;
       }
     }
-    total += fac * csize(prec) + pts * io;
+    w.factor += ent * csize(prec);
+    w.vec += pts * io;
+    w.entries += ent;
   }
-  return launches ? total / launches : 0.0;
+  if (launches) {
+    w.factor /= launches;
+    w.vec /= launches;
+    w.entries /= launches;
+  }
+  return w;
 }
 
 void release(helm_handle* h) {
@@ -121,7 +134,7 @@ void release(helm_handle* h) {
                   h->d_setup_lines, h->d_line_one, h->factors, h->d_err, h->slab_scratch,
                   h->d_rhs_idx, h->xbuf};
   for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, h->last_stream);
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -165,8 +178,8 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   Plan plan;
   int rc = validate(grid, pml, slab_layers, prec, plan);
   if (rc != HELM_OK) return rc;
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(HELM_EHIP, "hipMemGetInfo failed");
+  size_t free_b = 0;
+  if (device_free_bytes(&free_b) != hipSuccess) return fail(HELM_EHIP, "hipMemGetInfo failed");
   const size_t need = planned_bytes(plan, prec);
   if (need > free_b)
     return fail(HELM_ENOMEM, "setup needs " + std::to_string(need) + " bytes, " +
@@ -182,14 +195,15 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   (void)hipGetDevice(&h->device);
   const size_t N = (size_t)plan.n * plan.n * plan.n;
   hipStream_t s = S(stream);
+  h->last_stream = s;
   auto bail = [&](int code, const std::string& m) {
     release(h);
     delete h;
     return fail(code, m);
   };
 #define ALLOC(ptr, bytes)                                                             \
-  if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess)                               \
-    return bail(HELM_ENOMEM, std::string("hipMalloc failed for ") + #ptr);
+  if (pool_alloc((void**)&(ptr), (bytes), s) != hipSuccess)                           \
+    return bail(HELM_ENOMEM, std::string("device allocation failed for ") + #ptr);
   ALLOC(h->kappa, N * sizeof(double));
   ALLOC(h->sbd, (size_t)(2 * (plan.n + 1) + 1) * sizeof(double2));
   ALLOC(h->smv, (size_t)(2 * plan.p + 2) * sizeof(double2));
@@ -219,7 +233,11 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
       hipStreamSynchronize(s) != hipSuccess)   // the host vector goes out of scope
     return bail(HELM_EHIP, "copying the plan failed");
   h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
-  h->kernel_bytes_per_rhs = kernel_bytes_per_rhs(plan, prec);
+  const KernelWork kw = kernel_work(plan, prec);
+  h->kernel_bytes_per_rhs = kw.factor + kw.vec;
+  h->kernel_factor_bytes = kw.factor;
+  h->kernel_vector_bytes_per_rhs = kw.vec;
+  h->kernel_flops_per_rhs = 8.0 * kw.entries;
   LaunchTimer t_setup;
   hipEvent_t ev = t_setup.begin(s);
   if (launch_coefficients(h, c_dev, true, s) != hipSuccess) return bail(HELM_EHIP, "coefficient kernels failed");
@@ -249,11 +267,23 @@ static int check_batch(helm_handle* h, const void* a, const void* b, int R) {
   return HELM_OK;
 }
 
+// the error word of the paired line solves: a member that gave up waiting for its partner
+// (possible only after a fault elsewhere) has written NaN into its line solution
+static int check_exchange(helm_handle* h, hipStream_t s) {
+  int bad = 0;
+  HIP_TRY(take_exchange_error(h, s, &bad));
+  if (bad) return fail(HELM_EHIP, "a paired line solve of the sweep timed out waiting for its partner");
+  return HELM_OK;
+}
+
 static int apply_impl(helm_handle* h, const void* r, void* z, int R, bool adjoint, void* stream) {
   int rc = check_batch(h, r, z, R);
   if (rc != HELM_OK) return rc;
   const long long N = (long long)h->n * h->n * h->n;
-  HIP_TRY(launch_apply(h, r, true, N, z, true, N, R, nullptr, adjoint, S(stream)));
+  hipStream_t s = S(stream);
+  h->last_stream = s;
+  HIP_TRY(launch_apply(h, r, true, N, z, true, N, R, nullptr, adjoint, s));
+  if (h->pairs_used) return check_exchange(h, s);
   return HELM_OK;
 }
 
@@ -280,13 +310,16 @@ int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol
   if (rc != HELM_OK) return rc;
   if (!(tol > 0.0)) return fail(HELM_EINVAL, "tol must be > 0");
   if (maxit < 0) return fail(HELM_EINVAL, "maxit must be >= 0");
+  hipStream_t s = S(stream);
+  h->last_stream = s;
   std::string msg;
   rc = fgmres_solve(h, (const double2*)f_dev, (double2*)u_dev, R, tol, restart, maxit, adjoint != 0,
-                    iters_host, relres_host, S(stream), msg);
+                    iters_host, relres_host, s, msg);
+  // the error word is taken (and cleared) on every exit: a timed-out exchange is reported by
+  // the call whose sweeps it spoiled, and never by a later one
+  const int xrc = check_exchange(h, s);
   if (rc < 0) return fail(rc, msg);
-  int bad = 0;
-  HIP_TRY(take_exchange_error(h, &bad));
-  if (bad) return fail(HELM_EHIP, "a paired line solve of the sweep timed out waiting for its partner");
+  if (xrc != HELM_OK) return xrc;
   if (rc != HELM_OK && !msg.empty()) g_last_error = msg;
   return rc;
 }
@@ -307,16 +340,16 @@ int helm_misfit(helm_handle* h, const void* u_dev, const void* d_dev, int R, int
   if (plane_k < 1 || plane_k > h->n) return fail(HELM_EINVAL, "plane_k must be in [1, n]");
   hipStream_t s = S(stream);
   double* J_dev = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&J_dev, sizeof(double), s));
+  h->last_stream = s;
+  HIP_TRY(pool_alloc((void**)&J_dev, sizeof(double), s));
   hipError_t e = launch_misfit(h, (const double2*)u_dev, (const double2*)d_dev, R, plane_k, J_dev,
                                (double2*)g_dev, s);
   if (e == hipSuccess && J_host) {
     e = hipMemcpyAsync(J_host, J_dev, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  hipError_t e2 = hipFreeAsync(J_dev, s);
+  pool_free(J_dev, s);
   HIP_TRY(e);
-  HIP_TRY(e2);
   return HELM_OK;
 }
 
@@ -371,6 +404,17 @@ int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host,
   h->setup_ms = t.ms;
   if (n_refactored) *n_refactored = (int)lines.size();
   if (err[0]) return fail(HELM_ESINGULAR, "singular block in line " + std::to_string(err[1]));
+  return HELM_OK;
+}
+
+int helm_workspace_bytes(const helm_handle* h, int R, int restart, int maxit, size_t* solve_bytes,
+                         size_t* apply_bytes) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (R < 1 || restart < 1 || restart > 200 || maxit < 0)
+    return fail(HELM_EINVAL, "need R >= 1, 1 <= restart <= 200, maxit >= 0");
+  const size_t ab = apply_scratch_bytes(h, R);
+  if (apply_bytes) *apply_bytes = ab;
+  if (solve_bytes) *solve_bytes = fgmres_bytes(h, R, restart, maxit) + ab;
   return HELM_OK;
 }
 
@@ -470,10 +514,10 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
   const int B = P.line_B[(size_t)g * P.Gy + l];
   const size_t elems = (size_t)h->n * B;
   double2 *r = nullptr, *x = nullptr;
-  HIP_TRY(hipMalloc((void**)&r, elems * sizeof(double2)));
-  if (hipMalloc((void**)&x, elems * sizeof(double2)) != hipSuccess) {
-    (void)hipFree(r);
-    return fail(HELM_EHIP, "autotune buffer allocation failed");
+  HIP_TRY(pool_alloc((void**)&r, elems * sizeof(double2), s));
+  if (pool_alloc((void**)&x, elems * sizeof(double2), s) != hipSuccess) {
+    pool_free(r, s);
+    return fail(HELM_ENOMEM, "autotune buffer allocation failed");
   }
   (void)hipMemsetAsync(r, 0, elems * sizeof(double2), s);
   const int saved = h->lanes_override;
@@ -504,8 +548,8 @@ int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
   }
-  (void)hipFree(r);
-  (void)hipFree(x);
+  pool_free(r, s);
+  pool_free(x, s);
   if (!best) {
     h->lanes_override = saved;
     return fail(HELM_EHIP, "no launch shape could be timed");
@@ -542,6 +586,9 @@ int helm_get_stats(helm_handle* h, helm_stats* out) {
   out->kernel_rhs = h->t_kernel.rhs;
   out->kernel_ms = h->t_kernel.ms;
   out->kernel_bytes_per_rhs = h->kernel_bytes_per_rhs;
+  out->kernel_factor_bytes = h->kernel_factor_bytes;
+  out->kernel_vector_bytes_per_rhs = h->kernel_vector_bytes_per_rhs;
+  out->kernel_flops_per_rhs = h->kernel_flops_per_rhs;
   return HELM_OK;
 }
 

@@ -240,6 +240,7 @@ struct helm_handle {
   double setup_ms = 0.0;
   double apply_bytes_per_rhs = 0.0;
   double kernel_bytes_per_rhs = 0.0;
+  double kernel_factor_bytes = 0.0, kernel_vector_bytes_per_rhs = 0.0, kernel_flops_per_rhs = 0.0;
 
   // apply workspace (grown on demand)
   void* slab_scratch = nullptr;
@@ -250,16 +251,20 @@ struct helm_handle {
   void* xbuf = nullptr;
   size_t xpairs = 0;
   unsigned long long xseq = 0;
+  bool pairs_used = false;         // a paired launch ran since the error word was last taken
   int* d_rhs_idx = nullptr;
   int rhs_idx_cap = 0;
+  // the stream of the last call: the handle's buffers go back to the pool on it
+  hipStream_t last_stream = nullptr;
 };
 
 // layout of helm_handle::xbuf: an error word (padded), then per pair, chain and line parity a
 // slot of kZMax values of up to four 32-bit pieces, one tagged 64-bit word each
 constexpr size_t kXHead = 256;
 constexpr size_t kXSlot = (size_t)kZMax * 4;
-// nonzero if a paired line solve gave up waiting for its partner since the last call (clears it)
-hipError_t take_exchange_error(helm_handle* h, int* bad);
+// waits for stream s, then *bad = nonzero if a paired line solve gave up waiting for its
+// partner since the flag was last taken (and clears it)
+hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad);
 
 // ---------------------------------------------------------------------------------------
 // internal launchers (all asynchronous on `stream`)
@@ -283,6 +288,8 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
                         hipStream_t s);
+// device scratch of an apply of R right-hand sides (slab iterates and exchange slots)
+size_t apply_scratch_bytes(const helm_handle* h, int R);
 hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, double2* x, int R,
                              bool adjoint, hipStream_t s);
 // y = A u (mode 0) or y = f - A u (mode 1); u complex128 or complex64 (u64 = false)
@@ -293,10 +300,20 @@ hipError_t launch_grad(helm_handle* h, const double2* u, const double2* lam, int
                        hipStream_t s);
 hipError_t launch_misfit(helm_handle* h, const double2* u, const double2* d, int R, int plane_k,
                         double* J_dev, double2* g, hipStream_t s);
+// device bytes a solve of R right-hand sides may take at most (its Krylov bases are grown as
+// the iterations need them, up to min(restart, maxit) vectors)
+size_t fgmres_bytes(const helm_handle* h, int R, int restart, int maxit);
 int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol, int restart,
                  int maxit, bool adjoint, int* iters, double* relres, hipStream_t s, std::string& msg);
 
 void set_error(const std::string& msg);
+
+// device memory of the library (pool.cpp): a process-wide cache of blocks keyed by size,
+// stream-ordered (a block returned on one stream and reused on another waits for the first)
+hipError_t pool_alloc(void** out, size_t bytes, hipStream_t s);
+void pool_free(void* p, hipStream_t s);
+// free device memory plus the pool's cached bytes on the current device
+hipError_t device_free_bytes(size_t* avail);
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \

@@ -41,10 +41,34 @@ __device__ inline double2 block_sum(double2 v, double2* red) {
   return s;
 }
 
+// Krylov bases are allocated kChunk vectors at a time as the iterations need them (a solve
+// that converges in 7 iterations never holds the restart length's worth of vectors); within a
+// chunk the vectors of all R right-hand sides are stored k-major: vector k of right-hand side
+// q starts at c[k / kChunk] + ((k % kChunk) R + q) N.
+constexpr int kChunk = 4;
+constexpr int kMaxChunks = (kMaxRestart + 1 + kChunk - 1) / kChunk;
+
+template <typename T> struct Basis {
+  T* c[kMaxChunks];
+  long long N;
+  int R;
+  __host__ __device__ __forceinline__ T* at(int k, int q) const {
+    return c[k / kChunk] + ((long long)(k % kChunk) * R + q) * N;
+  }
+};
+
+// a basis holding one vector per right-hand side, R vectors of N values at v
+template <typename T> Basis<T> single(T* v, int R, long long N) {
+  Basis<T> b{};
+  b.c[0] = v;
+  b.N = N;
+  b.R = R;
+  return b;
+}
+
 // partial[(a*K + k)*nchunk + chunk] = sum over the chunk of conj(X_k) w, for the active vector a
 template <typename TX>
-__global__ void __launch_bounds__(kDotThreads) k_dots(const TX* __restrict__ X, long long xr,
-                                                      long long xk, int K,
+__global__ void __launch_bounds__(kDotThreads) k_dots(Basis<TX> X, int K,
                                                       const double2* __restrict__ w, long long wr,
                                                       const int* __restrict__ idx,
                                                       double2* __restrict__ partial, int nchunk,
@@ -59,7 +83,7 @@ __global__ void __launch_bounds__(kDotThreads) k_dots(const TX* __restrict__ X, 
     wv[t] = e < N ? w[(long long)q * wr + e] : make_double2(0.0, 0.0);
   }
   for (int k = 0; k < K; ++k) {
-    const TX* xp = X + (long long)q * xr + (long long)k * xk;
+    const TX* xp = X.at(k, q);
     double2 s = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < kDotPerThread; ++t) {
@@ -89,8 +113,7 @@ __global__ void k_dots_final(const double2* __restrict__ partial, int K, int nch
 // y_q += sign * sum_{k < K_q} coef[q][k] X_{q,k}
 template <typename TX>
 __global__ void __launch_bounds__(256) k_axpy_multi(double2* __restrict__ y, long long yr,
-                                                    const TX* __restrict__ X, long long xr,
-                                                    long long xk, const double2* __restrict__ coef,
+                                                    Basis<TX> X, const double2* __restrict__ coef,
                                                     int cstride, int K, const int* __restrict__ kq,
                                                     double sign, const int* __restrict__ idx,
                                                     long long N) {
@@ -105,8 +128,7 @@ __global__ void __launch_bounds__(256) k_axpy_multi(double2* __restrict__ y, lon
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   double2 acc = y[(long long)q * yr + e];
-  const TX* xp = X + (long long)q * xr + e;
-  for (int k = 0; k < Kq; ++k) acc = cfma(acc, c[k], cvt<double2>(xp[(long long)k * xk]));
+  for (int k = 0; k < Kq; ++k) acc = cfma(acc, c[k], cvt<double2>(X.at(k, q)[e]));
   y[(long long)q * yr + e] = acc;
 }
 
@@ -200,26 +222,50 @@ __global__ void k_trisolve(int m, const double2* H, const double2* g, const int*
   }
 }
 
+// Device workspace of one solve, taken from the library's pool (pool.cpp) and returned to it
+// at the end, so that consecutive solves of the same size reuse the same memory.
 struct Workspace {
-  double2 *V = nullptr, *W = nullptr, *partial = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr;
+  hipStream_t s = nullptr;
+  double2 *W = nullptr, *partial = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr;
   double2 *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *ycoef = nullptr, *fnrm = nullptr;
-  void* Z = nullptr;
   double *cs = nullptr, *resid = nullptr;
   int *idx = nullptr, *kq = nullptr;
+  Basis<double2> V{};
+  Basis<float2> Z64{};     // mixed mode: the preconditioned directions in complex64
+  Basis<double2> Z128{};
+  int nv = 0, nz = 0;      // chunks held
   std::vector<void*> all;
   ~Workspace() {
-    for (void* p : all) (void)hipFree(p);
+    for (void* p : all) pool_free(p, s);
   }
   template <typename T> hipError_t get(T** p, size_t count) {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    hipError_t e = pool_alloc(&q, std::max<size_t>(count, 1) * sizeof(T), s);
     if (e == hipSuccess) {
       all.push_back(q);
       *p = (T*)q;
     }
     return e;
   }
+  // makes V hold vectors 0..kv and Z vectors 0..kz - 1
+  hipError_t grow(int kv, int kz, bool c64) {
+    while (nv * kChunk <= kv) {
+      hipError_t e = get(&V.c[nv], (size_t)kChunk * V.R * V.N);
+      if (e != hipSuccess) return e;
+      ++nv;
+    }
+    while (nz * kChunk < kz) {
+      hipError_t e = c64 ? get(&Z64.c[nz], (size_t)kChunk * Z64.R * Z64.N)
+                         : get(&Z128.c[nz], (size_t)kChunk * Z128.R * Z128.N);
+      if (e != hipSuccess) return e;
+      ++nz;
+    }
+    return hipSuccess;
+  }
 };
+
+// chunks of kChunk vectors that hold k vectors
+inline long long chunks_for(long long k) { return (k + kChunk - 1) / kChunk; }
 
 }  // namespace
 
@@ -231,6 +277,20 @@ struct Workspace {
       return HELM_EHIP;                                                 \
     }                                                                   \
   } while (0)
+
+size_t fgmres_bytes(const helm_handle* h, int R, int restart, int maxit) {
+  const long long N = (long long)h->n * h->n * h->n;
+  const long long kmax = std::max(0, std::min(restart, maxit));
+  const size_t zsz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
+  const long long nchunk = (N + kDotChunk - 1) / kDotChunk;
+  size_t b = (size_t)chunks_for(kmax + 1) * kChunk * R * N * sizeof(double2) +   // V
+             (size_t)chunks_for(kmax) * kChunk * R * N * zsz +                      // Z
+             (size_t)R * N * sizeof(double2) +                                       // W
+             (size_t)R * (restart + 1) * nchunk * sizeof(double2);                   // partial sums
+  // Hessenberg matrices, rotations and the per-right-hand-side scalars
+  b += (size_t)R * ((restart + 1) * (restart + 4) + 3 * restart + 4) * sizeof(double2);
+  return b;
+}
 
 int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol, int restart,
                  int maxit, bool adjoint, int* iters, double* relres, hipStream_t s,
@@ -244,31 +304,44 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
   const bool c64 = h->prec == HELM_C64;
   const int nchunk = (int)((N + kDotChunk - 1) / kDotChunk);
   const unsigned nb = (unsigned)((N + 255) / 256);
-  Workspace ws;
-  HIP_MSG(ws.get(&ws.V, (size_t)R * (m + 1) * N));
-  if (c64) {
-    float2* z = nullptr;
-    HIP_MSG(ws.get(&z, (size_t)R * m * N));
-    ws.Z = z;
-  } else {
-    double2* z = nullptr;
-    HIP_MSG(ws.get(&z, (size_t)R * m * N));
-    ws.Z = z;
+  // planned before anything is allocated: the bases of the longest cycle maxit allows
+  {
+    size_t avail = 0;
+    HIP_MSG(device_free_bytes(&avail));
+    const size_t need = fgmres_bytes(h, R, restart, maxit);
+    if (need > avail) {
+      msg = "the solve needs up to " + std::to_string(need) + " bytes of device memory (Krylov "
+            "bases of min(restart, maxit) iterations for " + std::to_string(R) +
+            " right-hand sides), " + std::to_string(avail) + " available";
+      return HELM_ENOMEM;
+    }
   }
-  HIP_MSG(ws.get(&ws.W, (size_t)R * N));
-  HIP_MSG(ws.get(&ws.partial, (size_t)R * (m + 1) * nchunk));
-  HIP_MSG(ws.get(&ws.H, (size_t)R * (m + 1) * m));
-  HIP_MSG(ws.get(&ws.sn, (size_t)R * m));
-  HIP_MSG(ws.get(&ws.cs, (size_t)R * m));
-  HIP_MSG(ws.get(&ws.g, (size_t)R * (m + 1)));
-  HIP_MSG(ws.get(&ws.h1, (size_t)R * (m + 1)));
-  HIP_MSG(ws.get(&ws.h2, (size_t)R * (m + 1)));
-  HIP_MSG(ws.get(&ws.nrm, (size_t)R));
-  HIP_MSG(ws.get(&ws.fnrm, (size_t)R));
-  HIP_MSG(ws.get(&ws.ycoef, (size_t)R * m));
-  HIP_MSG(ws.get(&ws.resid, (size_t)R));
-  HIP_MSG(ws.get(&ws.idx, (size_t)R));
-  HIP_MSG(ws.get(&ws.kq, (size_t)R));
+  Workspace ws;
+  ws.s = s;
+  ws.V.N = ws.Z64.N = ws.Z128.N = N;
+  ws.V.R = ws.Z64.R = ws.Z128.R = R;
+#define WS_GET(ptr, count)                                                           \
+  do {                                                                               \
+    if (ws.get(&(ptr), (count)) != hipSuccess) {                                     \
+      msg = "device allocation failed for the Krylov workspace";                     \
+      return HELM_ENOMEM;                                                            \
+    }                                                                                \
+  } while (0)
+  WS_GET(ws.W, (size_t)R * N);
+  WS_GET(ws.partial, (size_t)R * (m + 1) * nchunk);
+  WS_GET(ws.H, (size_t)R * (m + 1) * m);
+  WS_GET(ws.sn, (size_t)R * m);
+  WS_GET(ws.cs, (size_t)R * m);
+  WS_GET(ws.g, (size_t)R * (m + 1));
+  WS_GET(ws.h1, (size_t)R * (m + 1));
+  WS_GET(ws.h2, (size_t)R * (m + 1));
+  WS_GET(ws.nrm, (size_t)R);
+  WS_GET(ws.fnrm, (size_t)R);
+  WS_GET(ws.ycoef, (size_t)R * m);
+  WS_GET(ws.resid, (size_t)R);
+  WS_GET(ws.idx, (size_t)R);
+  WS_GET(ws.kq, (size_t)R);
+#undef WS_GET
 
   std::vector<int> its(R, 0), kq(R, 0);
   std::vector<double> fn(R), beta(R), res(R);
@@ -278,10 +351,11 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
   auto upload = [&](const std::vector<int>& v) -> hipError_t {
     return hipMemcpyAsync(ws.idx, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s);
   };
-  // norms of the batch (X = w)
+  // norms of the batch w (R vectors of N values)
   auto norms = [&](const double2* w, const std::vector<int>& a, double2* out) -> hipError_t {
     dim3 gd(nchunk, (unsigned)a.size());
-    k_dots<double2><<<gd, kDotThreads, 0, s>>>(w, N, 0, 1, w, N, ws.idx, ws.partial, nchunk, N);
+    k_dots<double2><<<gd, kDotThreads, 0, s>>>(single(const_cast<double2*>(w), R, N), 1, w, N, ws.idx,
+                                               ws.partial, nchunk, N);
     k_dots_final<<<(unsigned)a.size(), 64, 0, s>>>(ws.partial, 1, nchunk, ws.idx, out, 1, 1);
     return hipGetLastError();
   };
@@ -301,7 +375,6 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
     }
   }
 
-  const long long Vr = (long long)(m + 1) * N, Zr = (long long)m * N;
   int status = HELM_OK;
   const bool verbose = std::getenv("HELM_VERBOSE") != nullptr;
   while (true) {
@@ -339,36 +412,38 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
     act = next;
     HIP_MSG(upload(act));
     const unsigned na = (unsigned)act.size();
+    if (ws.grow(0, 0, c64) != hipSuccess) {
+      msg = "device allocation failed for the Krylov basis";
+      return HELM_ENOMEM;
+    }
     // V_0 = r / beta, g = (beta, 0, ...)
-    k_scale<<<dim3(nb, na), 256, 0, s>>>(ws.V, Vr, ws.W, N, ws.nrm, ws.idx, N);
+    k_scale<<<dim3(nb, na), 256, 0, s>>>(ws.V.at(0, 0), N, ws.W, N, ws.nrm, ws.idx, N);
     k_cycle_init<<<(na + 63) / 64, 64, 0, s>>>(ws.g, m + 1, ws.nrm, ws.idx, (int)na);
     HIP_MSG(hipGetLastError());
     std::vector<int> cycle_set = act;
     for (int q : cycle_set) kq[q] = 0;
     for (int j = 0; j < m && !act.empty(); ++j) {
       const unsigned a = (unsigned)act.size();
+      if (ws.grow(j + 1, j + 1, c64) != hipSuccess) {
+        msg = "device allocation failed for the Krylov basis";
+        return HELM_ENOMEM;
+      }
+      void* zj = c64 ? (void*)ws.Z64.at(j, 0) : (void*)ws.Z128.at(j, 0);
       // z_j = M^{-1} v_j
-      HIP_MSG(launch_apply(h, ws.V + (long long)j * N, true, Vr,
-                           c64 ? (void*)((float2*)ws.Z + (long long)j * N)
-                               : (void*)((double2*)ws.Z + (long long)j * N),
-                           !c64, Zr, (int)a, ws.idx, adjoint, s));
+      HIP_MSG(launch_apply(h, ws.V.at(j, 0), true, N, zj, !c64, N, (int)a, ws.idx, adjoint, s));
       // w = A z_j
-      HIP_MSG(launch_matvec(h,
-                            c64 ? (const void*)((float2*)ws.Z + (long long)j * N)
-                                : (const void*)((double2*)ws.Z + (long long)j * N),
-                            !c64, nullptr, ws.W, (int)a, ws.idx, Zr, N, adjoint, 0, s));
+      HIP_MSG(launch_matvec(h, zj, !c64, nullptr, ws.W, (int)a, ws.idx, N, N, adjoint, 0, s));
       // two classical Gram-Schmidt passes
       for (int pass = 0; pass < 2; ++pass) {
         double2* hp = pass == 0 ? ws.h1 : ws.h2;
-        k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, Vr, N, j + 1, ws.W, N,
-                                                                ws.idx, ws.partial, nchunk, N);
+        k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, j + 1, ws.W, N, ws.idx,
+                                                                ws.partial, nchunk, N);
         k_dots_final<<<a, 64, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, hp, m + 1, 0);
-        k_axpy_multi<double2><<<dim3(nb, a), 256, 0, s>>>(ws.W, N, ws.V, Vr, N, hp, m + 1, j + 1,
-                                                          nullptr, -1.0, ws.idx, N);
+        k_axpy_multi<double2><<<dim3(nb, a), 256, 0, s>>>(ws.W, N, ws.V, hp, m + 1, j + 1, nullptr,
+                                                          -1.0, ws.idx, N);
       }
       HIP_MSG(norms(ws.W, act, ws.nrm));
-      k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V + (long long)(j + 1) * N, Vr, ws.W, N, ws.nrm,
-                                          ws.idx, N);
+      k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V.at(j + 1, 0), N, ws.W, N, ws.nrm, ws.idx, N);
       k_givens<<<(a + 63) / 64, 64, 0, s>>>(j, m, ws.h1, ws.h2, ws.nrm, ws.H, ws.cs, ws.sn, ws.g,
                                            ws.resid, ws.idx, (int)a);
       HIP_MSG(hipGetLastError());
@@ -399,11 +474,11 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
     const unsigned nc = (unsigned)cycle_set.size();
     k_trisolve<<<(nc + 63) / 64, 64, 0, s>>>(m, ws.H, ws.g, ws.kq, ws.ycoef, ws.idx, (int)nc);
     if (c64)
-      k_axpy_multi<float2><<<dim3(nb, nc), 256, 0, s>>>(u, N, (const float2*)ws.Z, Zr, N, ws.ycoef,
-                                                        m, m, ws.kq, 1.0, ws.idx, N);
+      k_axpy_multi<float2><<<dim3(nb, nc), 256, 0, s>>>(u, N, ws.Z64, ws.ycoef, m, m, ws.kq, 1.0,
+                                                        ws.idx, N);
     else
-      k_axpy_multi<double2><<<dim3(nb, nc), 256, 0, s>>>(u, N, (const double2*)ws.Z, Zr, N,
-                                                         ws.ycoef, m, m, ws.kq, 1.0, ws.idx, N);
+      k_axpy_multi<double2><<<dim3(nb, nc), 256, 0, s>>>(u, N, ws.Z128, ws.ycoef, m, m, ws.kq, 1.0,
+                                                         ws.idx, N);
     HIP_MSG(hipGetLastError());
   }
   for (int q = 0; q < R; ++q) {

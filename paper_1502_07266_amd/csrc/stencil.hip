@@ -104,13 +104,13 @@ hipError_t launch_misfit(helm_handle* h, const double2* u, const double2* d, int
   const long long N = (long long)n * n * n;
   const unsigned nb = (unsigned)((N + 255) / 256);
   double* part = nullptr;
-  hipError_t e = hipMallocAsync((void**)&part, (size_t)nb * R * sizeof(double), s);
+  hipError_t e = pool_alloc((void**)&part, (size_t)nb * R * sizeof(double), s);
   if (e != hipSuccess) return e;
   k_misfit<<<dim3(nb, (unsigned)R), 256, 0, s>>>(u, d, n, plane_k, g, part);
   k_sum<<<1, 256, 0, s>>>(part, (long long)nb * R, 0.5, J_dev);
   e = hipGetLastError();
-  hipError_t e2 = hipFreeAsync(part, s);
-  return e != hipSuccess ? e : e2;
+  pool_free(part, s);
+  return e;
 }
 
 hipError_t launch_matvec(helm_handle* h, const void* u, bool u64, const double2* f, double2* y,

@@ -892,6 +892,7 @@ hipError_t sweep_launch(helm_handle* h, SweepArgs a, const SweepLaunch& L, int R
     a.seq0 = h->xseq;
     a.seq_span = (unsigned long long)(2 * h->plan.Gz) * (2 * h->plan.Gy);
     h->xseq += a.seq_span;
+    h->pairs_used = true;
   }
   return adjoint ? dispatch_sweep<R, TI, TO, true>(sh, L.chains, grid, sm, s, a)
                  : dispatch_sweep<R, TI, TO, false>(sh, L.chains, grid, sm, s, a);
@@ -918,23 +919,35 @@ hipError_t sweep_all(helm_handle* h, SweepArgs a, int R_, bool adjoint, hipStrea
 }  // namespace
 
 
+// one slab iterate per outer front of every right-hand side (shared by its inner fronts)
+static size_t slab_bytes(const helm_handle* h, int R) {
+  const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
+  return (size_t)R * h->plan.fronts * h->n * h->n * h->plan.maxW * csz;
+}
+
+// exchange slots of the paired two-chain launches: a pair per workgroup of a launch
+static size_t exchange_bytes(const helm_handle* h, int R) {
+  const size_t pairs = (size_t)R * h->plan.fronts * h->plan.fronts_inner;
+  return kXHead + pairs * 2 * 2 * kXSlot * sizeof(unsigned long long);
+}
+
+size_t apply_scratch_bytes(const helm_handle* h, int R) {
+  return slab_bytes(h, R) + (h->split ? exchange_bytes(h, R) : 0);
+}
+
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
                         hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  const int n = h->n;
   const bool c64 = h->prec == HELM_C64;
-  const size_t csz = c64 ? sizeof(float2) : sizeof(double2);
-  // one slab iterate per workgroup: two per right-hand side with two fronts
-  const size_t need = (size_t)R * h->plan.fronts * n * n * h->plan.maxW * csz;
+  const size_t need = slab_bytes(h, R);
   if (need > h->slab_scratch_bytes) {
     if (h->slab_scratch) {
-      hipError_t e = hipFree(h->slab_scratch);
-      if (e != hipSuccess) return e;
+      pool_free(h->slab_scratch, s);
       h->slab_scratch = nullptr;
       h->slab_scratch_bytes = 0;
     }
-    hipError_t e = hipMalloc(&h->slab_scratch, need);
+    hipError_t e = pool_alloc(&h->slab_scratch, need, s);
     if (e != hipSuccess) return e;
     h->slab_scratch_bytes = need;
   }
@@ -942,14 +955,13 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   const size_t pairs = (size_t)R * h->plan.fronts * h->plan.fronts_inner;
   if (h->split && pairs > h->xpairs) {
     if (h->xbuf) {
-      hipError_t e = hipFree(h->xbuf);
-      if (e != hipSuccess) return e;
+      pool_free(h->xbuf, s);
       h->xbuf = nullptr;
       h->xpairs = 0;
     }
     // (cleared whole: tags left in reused memory by another handle must not match)
-    const size_t bytes = kXHead + pairs * 2 * 2 * kXSlot * sizeof(unsigned long long);
-    hipError_t e = hipMalloc(&h->xbuf, bytes);
+    const size_t bytes = exchange_bytes(h, R);
+    hipError_t e = pool_alloc(&h->xbuf, bytes, s);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(h->xbuf, 0, bytes, s);
     if (e != hipSuccess) return e;
@@ -976,11 +988,16 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
   return e;
 }
 
-hipError_t take_exchange_error(helm_handle* h, int* bad) {
+hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad) {
   *bad = 0;
+  h->pairs_used = false;
   if (!h->xbuf) return hipSuccess;
-  hipError_t e = hipMemcpy(bad, h->xbuf, sizeof(int), hipMemcpyDeviceToHost);
-  if (e == hipSuccess && *bad) e = hipMemset(h->xbuf, 0, sizeof(int));
+  hipError_t e = hipMemcpyAsync(bad, h->xbuf, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && *bad) {
+    e = hipMemsetAsync(h->xbuf, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
   return e;
 }
 

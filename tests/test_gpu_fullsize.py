@@ -3,12 +3,15 @@
 31^3 (plain method, complex128): the whole preconditioner is compared element by element with
 the oracle's Algorithm 6 on seeded right-hand sides (one front and two fronts), and the solve
 with a sparse direct solve.
-127^3 (the batched mixed-precision workload): the oracle cannot run a whole sweep in seconds,
-so sampled line factorisations are compared block by block with the oracle's, and the sweep is
+127^3 (the batched mixed-precision workload): in the benchmarked configuration (d = 5,
+p = 2, C_moving = C/8, two fronts in x3 and x2) the matvec and the whole preconditioner are
+compared element by element with the oracle's (its setup takes about a minute), and the
+mixed-precision solve with the oracle's solutions to 1e-10 stored under tests/golden; with one
+front per axis, sampled line factorisations are compared block by block, and the sweep is
 checked through properties that hold at any size: the adjoint dot test
 <M^{-1} x, y> = <x, M^{-H} y>, linearity, and the distance between the complex64 and the
-complex128 sweeps.  Tolerances as in test_gpu_parity.py; the complex64 sweep composes
-(2G - 1)^2 line solves (thousands at 127^3 with one front) and is allowed 1e-3.
+complex128 sweeps.  63^3 (the lens): the mixed and the complex128 solves against the oracle's
+stored solution.
 """
 import numpy as np
 import pytest
@@ -52,7 +55,7 @@ def c1_oracle():
     return wl, prob, O.RecursiveSweep(prob)
 
 
-@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1.2e-5)])
 def test_c1_apply_matches_oracle(c1_oracle, prec, tol):
     wl, prob, M = c1_oracle
     n = wl["n"]
@@ -73,7 +76,7 @@ def c1_two_front_oracle():
     return wl, O.RecursiveSweep(prob)
 
 
-@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1.2e-5)])
 def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
     """Two fronts at 31^3: the middle slab's lines have blocks of 13 x 7 = 91 unknowns (moving
     PML on both sides in x3), solved by the one-chain shapes."""
@@ -98,7 +101,7 @@ def c1_two_inner_front_oracle():
     return wl, O.RecursiveSweep(prob)
 
 
-@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1.2e-5)])
 def test_c1_two_inner_front_apply_matches_oracle(c1_two_inner_front_oracle, prec, tol):
     """Two inner fronts at 31^3 (one outer front): three launches per slab; the middle
     x2-line of every slab has blocks of 13 x 7 = 91 unknowns, solved by one chain."""
@@ -148,7 +151,7 @@ def test_c3_sampled_line_factors(c3_handles):
     for (g, l) in [(0, 0), (0, last), (last // 2, last // 2 + 1), (last, 3)]:
         ln = O.LineFactors(prob, G, g, G, l, order="two-sided")
         ref = np.stack(ln.block_T)
-        for H, tol in [(H128, 1e-10), (H64, 1e-3)]:
+        for H, tol in [(H128, 1e-10), (H64, 7e-6)]:
             T = H.line_factors(g, l).cpu().numpy()
             err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
             print(f"c3 line ({g}, {l}) B={ln.B} {H.prec}: worst block rel err {err:.2e}")
@@ -175,7 +178,7 @@ def test_c3_sweep_dot_test_and_linearity(c3_handles):
     Mx64 = H64.apply(x)
     prec_err = float((Mx64 - Mx).norm() / Mx.norm())
     print(f"c3 complex64 vs complex128 sweep: {prec_err:.2e}")
-    assert prec_err <= 1e-3
+    assert prec_err <= 3e-5
 
 
 def test_c3_two_fronts_both_axes():
@@ -199,7 +202,7 @@ def test_c3_two_fronts_both_axes():
         T = H.line_factors(g, l).cpu().numpy()
         err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
         print(f"c3 2f2i line ({g}, {l}) B={ln.B}: worst block rel err {err:.2e}")
-        assert err <= 1e-3
+        assert err <= 1e-5
     x = torch.from_numpy(inputs.random_rhs(n, 1, seed=33)).cuda()
     y = torch.from_numpy(inputs.random_rhs(n, 1, seed=34)).cuda()
     Mx, My = H.apply(x), H.apply(y)
@@ -210,8 +213,8 @@ def test_c3_two_fronts_both_axes():
     lin_err = float((comb - (2 * Mx + 3j * My)).norm() / comb.norm())
     H.close()
     print(f"c3 2f2i complex64 sweep: dot test {dot_err:.2e}, linearity {lin_err:.2e}")
-    assert dot_err <= 1e-4
-    assert lin_err <= 1e-4
+    assert dot_err <= 1.2e-5
+    assert lin_err <= 3.5e-6
 
 
 def test_c4_gradient_against_central_differences():
@@ -225,3 +228,128 @@ def test_c4_gradient_against_central_differences():
         print(f"c4 cell {r['cell']}: adjoint {r['adjoint']:.6e}, central difference "
               f"{r['central_difference']:.6e}, rel err {r['rel_err']:.2e}")
     assert summary["max_rel_err"] <= 1e-4
+
+
+# ---------------------------------------------------------------------------------------------
+# The benchmarked 127^3 configuration in full: d = 5, p = 2, C_moving = C/8, two fronts in x3
+# and in x2 (the oracle's setup takes about a minute on 8 cores, one apply 15 s)
+# ---------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c3_bench_oracle():
+    wl, _ = workload("c3")
+    prob = O.Problem(n=wl["n"], c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                     C_moving=wl.get("C_moving", 0.0), fronts=2, fronts_inner=2)
+    return wl, prob, O.RecursiveSweep(prob)
+
+
+def bench_helm(wl, prec):
+    from paper_1502_07266_amd.binding import Helm
+    return Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec,
+                C_moving=wl.get("C_moving", 0.0), fronts=2, fronts_inner=2)
+
+
+def bench_config_supported(wl, prec):
+    from paper_1502_07266_amd.binding import HelmError, plan_bytes, HELM_C64, HELM_C128
+    try:
+        plan_bytes(wl["n"], wl["b"], wl["C"], wl["p"], wl["d"], HELM_C64 if prec == "c64" else HELM_C128, 2, 2)
+        return True
+    except HelmError:
+        return False
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_c3_matvec_matches_oracle_elementwise(c3_bench_oracle, adjoint):
+    """helm_matvec at 127^3 against the oracle's sparse A of eq. (3), every element."""
+    wl, prob, M = c3_bench_oracle
+    n = wl["n"]
+    x = inputs.random_rhs(n, 2, seed=41)
+    H = bench_helm(wl, "c64")
+    y = H.matvec(torch.from_numpy(x).cuda(), adjoint=adjoint).cpu().numpy()
+    H.close()
+    A = M.AH if adjoint else M.A
+    ref = (A @ x.reshape(2, -1).T).T.reshape(x.shape)
+    err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+    print(f"c3 matvec adj={adjoint}: max abs err / max abs {err:.2e}, rel-L2 {rel(y, ref):.2e}")
+    assert err <= 1e-14 and rel(y, ref) <= 1e-14
+
+
+# observed relative error of the full 127^3 apply in complex64: 2.8e-6 (tolerance about 10x)
+C3_APPLY_TOL = {"c128": 1e-10, "c64": 3e-5}
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_c3_benchmarked_apply_matches_oracle(c3_bench_oracle, prec):
+    """The whole preconditioner of the benchmarked configuration, M^{-1} x on 2 seeded
+    right-hand sides, against the oracle's Algorithm 6 (two fronts, with Algorithm 4 from both
+    x2-faces inside), element by element."""
+    wl, prob, M = c3_bench_oracle
+    if not bench_config_supported(wl, prec):
+        pytest.skip(f"{prec}: the benchmarked fronts need a line vector beyond LDS in this precision")
+    n = wl["n"]
+    x = inputs.random_rhs(n, 2, seed=42)
+    H = bench_helm(wl, prec)
+    z = H.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    H.close()
+    ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
+    errs = [rel(z[q], ref[q]) for q in range(2)]
+    print(f"c3 benchmarked apply {prec}: rel err {max(errs):.2e}")
+    assert max(errs) <= C3_APPLY_TOL[prec]
+
+
+def _reference(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no oracle reference solutions at {path} (tests/golden/make_reference_solutions.py)")
+    return np.load(path)
+
+
+def test_c3_mixed_solve_matches_oracle_reference(c3_bench_oracle):
+    """The benchmarked mixed-precision solve (complex64 sweeps, FP64 FGMRES to 1e-6) of the
+    first two of the 32 sources against the oracle's solutions of A u = f to 1e-10
+    (tests/golden, written by make_reference_solutions.py from the oracle only): relative L2
+    error <= 1e-5 on the stored subsample (every 4th node per axis), the norms agree, and the
+    true residual of the GPU solution recomputed with the oracle's A is <= 1e-6."""
+    wl, prob, M = c3_bench_oracle
+    ref = _reference("c3")
+    n, m, s = wl["n"], ref["sub"].shape[0], int(ref["stride"])
+    assert [tuple(v) for v in ref["nodes"]] == [tuple(v) for v in wl["nodes"][:m]]
+    f = inputs.sources(n, wl["nodes"][:m])
+    H = bench_helm(wl, "c64")
+    u, its, relres, rc = H.solve(torch.from_numpy(f).cuda(), tol=1e-6, restart=50, maxit=100)
+    H.close()
+    u = u.cpu().numpy()
+    assert rc == 0
+    for q in range(m):
+        sub = u[q, ::s, ::s, ::s]
+        err = rel(sub, ref["sub"][q])
+        nerr = abs(np.linalg.norm(u[q]) - ref["norms"][q]) / ref["norms"][q]
+        tres = float(np.linalg.norm(f[q].ravel() - M.A @ u[q].ravel()) / np.linalg.norm(f[q]))
+        print(f"c3 source {q}: {its[q]} iterations, rel-L2 vs oracle {err:.2e}, norm {nerr:.2e}, "
+              f"true residual {tres:.2e}")
+        assert err <= 1e-5 and nerr <= 1e-5
+        assert tres <= 1.01e-6
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_c2_solve_matches_oracle_reference(prec):
+    """63^3 Gaussian lens (mixed precision against complex128): each solve to 1e-6 against the
+    oracle's solution to 1e-10 (tests/golden): relative L2 error <= 1e-5 on the stored
+    subsample (every 2nd node per axis) and in norm; the true residual recomputed with the
+    oracle's A is <= 1e-6."""
+    ref = _reference("c2")
+    wl, prob = workload("c2")
+    n, s = wl["n"], int(ref["stride"])
+    f = inputs.sources(n, wl["nodes"])
+    H = helm(wl, prec)
+    u, its, relres, rc = H.solve(torch.from_numpy(f).cuda(), tol=1e-6, restart=50, maxit=200)
+    H.close()
+    assert rc == 0
+    u = u.cpu().numpy()[0]
+    err = rel(u[::s, ::s, ::s], ref["sub"][0])
+    nerr = abs(np.linalg.norm(u) - ref["norms"][0]) / ref["norms"][0]
+    from oracle.problem import helmholtz_matrix
+    tres = float(np.linalg.norm(f[0].ravel() - helmholtz_matrix(prob) @ u.ravel()) / np.linalg.norm(f[0]))
+    print(f"c2 {prec}: {its[0]} iterations, rel-L2 vs oracle {err:.2e}, norm {nerr:.2e}, true residual {tres:.2e}")
+    assert err <= 1e-5 and nerr <= 1e-5
+    assert tres <= 1.01e-6
