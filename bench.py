@@ -39,14 +39,10 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-PAIRED = True   # two-chain line solves on workgroup pairs (helm_set_split)
-
-
 def run_step(Helm, c, wl, F, prec, fronts, fronts_inner):
     import torch
     H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts,
              fronts_inner=fronts_inner, C_moving=wl.get("C_moving", 0.0))
-    H.set_split(PAIRED)
     u, its, rel, rc = H.solve(F, tol=wl["tol"], restart=wl["restart"], maxit=wl.get("maxit", 400))
     torch.cuda.synchronize()
     st = H.stats()
@@ -60,16 +56,17 @@ def group_count(n, b, d, fronts):
 
 
 def dependent_steps(n, b, d, fronts, fronts_inner, line_steps=None):
-    """Dependent block steps of one sweep (the longest chain through its launches) and of one
-    launch of the dominant kernel.  A two-sided line solve takes 2 (n/2) + 1 steps, a
-    one-chain solve 2n - 1; line_steps(g, l) gives them per line (default: the lines on a
-    middle group one chain, the others two-sided).  With two fronts the chain runs through
-    the front with more groups."""
-    S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
+    """Dependent block steps of one sweep (the longest chain through it).  A two-sided line
+    solve takes 2 (n/2) + 1 steps; line_steps(g, l) may give them per line.  With two fronts
+    the chain runs through the front with more groups, then the middle group, then that front
+    again backwards.  Also returned, for comparison with the launches of earlier designs, the
+    steps of one inner front's lines of one slab step (two inner fronts) or of one outer front
+    (one inner front)."""
+    S2 = 2 * (n // 2) + 1
     Gz, Gy = group_count(n, b, d, fronts), group_count(n, b, d, fronts_inner)
     zmid, ymid = Gz // 2, Gy // 2
     if line_steps is None:
-        line_steps = lambda g, l: S1 if (fronts == 2 and g == zmid) or (fronts_inner == 2 and l == ymid) else S2
+        line_steps = lambda g, l: S2
 
     def longer_front(G, mid):
         lo, hi = list(range(mid)), list(range(mid + 1, G))
@@ -233,8 +230,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-fp64", action="store_true", help="skip the complex128 path")
-    ap.add_argument("--no-pair", action="store_true",
-                    help="run both chains of each two-sided line solve in one workgroup")
     ap.add_argument("--fronts", type=int, default=2, choices=[1, 2],
                     help="outer sweep from both x3-faces meeting in a middle slab (2, the "
                          "configuration of the paper's experiments) or from x3 = 0 only (1)")
@@ -247,8 +242,6 @@ def main():
                          "solution the two 1e-6 solves are measured against (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
     args = ap.parse_args()
-    global PAIRED
-    PAIRED = not args.no_pair
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the sweep for one "
               "right-hand side is a single dependent chain; multi-GPU sharding by right-hand "
@@ -286,7 +279,8 @@ def main():
     t0 = time.perf_counter()
     tot = {"apply_ms": 0.0, "apply_launches": 0, "apply_rhs": 0, "setup_ms": 0.0,
            "matvec_ms": 0.0, "matvec_launches": 0, "matvec_rhs": 0,
-           "kernel_ms": 0.0, "kernel_launches": 0, "kernel_rhs": 0}
+           "kernel_ms": 0.0, "kernel_launches": 0, "kernel_rhs": 0, "kernel_bytes": 0.0,
+           "kernel_flops": 0.0}
     u_mix = None
     step_s = []
     for k in range(args.steps):
@@ -297,6 +291,7 @@ def main():
             tot[key] += st[key]
         kst = st
         info = H.info()
+        shape = H.sweep_shape(R)
         log(f"step {k}: {step_s[-1]:.3f} s, iters {its.tolist()} relres max {rel.max():.2e} status {rc}")
         H.close()
         if k == args.steps - 1:
@@ -310,24 +305,16 @@ def main():
         first_step_s = step_s[0]
 
     apply_avg_ms = tot["apply_ms"] / max(tot["apply_launches"], 1)
-    # the dominant kernel (its two-chain launches), per launch
+    # the sweep kernel: one cooperative launch per sweep (per chunk of right-hand sides)
     kl = max(tot["kernel_launches"], 1)
     kernel_avg_ms = tot["kernel_ms"] / kl
     rhs_per_launch = tot["kernel_rhs"] / kl
-    unique_bytes = kst["kernel_factor_bytes"] + kst["kernel_vector_bytes_per_rhs"] * rhs_per_launch
-    effective_bytes = kst["kernel_bytes_per_rhs"] * rhs_per_launch
-    flops = kst["kernel_flops_per_rhs"] * rhs_per_launch
+    unique_bytes = tot["kernel_bytes"] / kl
+    effective_bytes = kst["apply_bytes_per_rhs"] * rhs_per_launch
+    flops = tot["kernel_flops"] / kl
     achieved = unique_bytes / (kernel_avg_ms * 1e-3) / 1e9
-    # each line's chain count as a handle of this configuration factors it (two-sided or x1
-    # order), from a handle made after the timed region
-    S2, S1 = 2 * (n // 2) + 1, 2 * n - 1
-    Hq = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64", fronts=args.fronts,
-              fronts_inner=args.fronts_inner, C_moving=wl.get("C_moving", 0.0))
-    chains = {}
-    line_steps = lambda g, l: chains.setdefault((g, l), S2 if Hq.line_order(g, l) == "two-sided" else S1)
-    steps_per_sweep, steps_per_kernel = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner,
-                                                        line_steps)
-    Hq.close()
+    steps_per_sweep, _ = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner)
+    steps_per_kernel = steps_per_sweep
     mv_gbs = kst["matvec_bytes_per_rhs"] * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
     # device time of the step's kernels, from the library's own event pairs (sweeps and
     # matvecs) plus the setup; the rest is Krylov kernels and host work
@@ -356,15 +343,14 @@ def main():
                    "factor_bytes": info["factor_bytes"], "lines": info["n_lines"], "max_block": info["max_block"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_sweep, complex64, two-chain launches on workgroup pairs ("
-                               + (f"{tot['kernel_launches'] // max(tot['apply_launches'], 1)} per sweep"
-                                  + (": inner fronts forward / backward, one slab step each"
-                                     if args.fronts_inner == 2 else "") + ")"),
+                     "kernel": "k_sweep, complex64: the whole sweep of the batch in one cooperative "
+                               f"launch ({tot['kernel_launches'] / max(tot['apply_launches'], 1):g} per "
+                               f"sweep), launch shape {shape[1]} (variant {shape[0]})",
                      "avg_launch_ms": round(kernel_avg_ms, 4),
                      "algorithmic_bytes_per_launch": unique_bytes,
-                     "algorithmic_bytes_note": "the launch's factor blocks once per visit (its right-hand "
-                                               "sides share them) plus every right-hand side's input "
-                                               "read and output written",
+                     "algorithmic_bytes_note": "the sweep's factor blocks once per visit (the launch's "
+                                               "right-hand sides share them) plus every right-hand "
+                                               "side's input read and output written",
                      "effective_bytes_per_launch": effective_bytes,
                      "effective_gbs": round(effective_bytes / (kernel_avg_ms * 1e-3) / 1e9, 1),
                      "effective_note": "the factor stream counted once per right-hand side, as if "
@@ -375,6 +361,7 @@ def main():
                      "rhs_per_launch": rhs_per_launch},
         "sweep_ms_per_apply": round(apply_avg_ms, 3),
         "ns_per_dependent_step": round(kernel_avg_ms * 1e6 / steps_per_kernel, 1),
+        "sweep_shape": {"variant": shape[0], "shapes": shape[1]},
         "dependent_steps_per_sweep": steps_per_sweep,
         "iters": its_mix.tolist(),
         "relres_max": float(rel_mix.max()),

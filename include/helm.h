@@ -82,11 +82,10 @@ typedef struct {
  * shorter) and nodes n-b+1..n; with G of them the middle one is group G/2; groups below it
  * are padded below as above, groups above it padded above with the mirror image (plane p+1
  * spacings above the group), the middle group on both sides, and the first and last groups
- * not at all.  Line blocks have B = (x2 window) x (x3 window) unknowns.  The sweep solves
- * the lines of one launch by two chains from the lines' ends when every block of the launch
- * has B <= 64, else by one chain in x1 order
- * (helm_line_factors).  One-chain blocks are limited to B <= 128 (complex64) or 96
- * (complex128), and n*B line values must fit in LDS.
+ * not at all.  Line blocks have B = (x2 window) x (x3 window) unknowns, at most 128
+ * (complex64) or 96 (complex128), and half a line's values ((n/2 + 1) x B) must fit in the
+ * LDS of a workgroup.  Every line is factored with its x1-blocks eliminated from both ends
+ * towards the middle block (helm_line_factors).
  * Errors: HELM_EINVAL, HELM_ENOMEM (the planned bytes of helm_plan_bytes exceed the free
  * device memory plus the pool's cached blocks; checked before anything is allocated),
  * HELM_ESINGULAR, HELM_EHIP.
@@ -101,14 +100,19 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
  * LDU): z = M^{-1} r for R right-hand sides in one persistent launch.  With two fronts the
  * outer sweep is the block LDU with the x3-groups eliminated from both faces towards the
  * middle group (forward: each front carries its f - A u coupling, the middle slab takes
- * both; backward: each front subtracts the correction from its neighbour nearer the middle),
- * in three launches (fronts forward, middle slab, fronts backward).  Two inner fronts do the
- * same over the x2-groups of every slab, in three launches per slab (inner fronts forward,
- * middle line, inner fronts backward).
+ * both; backward: each front subtracts the correction from its neighbour nearer the middle).
+ * Two inner fronts do the same over the x2-groups of every slab.  The whole sweep of the R
+ * right-hand sides is one cooperative launch (in chunks of right-hand sides when they cannot
+ * all be resident): per right-hand side one workgroup for each half of every line solve
+ * (the two chains of the two-sided block LDU), each outer front and each inner front; they
+ * exchange the few values they share through device memory (a wait gives up after a bounded
+ * number of polls, leaving NaN and an error word).
  *   r_dev, z_dev : R*n^3 complex128 each (may not alias).  In HELM_C64 mode r is rounded to
  *                  complex64 on entry and z is widened on exit.
- * When paired line solves ran (helm_set_split), the call synchronises `stream` to read their
- * error word and returns HELM_EHIP if one of them timed out (z then holds NaN there).
+ * Synchronises `stream` to read the sweep's error word; returns HELM_EHIP if an exchange
+ * timed out (only possible after a fault elsewhere, or with helm_set_exchange_test).
+ * The first sweep of a configuration in the process runs the autotuner (helm_autotune) unless
+ * the environment sets HELM_AUTOTUNE=0; HELM_TUNE_CACHE may name a file of earlier choices.
  */
 int helm_apply(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream);
 
@@ -144,8 +148,7 @@ int helm_matvec(helm_handle* h, const void* u_dev, void* y_dev, int R, int adjoi
  * their largest size (helm_workspace_bytes) is checked against the free device memory before
  * anything is allocated and gives HELM_ENOMEM if it does not fit.  The workspace comes from
  * the library's memory pool and returns to it (helm_pool_trim).
- * Errors also: HELM_EHIP when a paired line solve of the sweep timed out (a fault elsewhere;
- * see helm_set_split).
+ * Errors also: HELM_EHIP when an exchange of the sweep timed out (see helm_apply).
  * Synchronises `stream`.
  */
 int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol, int restart,
@@ -238,12 +241,10 @@ int helm_plan_bytes(const helm_grid* grid, const helm_pml* pml, int slab_layers,
  * and x2-group) into dst_dev: n blocks of B*B complex values, block i (0-based x1 index)
  * holding the factor of x1-block i, row-major within a block, unknowns of a block ordered
  * (x2 window row, x3 window layer) with x3 fastest.  The blocks are eliminated from both
- * ends towards the middle block m (0-based): block i < m holds the inverse Schur complement
- * after eliminating blocks 0..i-1 (Sec. 3), block i > m the one after blocks i+1..n-1, and
- * block m the one after all others, which equals the (m, m) block of the line matrix's
- * inverse.  m = n/2 (integer division), except for the lines the sweep solves with one
- * chain, where m = n-1 (the x1 order of Sec. 3): the lines of every sweep launch that holds
- * a block above 64 unknowns, e.g. the lines on the middle groups of two fronts at 127^3.  The solve is exact for any such order.
+ * ends towards the middle block m = n/2 (0-based, integer division): block i < m holds the
+ * inverse Schur complement after eliminating blocks 0..i-1 (Sec. 3), block i > m the one
+ * after blocks i+1..n-1, and block m the one after all others, which equals the (m, m)
+ * block of the line matrix's inverse.  The solve is exact for any such order.
  * Element type is complex64 in HELM_C64 mode and complex128 in HELM_C128 mode.
  * *B_out receives B and *mid_out m (either may be NULL).  Pass dst_dev = NULL to query them
  * only.
@@ -261,41 +262,46 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
                     int adjoint, void* stream);
 
 /*
- * helm_set_split -- where the two elimination chains of a two-sided line solve run (the
- * two-sided block LDU of Sec. 3, eliminated from both ends towards the middle block): on = 1
- * (default) gives each chain a workgroup of its own, a pair per line solve holding the grid
- * points of its half of the line in x1, which meet once per line solve to exchange the
- * middle block's partial right-hand sides through device memory; on = 0 runs both chains in
- * one workgroup.  The operations and their order are the same either way; results agree to
- * rounding (the two kernels may contract multiply-adds differently).  Pairs are used only
- * when every pair of a launch can be resident at once (a cooperative launch; otherwise that
- * launch runs unpaired); they take (R * fronts * fronts_inner) x 16 KiB of device memory
- * beside the slab scratch.  A member whose partner never arrives gives up after 2^20 polls
- * (on the order of a second), writes NaN into its line solution and makes the next
- * helm_solve on the handle return HELM_EHIP.
- * Errors: HELM_EINVAL (h NULL, on not 0 or 1).
+ * helm_set_launch -- choose the sweep's launch shape: variant k (0-based) of the library's
+ * list (two shapes each: lanes per block row, columns per lane and factor-ring depth for the
+ * lines on no middle group and for the others; helm_sweep_shape names them), or -1 for the
+ * automatic choice (the autotuner's for this configuration, else the first listed variant
+ * that covers the blocks).  Changes summation order only: results agree to rounding.
+ * Errors: HELM_EINVAL (h NULL, k not a variant covering this handle's blocks).
  */
-int helm_set_split(helm_handle* h, int on);
+int helm_set_launch(helm_handle* h, int variant);
 
 /*
- * helm_set_launch -- override the sweep's launch shape: lanes per block row (4, 8 or 16;
- * 0 = automatic).  Changes summation order only, i.e. results agree to rounding.
+ * helm_sweep_shape -- the variant a sweep of R right-hand sides on this handle uses now
+ * (*variant, may be NULL) and its description "NCxCW/ringD + NCxCW/ringD" (written to name,
+ * at most name_len bytes with the terminating zero; name may be NULL).
  */
-int helm_set_launch(helm_handle* h, int lanes_per_row);
+int helm_sweep_shape(const helm_handle* h, int R, int* variant, char* name, int name_len);
 
 /*
- * helm_autotune -- pick the sweep's launch shape for this handle: time every valid
- * lanes-per-row candidate on an interior line problem of the handle (the sweep's inner loop)
- * and keep the fastest via helm_set_launch.  If cache_path is not NULL the choice is looked up
- * in / appended to that file (one JSON object per line, keyed by n, largest block and
- * precision), so the timing runs once per configuration.  *lanes_out (may be NULL) receives
- * the choice and *ns_per_step (may be NULL) its measured time per x1-block of a line solve,
- * i.e. the time of one line solve divided by n (0 when taken from the cache).  Results of
- * later sweeps change only by rounding (summation order).
- * Synchronises `stream`.
+ * helm_autotune -- time one sweep of R right-hand sides (after a warm-up sweep) with each
+ * candidate launch shape for this handle (the variants whose two shapes are each among the
+ * two smallest covering its blocks, with every ring depth listed for them) and keep the
+ * fastest, for this handle (helm_set_launch) and for the process (handles of the same
+ * configuration and batch size, rounded up to a multiple of 8, take it on their first
+ * sweep).  If cache_path is not NULL the choice is looked up in / appended to that file (one
+ * JSON object per line, keyed by n, block sizes, window, fronts, precision and batch size),
+ * so the timing runs once per configuration.  *variant_out (may be NULL) receives the choice
+ * and *ms_per_sweep (may be NULL) its time per sweep (0 when taken from the file).  Results
+ * of later sweeps change only by rounding.  Synchronises `stream`.
  */
-int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,
-                  void* stream);
+int helm_autotune(helm_handle* h, int R, const char* cache_path, int* variant_out,
+                  double* ms_per_sweep, void* stream);
+
+/*
+ * helm_set_exchange_test -- failure-injection hook for tests of the sweep's error path:
+ * drop_publish = 1 makes the first-half workgroup of every line solve skip publishing its
+ * partial middle-block values, so its partner gives up after spin_limit polls (0: the
+ * default bound, about a second) and the next helm_apply / helm_solve returns HELM_EHIP;
+ * drop_publish = 0 restores normal operation.  Every kernel still ends normally.
+ * Errors: HELM_EINVAL (h NULL, drop_publish not 0 or 1).
+ */
+int helm_set_exchange_test(helm_handle* h, int drop_publish, unsigned spin_limit);
 
 /*
  * Device-time statistics of one handle, from HIP events recorded on the launch stream around
@@ -313,21 +319,17 @@ typedef struct {
   long long matvec_rhs;
   double matvec_ms;
   double matvec_bytes_per_rhs; /* 40 bytes per grid point (u, kappa read; y written)          */
-  /* the sweep's dominant kernel: its two-chain launches (all lines but those on a middle    */
-  /* group; one launch per outer pass with one inner front, two per slab with two)          */
+  /* the sweep kernel: one cooperative launch per sweep (per chunk of right-hand sides when  */
+  /* they cannot all be resident at once)                                                     */
   long long kernel_launches;
   long long kernel_rhs;
   double kernel_ms;
-  double kernel_bytes_per_rhs; /* effective bytes of one such launch per right-hand side,     */
-                               /* averaged over a sweep's launches: the factor bytes of its   */
-                               /* line solves plus 16 bytes per grid point it reads as input  */
-                               /* and 16 per point it writes as output; counts the factor     */
-                               /* stream once per right-hand side                             */
-  double kernel_factor_bytes;  /* factor bytes of one such launch, counted once (the          */
-                               /* right-hand sides of a launch share one factor stream)       */
-  double kernel_vector_bytes_per_rhs; /* its input and output bytes per right-hand side       */
-  double kernel_flops_per_rhs; /* useful real flops of one such launch per right-hand side:   */
-                               /* 8 per factor entry visited (one complex multiply-add)       */
+  double kernel_bytes;         /* algorithmic bytes of those launches: each launch reads its  */
+                               /* sweep's factor blocks once per visit (its right-hand sides  */
+                               /* share them), and every right-hand side's input is read and */
+                               /* its output written once                                     */
+  double kernel_flops;         /* useful real flops: 8 per factor entry visited per           */
+                               /* right-hand side (one complex multiply-add)                  */
 } helm_stats;
 
 /* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */

@@ -4,8 +4,10 @@ Argument marshalling only: every numerical step runs in the library's HIP kernel
 provides device memory (tensors passed by data_ptr()) and the current HIP stream.  Loading
 fails loudly if libhelm.so has not been built; there is no fallback path.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -32,8 +34,7 @@ class helm_stats(ctypes.Structure):
                 ("matvec_rhs", ctypes.c_longlong), ("matvec_ms", ctypes.c_double),
                 ("matvec_bytes_per_rhs", ctypes.c_double), ("kernel_launches", ctypes.c_longlong),
                 ("kernel_rhs", ctypes.c_longlong), ("kernel_ms", ctypes.c_double),
-                ("kernel_bytes_per_rhs", ctypes.c_double), ("kernel_factor_bytes", ctypes.c_double),
-                ("kernel_vector_bytes_per_rhs", ctypes.c_double), ("kernel_flops_per_rhs", ctypes.c_double)]
+                ("kernel_bytes", ctypes.c_double), ("kernel_flops", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -60,9 +61,10 @@ _SIGS = {
     "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
-    "helm_set_split": (_I, [_P, _I]),
+    "helm_sweep_shape": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_char_p, _I]),
+    "helm_set_exchange_test": (_I, [_P, _I, ctypes.c_uint]),
     "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
-    "helm_autotune": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
+    "helm_autotune": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "helm_reset_stats": (_I, [_P]),
     "helm_destroy": (None, [_P]),
     "helm_error_string": (ctypes.c_char_p, [_I]),
@@ -70,6 +72,21 @@ _SIGS = {
 }
 
 _lib = None
+# handles not yet destroyed: closed (and the device pool released) by an exit handler that
+# runs before the interpreter tears down, so no HIP call reaches the runtime after a
+# profiler or the runtime itself has begun finalising
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for H in list(_live):
+        try:
+            H.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        _lib.helm_pool_trim()
 
 
 def lib():
@@ -161,6 +178,7 @@ class Helm:
                                 slab_layers, self.prec,
                                 _stream(), ctypes.byref(h)), "helm_setup")
         self._h = h
+        _live.add(self)
 
     # ------------------------------------------------------------------ helpers
     def _batch(self, x):
@@ -295,21 +313,30 @@ class Helm:
     def reset_stats(self):
         _check(lib().helm_reset_stats(self.handle), "helm_reset_stats")
 
-    def autotune(self, cache_path=None):
-        """Pick the fastest launch shape (cached in cache_path); returns (lanes, ns per x1-block
-        of a line solve)."""
-        lanes, ns = _I(), _D()
+    def autotune(self, R, cache_path=None):
+        """Time a sweep of R right-hand sides with each candidate launch shape and keep the
+        fastest (cached in cache_path); returns (variant, ms per sweep)."""
+        v, ms = _I(), _D()
         path = cache_path.encode() if cache_path else None
-        _check(lib().helm_autotune(self.handle, path, ctypes.byref(lanes), ctypes.byref(ns), _stream()),
+        _check(lib().helm_autotune(self.handle, int(R), path, ctypes.byref(v), ctypes.byref(ms), _stream()),
                "helm_autotune")
-        return lanes.value, ns.value
+        return v.value, ms.value
 
-    def set_launch(self, lanes_per_row):
-        _check(lib().helm_set_launch(self.handle, int(lanes_per_row)), "helm_set_launch")
+    def set_launch(self, variant):
+        """Use launch-shape variant k for the sweeps (-1: automatic)."""
+        _check(lib().helm_set_launch(self.handle, int(variant)), "helm_set_launch")
 
-    def set_split(self, on):
-        """Run each two-sided line solve's chains on a workgroup pair (True) or one workgroup."""
-        _check(lib().helm_set_split(self.handle, 1 if on else 0), "helm_set_split")
+    def sweep_shape(self, R):
+        """(variant, description) a sweep of R right-hand sides uses now."""
+        v = _I()
+        buf = ctypes.create_string_buffer(96)
+        _check(lib().helm_sweep_shape(self.handle, int(R), ctypes.byref(v), buf, 96), "helm_sweep_shape")
+        return v.value, buf.value.decode()
+
+    def set_exchange_test(self, drop_publish, spin_limit=0):
+        """Failure injection for tests of the sweep's error path (see helm.h)."""
+        _check(lib().helm_set_exchange_test(self.handle, int(drop_publish), int(spin_limit)),
+               "helm_set_exchange_test")
 
     def close(self):
         if self._h is not None:

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -12,9 +13,7 @@
 namespace {
 thread_local std::string g_last_error;
 
-constexpr int kBlockLimitOne = 128;      // largest block of the one-chain sweep shapes
 constexpr size_t kSetupLds = 144 * 1024; // dynamic LDS of the setup (one B x B block at least)
-constexpr size_t kLdsBytes = 160 * 1024; // LDS per workgroup on gfx950
 constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
 
 int fail(int code, const std::string& msg) {
@@ -35,15 +34,9 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
   int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, prec, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
-  if (plan.maxB_mid > (prec == HELM_C64 ? kBlockLimitOne : 96))
-    return fail(HELM_EINVAL, "block size (window width in x2 times in x3) exceeds 128 (complex64) "
-                             "or 96 (complex128) on a line solved by one chain (a line whose "
-                             "launch holds a block above 64)");
   if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
     return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
-  for (int B : {plan.maxB_front, plan.maxB_mid})
-    if (B && LdsLayout(plan.n, B, (int)csize(prec)).bytes > kLdsBytes)
-      return fail(HELM_EINVAL, "line vector n*B does not fit in LDS");
+  if (!sweep_plan_supported(plan, prec, msg)) return fail(HELM_EINVAL, msg);
   return HELM_OK;
 }
 
@@ -55,13 +48,13 @@ size_t planned_bytes(const Plan& p, int prec) {
          (size_t)p.Gz * p.Gy * (sizeof(long long) + sizeof(int) + 1);
 }
 
-// algorithmic bytes of one sweep of one right-hand side: line (g, l) is solved once per
-// inner pass it takes part in (twice unless l is the last x2-group with one inner front, or
-// the middle one with two) and once per outer pass (twice unless g is the last x3-group with
-// one front, or the middle one with two fronts); each solve visits its n blocks twice
-// (forward and backward substitution) and reads B*B entries per visit; plus the input
-// (complex128) read and the output written once.
-double sweep_bytes_per_rhs(const Plan& p, int prec) {
+// factor entries one sweep visits: line (g, l) is solved once per inner pass it takes part
+// in (twice unless l is the last x2-group with one inner front, or the middle one with two)
+// and once per outer pass (twice unless g is the last x3-group with one front, or the middle
+// one with two fronts); each solve visits its n blocks twice (forward and backward
+// substitution) and reads B*B entries per visit.  Algorithmic bytes of one sweep of one
+// right-hand side: these entries plus the input read and the output written (complex128).
+double sweep_entries(const Plan& p) {
   double acc = 0.0;
   for (int g = 0; g < p.Gz; ++g)
     for (int l = 0; l < p.Gy; ++l) {
@@ -71,59 +64,7 @@ double sweep_bytes_per_rhs(const Plan& p, int prec) {
       const double B = p.line_B[(size_t)g * p.Gy + l];
       acc += mult * 2.0 * p.n * B * B;
     }
-  const double N = (double)p.n * p.n * p.n;
-  return acc * csize(prec) + N * (sizeof(double2) + sizeof(double2));
-}
-
-// the same for one launch of the dominant kernel (the two-chain launches of sweep_schedule),
-// averaged over its launches in one sweep: the factor bytes of the line solves of a launch
-// (every block visit reads B*B entries), and per right-hand side 16 bytes per grid point of
-// its slabs' rows for reading the input and 16 for writing the output, each counted in the
-// launch that does it (an inner-front forward launch reads the input on its lines' rows, the
-// backward one writes the output there; a launch that runs whole inner sweeps does both on
-// every row).  factor: the factor bytes once per launch (the right-hand sides of a launch
-// share one factor stream); vec: the vector bytes of one right-hand side; entries: factor
-// entries visited (one complex multiply-add, 8 real flops, per entry and right-hand side).
-struct KernelWork {
-  double factor = 0.0, vec = 0.0, entries = 0.0;
-};
-KernelWork kernel_work(const Plan& p, int prec) {
-  KernelWork w;
-  int launches = 0;
-  for (const SweepLaunch& L : sweep_schedule(p)) {
-    if (!L.timed) continue;
-    ++launches;
-    double ent = 0.0, pts = 0.0;
-    const int io = L.ipass == 0 ? 32 : 16;
-    for (int fr = 0; fr < L.nfront; ++fr) {
-      const int cnt = std::min(L.slab_hi, sweep_count(L.pass, p.Gz, p.zmid, fr));
-      for (int si = L.slab_lo; si < cnt; ++si) {
-        const int g = sweep_at(L.pass, p.Gz, p.zmid, fr, si).x;
-        const double nph = p.zg(g).last - p.zg(g).first + 1;
-        int rows = 0;
-        for (int inf = 0; inf < L.ninner; ++inf) {
-          const int lc = sweep_count(L.ipass, p.Gy, p.ymid, inf);
-          for (int k = 0; k < lc; ++k) {
-            const int l = sweep_at(L.ipass, p.Gy, p.ymid, inf, k).x;
-            const double B = p.line_B[(size_t)g * p.Gy + l];
-            ent += 2.0 * p.n * B * B;
-            if (L.ipass != 0) rows += p.yg(l).last - p.yg(l).first + 1;
-          }
-        }
-        if (L.ipass == 0) rows = p.n;
-        pts += (double)p.n * rows * nph;
-      }
-    }
-    w.factor += ent * csize(prec);
-    w.vec += pts * io;
-    w.entries += ent;
-  }
-  if (launches) {
-    w.factor /= launches;
-    w.vec /= launches;
-    w.entries /= launches;
-  }
-  return w;
+  return acc;
 }
 
 void release(helm_handle* h) {
@@ -131,7 +72,7 @@ void release(helm_handle* h) {
   h->t_matvec.reset();
   h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
-                  h->d_setup_lines, h->d_line_one, h->factors, h->d_err, h->slab_scratch,
+                  h->d_setup_lines, h->factors, h->d_err, h->slab_scratch, h->layer,
                   h->d_rhs_idx, h->xbuf};
   for (void* p : ptrs)
     if (p) pool_free(p, h->last_stream);
@@ -212,7 +153,6 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   ALLOC(h->d_groups, plan.groups.size() * sizeof(GroupInfo));
   ALLOC(h->d_line_off, plan.line_off.size() * sizeof(long long));
   ALLOC(h->d_setup_lines, plan.line_off.size() * sizeof(int));
-  ALLOC(h->d_line_one, plan.one.size());
   // the sweep's row-major block walk may read up to 64 entries past the last block
   ALLOC(h->factors, ((size_t)plan.total_elems + kFactorPad) * csize(prec));
   ALLOC(h->d_err, 2 * sizeof(int));
@@ -228,16 +168,11 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
   const std::vector<int> setup_lines = setup_classes(plan, (int)csize(prec), nullptr).order;
   if (hipMemcpyAsync(h->d_setup_lines, setup_lines.data(), setup_lines.size() * sizeof(int),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(h->d_line_one, h->plan.one.data(), h->plan.one.size(), hipMemcpyHostToDevice,
-                     s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)   // the host vector goes out of scope
     return bail(HELM_EHIP, "copying the plan failed");
-  h->apply_bytes_per_rhs = sweep_bytes_per_rhs(plan, prec);
-  const KernelWork kw = kernel_work(plan, prec);
-  h->kernel_bytes_per_rhs = kw.factor + kw.vec;
-  h->kernel_factor_bytes = kw.factor;
-  h->kernel_vector_bytes_per_rhs = kw.vec;
-  h->kernel_flops_per_rhs = 8.0 * kw.entries;
+  h->sweep_factor_entries = sweep_entries(plan);
+  h->sweep_factor_bytes = h->sweep_factor_entries * csize(prec);
+  h->apply_bytes_per_rhs = h->sweep_factor_bytes + 32.0 * N;
   LaunchTimer t_setup;
   hipEvent_t ev = t_setup.begin(s);
   if (launch_coefficients(h, c_dev, true, s) != hipSuccess) return bail(HELM_EHIP, "coefficient kernels failed");
@@ -276,12 +211,27 @@ static int check_exchange(helm_handle* h, hipStream_t s) {
   return HELM_OK;
 }
 
+// the first sweep of a configuration (and batch size) in the process times the candidate
+// launch shapes and keeps the fastest (HELM_AUTOTUNE=0 turns this off; HELM_TUNE_CACHE names
+// a file of earlier choices, read and appended)
+static int first_use_tune(helm_handle* h, int R, hipStream_t s) {
+  if (h->variant >= 0) return HELM_OK;
+  const char* env = std::getenv("HELM_AUTOTUNE");
+  if (env && env[0] == '0') return HELM_OK;
+  const std::string key = tune_key(h, R);
+  if (tuned_variant(key) >= 0) return HELM_OK;
+  const char* path = std::getenv("HELM_TUNE_CACHE");
+  return tune_and_remember(h, R, key, path, nullptr, nullptr, s);
+}
+
 static int apply_impl(helm_handle* h, const void* r, void* z, int R, bool adjoint, void* stream) {
   int rc = check_batch(h, r, z, R);
   if (rc != HELM_OK) return rc;
   const long long N = (long long)h->n * h->n * h->n;
   hipStream_t s = S(stream);
   h->last_stream = s;
+  rc = first_use_tune(h, R, s);
+  if (rc != HELM_OK) return rc;
   HIP_TRY(launch_apply(h, r, true, N, z, true, N, R, nullptr, adjoint, s));
   if (h->pairs_used) return check_exchange(h, s);
   return HELM_OK;
@@ -312,6 +262,8 @@ int helm_solve(helm_handle* h, const void* f_dev, void* u_dev, int R, double tol
   if (maxit < 0) return fail(HELM_EINVAL, "maxit must be >= 0");
   hipStream_t s = S(stream);
   h->last_stream = s;
+  rc = first_use_tune(h, R, s);
+  if (rc != HELM_OK) return rc;
   std::string msg;
   rc = fgmres_solve(h, (const double2*)f_dev, (double2*)u_dev, R, tol, restart, maxit, adjoint != 0,
                     iters_host, relres_host, s, msg);
@@ -434,7 +386,7 @@ int helm_line_factors(const helm_handle* h, int zg, int yg, void* dst_dev, int* 
   const size_t line = (size_t)zg * h->plan.Gy + yg;
   const int B = h->plan.line_B[line];
   if (B_out) *B_out = B;
-  if (mid_out) *mid_out = h->plan.line_mid(zg, yg);
+  if (mid_out) *mid_out = h->plan.line_mid();
   if (!dst_dev) return HELM_OK;
   const size_t cs = csize(h->prec);
   HIP_TRY(hipMemcpyAsync(dst_dev, (const char*)h->factors + (size_t)h->plan.line_off[line] * cs,
@@ -453,118 +405,100 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
   return HELM_OK;
 }
 
-int helm_set_split(helm_handle* h, int on) {
+int helm_set_launch(helm_handle* h, int variant) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
-  if (on != 0 && on != 1) return fail(HELM_EINVAL, "on must be 0 or 1");
-  h->split = on;
+  if (variant < -1 || (variant >= 0 && !sweep_variant_valid(h, variant)))
+    return fail(HELM_EINVAL, "variant " + std::to_string(variant) + " does not cover this handle's blocks");
+  h->variant = variant;
   return HELM_OK;
 }
 
-int helm_set_launch(helm_handle* h, int lanes_per_row) {
+int helm_sweep_shape(const helm_handle* h, int R, int* variant, char* name, int name_len) {
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
-  if (lanes_per_row != 0 && lanes_per_row != 4 && lanes_per_row != 8 && lanes_per_row != 16)
-    return fail(HELM_EINVAL, "lanes_per_row must be 0, 4, 8 or 16");
-  h->lanes_override = lanes_per_row;
+  if (R < 1) return fail(HELM_EINVAL, "R must be >= 1");
+  const int k = sweep_variant_for(h, R);
+  if (variant) *variant = k;
+  if (name && name_len > 0) {
+    const std::string nm = sweep_variant_name(h->prec == HELM_C64, k);
+    std::snprintf(name, (size_t)name_len, "%s", nm.c_str());
+  }
   return HELM_OK;
 }
+
+int helm_set_exchange_test(helm_handle* h, int drop_publish, unsigned spin_limit) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (drop_publish != 0 && drop_publish != 1) return fail(HELM_EINVAL, "drop_publish must be 0 or 1");
+  h->drop_publish = drop_publish;
+  h->spin_limit = spin_limit ? spin_limit : (1u << 20);
+  return HELM_OK;
+}
+
+}  // extern "C"
 
 // ---- launch-shape autotuner -------------------------------------------------------------
-static std::string tune_key(const helm_handle* h) {
-  const int B = h->plan.maxB_front;
-  return "n=" + std::to_string(h->n) + ",maxB=" + std::to_string(B) +
-         ",prec=" + (h->prec == HELM_C64 ? "c64" : "c128");
-}
-
 static int tune_lookup(const char* path, const std::string& key) {
   FILE* fp = std::fopen(path, "r");
-  if (!fp) return 0;
+  if (!fp) return -1;
   char line[512];
-  int found = 0;
+  int found = -1;
   const std::string pat = "\"key\": \"" + key + "\"";
   while (std::fgets(line, sizeof line, fp)) {
     if (std::strstr(line, pat.c_str())) {
-      const char* q = std::strstr(line, "\"lanes\":");
-      int v = 0;
-      if (q && std::sscanf(q + 8, "%d", &v) == 1 && (v == 4 || v == 8 || v == 16)) found = v;
+      const char* q = std::strstr(line, "\"variant\":");
+      int v = -1;
+      if (q && std::sscanf(q + 10, "%d", &v) == 1) found = v;
     }
   }
   std::fclose(fp);
   return found;
 }
 
-int helm_autotune(helm_handle* h, const char* cache_path, int* lanes_out, double* ns_per_step,
-                  void* stream) {
-  if (!h) return fail(HELM_EINVAL, "handle is NULL");
-  const std::string key = tune_key(h);
-  if (cache_path) {
-    int v = tune_lookup(cache_path, key);
-    if (v) {
-      h->lanes_override = v;
-      if (lanes_out) *lanes_out = v;
-      if (ns_per_step) *ns_per_step = 0.0;
+int tune_and_remember(helm_handle* h, int R, const std::string& key, const char* path, int* out,
+                      double* ms_out, hipStream_t s) {
+  if (path) {
+    const int v = tune_lookup(path, key);
+    if (v >= 0 && sweep_variant_valid(h, v)) {
+      remember_variant(key, v);
+      if (out) *out = v;
+      if (ms_out) *ms_out = 0.0;
       return HELM_OK;
     }
   }
-  hipStream_t s = S(stream);
-  // an interior line with the largest two-chain block: x3-group Gz/2 and x2-group Gy/2, or
-  // the groups just below the middle ones with two fronts
-  const Plan& P = h->plan;
-  const int g = P.fronts == 2 ? P.zmid - 1 : P.Gz / 2;
-  const int l = P.fronts_inner == 2 ? P.ymid - 1 : P.Gy / 2;
-  const int B = P.line_B[(size_t)g * P.Gy + l];
-  const size_t elems = (size_t)h->n * B;
-  double2 *r = nullptr, *x = nullptr;
-  HIP_TRY(pool_alloc((void**)&r, elems * sizeof(double2), s));
-  if (pool_alloc((void**)&x, elems * sizeof(double2), s) != hipSuccess) {
-    pool_free(r, s);
-    return fail(HELM_ENOMEM, "autotune buffer allocation failed");
-  }
-  (void)hipMemsetAsync(r, 0, elems * sizeof(double2), s);
-  const int saved = h->lanes_override;
-  int best = 0;
-  double best_ns = 0.0;
-  const int reps = 8;
-  for (int lanes : {16, 8, 4}) {
-    h->lanes_override = lanes;
-    if (launch_line_solve(h, g, l, r, x, 1, false, s) != hipSuccess) {   // warm-up / validity
-      (void)hipGetLastError();
-      continue;
-    }
-    hipEvent_t a = nullptr, b = nullptr;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
-    (void)hipEventRecord(a, s);
-    bool ok = true;
-    for (int k = 0; k < reps && ok; ++k) ok = launch_line_solve(h, g, l, r, x, 1, false, s) == hipSuccess;
-    (void)hipEventRecord(b, s);
-    float ms = 0.f;
-    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
-      const double ns = ms * 1e6 / (reps * (double)h->n);   // per x1-block of a line solve
-      if (!best || ns < best_ns) {
-        best = lanes;
-        best_ns = ns;
-      }
-    }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-  }
-  pool_free(r, s);
-  pool_free(x, s);
-  if (!best) {
-    h->lanes_override = saved;
-    return fail(HELM_EHIP, "no launch shape could be timed");
-  }
-  h->lanes_override = best;
-  if (lanes_out) *lanes_out = best;
-  if (ns_per_step) *ns_per_step = best_ns;
-  if (cache_path) {
-    FILE* fp = std::fopen(cache_path, "a");
+  int best = -1;
+  double ms = 0.0;
+  HIP_TRY(autotune_sweep(h, R, &best, &ms, s));
+  int bad = 0;
+  HIP_TRY(take_exchange_error(h, s, &bad));
+  if (bad) return fail(HELM_EHIP, "a sweep exchange timed out while tuning");
+  remember_variant(key, best);
+  if (out) *out = best;
+  if (ms_out) *ms_out = ms;
+  if (path) {
+    FILE* fp = std::fopen(path, "a");
     if (fp) {
-      std::fprintf(fp, "{\"key\": \"%s\", \"lanes\": %d, \"ns_per_step\": %.1f}\n", key.c_str(),
-                   best, best_ns);
+      std::fprintf(fp, "{\"key\": \"%s\", \"variant\": %d, \"shape\": \"%s\", \"ms_per_sweep\": %.3f}\n",
+                   key.c_str(), best, sweep_variant_name(h->prec == HELM_C64, best).c_str(), ms);
       std::fclose(fp);
     }
   }
+  return HELM_OK;
+}
+
+extern "C" {
+
+int helm_autotune(helm_handle* h, int R, const char* cache_path, int* variant_out, double* ms_per_sweep,
+                  void* stream) {
+  if (!h) return fail(HELM_EINVAL, "handle is NULL");
+  if (R < 1) return fail(HELM_EINVAL, "R must be >= 1");
+  hipStream_t s = S(stream);
+  h->last_stream = s;
+  int best = -1;
+  double ms = 0.0;
+  const int rc = tune_and_remember(h, R, tune_key(h, R), cache_path, &best, &ms, s);
+  if (rc != HELM_OK) return rc;
+  h->variant = best;
+  if (variant_out) *variant_out = best;
+  if (ms_per_sweep) *ms_per_sweep = ms;
   return HELM_OK;
 }
 
@@ -585,10 +519,8 @@ int helm_get_stats(helm_handle* h, helm_stats* out) {
   out->kernel_launches = h->t_kernel.launches;
   out->kernel_rhs = h->t_kernel.rhs;
   out->kernel_ms = h->t_kernel.ms;
-  out->kernel_bytes_per_rhs = h->kernel_bytes_per_rhs;
-  out->kernel_factor_bytes = h->kernel_factor_bytes;
-  out->kernel_vector_bytes_per_rhs = h->kernel_vector_bytes_per_rhs;
-  out->kernel_flops_per_rhs = h->kernel_flops_per_rhs;
+  out->kernel_bytes = h->t_kernel.bytes;
+  out->kernel_flops = h->t_kernel.flops;
   return HELM_OK;
 }
 

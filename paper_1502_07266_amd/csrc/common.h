@@ -52,40 +52,8 @@ template <> __host__ __device__ inline double2 cvt<double2, float2>(float2 s) {
   return make_double2((double)s.x, (double)s.y);
 }
 
-// ---------------------------------------------------------------------------------------
-// LDS of the sweep kernels
-// ---------------------------------------------------------------------------------------
-// largest NC * CW of the sweep's launch shapes and largest block B (the one-chain shapes of
-// the two-front middle slab reach 8 x 16 columns); sizes the published vectors and the zero
-// and junk rows
+// largest block B of a line and largest published vector of the sweep's launch shapes
 constexpr int kZMax = 128;
-
-// LDS layout of the sweep kernels, in complex elements from the base (the step table follows
-// at a 16-byte boundary): line vector, published vectors, zero and junk rows, couplings, the
-// per-step couplings and the per-step table (2 (n + 3) entries each: two chains of at most
-// n + 3, or one chain of at most 2n + 1).
-struct LdsLayout {
-  int ybuf, zb, zeros, junk, cf, cb, ctab;
-  size_t tab_byte, bytes;
-  __host__ __device__ LdsLayout(int n, int maxB, int csz) {
-    ybuf = 0;
-    zb = n * maxB;
-    zeros = zb + 4 * kZMax;
-    junk = zeros + kZMax;
-    cf = junk + kZMax;
-    cb = cf + (n + 2);
-    ctab = cb + (n + 2);
-    tab_byte = ((size_t)(ctab + 2 * (n + 3)) * csz + 15) / 16 * 16;
-    bytes = tab_byte + 2 * (size_t)(n + 3) * 16;
-  }
-};
-
-// largest block of the two-chain sweep shapes (two chains of B rows x NC lanes per workgroup):
-// 8 x 8 or 4 x 16.  (A 4 x 20 shape for blocks up to 80 was measured: at 640 threads it
-// spills registers and keeps a ring of only 2 blocks, and its lines took as long as one
-// chain over twice the steps.)
-constexpr int kTwoChainMaxB64 = 64;
-constexpr int kTwoChainMaxB128 = 64;
 
 // ---------------------------------------------------------------------------------------
 // partition of an axis into groups and their auxiliary windows
@@ -109,16 +77,11 @@ struct Plan {
   std::vector<int> line_B;            // [Gz*Gy]
   long long total_elems = 0;          // sum over lines of n * B^2
   int maxB = 0, maxW = 0;             // over all lines / windows
-  int maxB_front = 0, maxB_mid = 0;   // largest block of the two-chain / one-chain lines
-  int two_cap = 0;                    // largest block two chains per workgroup can solve
-  std::vector<unsigned char> one;     // [Gz*Gy] line solved by one chain (see build_plan)
+  int maxB_front = 0;                 // over the lines on no middle group
   const GroupInfo& zg(int g) const { return groups[g]; }
   const GroupInfo& yg(int l) const { return groups[Gz + l]; }
-  // lines whose launch holds a block too large for two chains per workgroup are eliminated
-  // in x1 order and solved by one chain spanning the workgroup (see build_plan)
-  bool one_chain(int g, int l) const { return one[(size_t)g * Gy + l] != 0; }
-  // middle block of line (g, l)'s elimination order: both ends towards n/2, or n - 1 (x1 order)
-  int line_mid(int g, int l) const { return one_chain(g, l) ? n - 1 : n / 2; }
+  // every line is eliminated from both ends towards its middle block n/2 (Sec. 3, that order)
+  int line_mid() const { return n / 2; }
 };
 
 // builds the plan; returns HELM_OK or HELM_EINVAL (with a message)
@@ -151,15 +114,6 @@ __host__ __device__ inline int2 sweep_at(int pass, int G, int mid, int front, in
   }
 }
 
-// one launch of the sweep: outer pass and its fronts, the range of the pass's slab steps,
-// inner pass and its fronts, line chains per workgroup, largest block, and whether it is a
-// launch of the dominant (two-chain) kernel
-struct SweepLaunch {
-  int pass, nfront, slab_lo, slab_hi, ipass, ninner, chains, maxB;
-  bool timed;
-};
-std::vector<SweepLaunch> sweep_schedule(const Plan& P);
-
 // ---------------------------------------------------------------------------------------
 // device-time accounting: event pairs recorded around launches, resolved lazily
 // ---------------------------------------------------------------------------------------
@@ -167,10 +121,11 @@ struct LaunchTimer {
   struct Pending {
     hipEvent_t a, b;
     long long rhs;
+    double bytes, flops;
   };
   std::vector<Pending> pending;
   long long launches = 0, rhs = 0;
-  double ms = 0.0;
+  double ms = 0.0, bytes = 0.0, flops = 0.0;
   // records the start event; returns it for end()
   hipEvent_t begin(hipStream_t s) {
     hipEvent_t a = nullptr;
@@ -181,7 +136,7 @@ struct LaunchTimer {
     }
     return a;
   }
-  void end(hipEvent_t a, hipStream_t s, long long nrhs) {
+  void end(hipEvent_t a, hipStream_t s, long long nrhs, double nbytes = 0.0, double nflops = 0.0) {
     if (!a) return;
     hipEvent_t b = nullptr;
     if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
@@ -189,7 +144,7 @@ struct LaunchTimer {
       if (b) (void)hipEventDestroy(b);
       return;
     }
-    pending.push_back({a, b, nrhs});
+    pending.push_back({a, b, nrhs, nbytes, nflops});
     if (pending.size() >= 2048) flush();   // bounds the events alive between reads
   }
   void flush() {
@@ -199,6 +154,8 @@ struct LaunchTimer {
         ms += t;
         launches += 1;
         rhs += p.rhs;
+        bytes += p.bytes;
+        flops += p.flops;
       }
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
@@ -208,7 +165,7 @@ struct LaunchTimer {
   void reset() {
     flush();
     launches = rhs = 0;
-    ms = 0.0;
+    ms = bytes = flops = 0.0;
   }
 };
 
@@ -219,7 +176,7 @@ struct helm_handle {
   Plan plan;
   int n = 0, prec = HELM_C64, device = 0;
   double omega = 0, h = 0, C = 0, C_mv = 0;
-  int lanes_override = 0;
+  int variant = -1;                // sweep launch shape (sweep_variants.h); -1: automatic
 
   // device data
   double* kappa = nullptr;         // n^3, omega^2 / c^2
@@ -228,7 +185,6 @@ struct helm_handle {
   double2* coef = nullptr;         // [4][n+2]: A[m,m-1], A[m,m+1], A^H[m,m-1], A^H[m,m+1]
   double2* diag = nullptr;         // [n+2]: -s_m (s_{m+1/2} + s_{m-1/2}) / h^2
   GroupInfo* d_groups = nullptr;   // [Gz + Gy]
-  unsigned char* d_line_one = nullptr;   // [Gz*Gy] Plan::one
   int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_classes order
   long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128
@@ -236,32 +192,33 @@ struct helm_handle {
 
   // timing
   LaunchTimer t_apply, t_matvec;
-  LaunchTimer t_kernel;            // the sweep's dominant kernel (see helm_stats)
+  LaunchTimer t_kernel;            // the sweep kernel's launches (see helm_stats)
   double setup_ms = 0.0;
   double apply_bytes_per_rhs = 0.0;
-  double kernel_bytes_per_rhs = 0.0;
-  double kernel_factor_bytes = 0.0, kernel_vector_bytes_per_rhs = 0.0, kernel_flops_per_rhs = 0.0;
+  double sweep_factor_bytes = 0.0;    // factor bytes one sweep reads (every block visit once)
+  double sweep_factor_entries = 0.0;  // factor entries one sweep visits
 
-  // apply workspace (grown on demand)
+  // sweep workspace (grown on demand): slab iterates, received layers, exchange words (an
+  // error word, then the words of every launch slot); xseq numbers exchange events across
+  // launches; spin_limit and drop_publish are the exchange's bound and failure-injection hook
   void* slab_scratch = nullptr;
   size_t slab_scratch_bytes = 0;
-  // paired two-chain launches (helm_set_split): error word and exchange slots for xpairs
-  // workgroup pairs; xseq numbers the lines across launches
-  int split = 1;
+  void* layer = nullptr;
+  size_t layer_bytes = 0;
   void* xbuf = nullptr;
-  size_t xpairs = 0;
+  size_t xbytes = 0;
   unsigned long long xseq = 0;
-  bool pairs_used = false;         // a paired launch ran since the error word was last taken
+  bool pairs_used = false;         // a sweep ran since the error word was last taken
+  unsigned spin_limit = 1u << 20;
+  int drop_publish = 0;
   int* d_rhs_idx = nullptr;
   int rhs_idx_cap = 0;
   // the stream of the last call: the handle's buffers go back to the pool on it
   hipStream_t last_stream = nullptr;
 };
 
-// layout of helm_handle::xbuf: an error word (padded), then per pair, chain and line parity a
-// slot of kZMax values of up to four 32-bit pieces, one tagged 64-bit word each
+// bytes before the exchange words in helm_handle::xbuf (the error word, padded)
 constexpr size_t kXHead = 256;
-constexpr size_t kXSlot = (size_t)kZMax * 4;
 // waits for stream s, then *bad = nonzero if a paired line solve gave up waiting for its
 // partner since the flag was last taken (and clears it)
 hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad);
@@ -271,8 +228,8 @@ hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad);
 // ---------------------------------------------------------------------------------------
 hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables, hipStream_t s);
 hipError_t launch_setup(helm_handle* h, hipStream_t s);
-// the setup's launches: lines in class order (small two-chain blocks, other two-chain
-// blocks, one-chain lines), the count and largest block of each class
+// the setup's launches: lines in class order (blocks whose two B x B copies fit a quarter of
+// the LDS, other blocks up to 64, larger blocks), the count and largest block of each class
 struct SetupClasses {
   std::vector<int> order;
   int count[3];
@@ -288,8 +245,26 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
                         hipStream_t s);
-// device scratch of an apply of R right-hand sides (slab iterates and exchange slots)
+// device scratch of an apply of R right-hand sides (slab iterates, layers, exchange words)
 size_t apply_scratch_bytes(const helm_handle* h, int R);
+// the sweep's launch shape for R right-hand sides: the handle's, the autotuner's or the default
+int sweep_variant_for(const helm_handle* h, int R);
+bool sweep_variant_valid(const helm_handle* h, int k);
+std::string sweep_variant_name(bool c64, int k);
+std::string tune_key(const helm_handle* h, int R);
+int tuned_variant(const std::string& key);
+void remember_variant(const std::string& key, int k);
+std::vector<int> tune_candidates(const helm_handle* h);
+// times a sweep of R right-hand sides with every candidate variant; the fastest and its time
+hipError_t autotune_sweep(helm_handle* h, int R, int* best, double* best_ms, hipStream_t s);
+// x[0..count) = 1 + 0i
+hipError_t fill_ones(double2* x, long long count, hipStream_t s);
+// the autotuner's choice for key (from the file at path when it holds one, else measured and
+// appended there), remembered for the process; *out and *ms_out may be null
+int tune_and_remember(helm_handle* h, int R, const std::string& key, const char* path, int* out,
+                      double* ms_out, hipStream_t s);
+// whether the sweep kernel has a launch shape and LDS room for the plan's blocks (else why)
+bool sweep_plan_supported(const Plan& P, int prec, std::string& why);
 hipError_t launch_line_solve(helm_handle* h, int zg, int yg, const double2* r, double2* x, int R,
                              bool adjoint, hipStream_t s);
 // y = A u (mode 0) or y = f - A u (mode 1); u complex128 or complex64 (u64 = false)

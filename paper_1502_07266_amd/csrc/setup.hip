@@ -43,7 +43,6 @@ struct SetupArgs {
                      // each (workgroup 2w + h takes half h of line lines[w]); 2: their middle
                      // blocks, after part 1
   const int* lines;  // the lines of this launch (workgroup w takes line lines[w])
-  const unsigned char* line_one;   // per line: solved by one chain (x1 order)
   double h;
   const GroupInfo* groups;
   const long long* line_off;
@@ -97,12 +96,11 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   __syncthreads();
 
   // Two-sided elimination order: blocks 0..m-1 upwards, blocks n-1..m+1 downwards, and the
-  // middle block m last, whose Schur complement takes the update from both sides; m = n/2
-  // (integer division), or m = n - 1 (the order of Sec. 3) for the lines the sweep solves with
-  // one chain (blocks too large for two chains).  It is the block LDU of Sec. 3 with the
-  // blocks in that order (every block eliminated is an end of the remaining chain, so there
-  // is no fill); the sweep runs the two halves of each line solve as two concurrent chains.
-  const int mid = a.line_one[line] ? n - 1 : n / 2;
+  // middle block m = n/2 (integer division) last, whose Schur complement takes the update
+  // from both sides.  It is the block LDU of Sec. 3 with the blocks in that order (every
+  // block eliminated is an end of the remaining chain, so there is no fill); the sweep runs
+  // the two halves of each line solve as two concurrent chains.
+  const int mid = n / 2;
   // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
   C* Tlds = S + B * B;
   const C* Tprev = Tlds;
@@ -273,9 +271,9 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
 
 }  // namespace
 
-// The setup's line classes, each one launch with LDS for its own largest block: two-chain
-// lines whose two B x B blocks take at most kSmallLds (several workgroups share a CU), the
-// other two-chain lines, and the one-chain lines (1024 threads each).
+// The setup's line classes, each with LDS for its own largest block: lines whose two B x B
+// blocks take at most kSmallLds (several workgroups share a CU), the other lines with blocks
+// up to 64, and the larger blocks (those of the lines on a middle group; 1024 threads).
 SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subset) {
   SetupClasses c;
   std::vector<int> all;
@@ -290,7 +288,7 @@ SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subse
   for (int k = 0; k < 3; ++k)
     for (int line : *subset) {
       const int B = P.line_B[line];
-      const int cls = P.one[line] ? 2 : (2 * (size_t)B * B * csz <= kSmallLds ? 0 : 1);
+      const int cls = B > 64 ? 2 : (2 * (size_t)B * B * csz <= kSmallLds ? 0 : 1);
       if (cls != k) continue;
       c.order.push_back(line);
       c.count[k] += 1;
@@ -316,7 +314,6 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
   a.zmid = P.zmid;
   a.fronts_inner = P.fronts_inner;
   a.ymid = P.ymid;
-  a.line_one = h->d_line_one;
   a.h = h->h;
   a.groups = h->d_groups;
   a.line_off = h->d_line_off;
@@ -344,7 +341,7 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
     if (e == hipSuccess) e = hipEventCreateWithFlags(&done[k - 1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamWaitEvent(side[k - 1], start, 0);
     if (e == hipSuccess)
-      e = k == 2 ? setup_launch<kSetupThreadsBig>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1], false)
+      e = k == 2 ? setup_launch<kSetupThreadsBig>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1], true)
                  : setup_launch<kSetupThreads>(h, a, d_lines + first, c.count[k], c.maxB[k], side[k - 1], true);
     if (e == hipSuccess) e = hipEventRecord(done[k - 1], side[k - 1]);
     first += c.count[k];

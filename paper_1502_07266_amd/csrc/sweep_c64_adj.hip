@@ -1,0 +1,13 @@
+// Instantiations of the sweep kernel: complex64 sweeps, adjoint (M^{-H}), writing complex128 output.
+#include "sweep_kernel.h"
+#include "sweep_variants.h"
+
+const void* sweep_kernel_c64_adj(bool z64, int k) {
+  if (!z64) return sweep_kernel_c64_adj_z32(k);
+  int idx = 0;
+#define X(NCA, CWA, DA, NCB, CWB, DB) \
+  if (idx++ == k) return (const void*)sweepk::k_sweep<float, double2, double2, NCA, CWA, DA, NCB, CWB, DB, true>;
+  HELM_SWEEP_VARIANTS_C64(X)
+#undef X
+  return nullptr;
+}

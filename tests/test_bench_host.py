@@ -30,20 +30,16 @@ def test_group_count_matches_the_oracle_partition(n, b, d):
 
 def test_dependent_steps_of_the_127_cubed_workload():
     # 26 groups per axis, middle group 13: 13 front groups below it, 12 above (the chain runs
-    # through the 13); a two-sided line solve takes 127 steps, a one-chain one 253.  As
-    # factored at this width only the middle-middle line (81 unknowns per block) takes one
-    # chain: per front slab 2 x 13 inner-front lines and the middle line, all two-sided; the
-    # middle slab the same but its middle line one chain.
-    S2, S1 = 127, 253
-    two_sided_but_middle = lambda g, l: S1 if (g, l) == (13, 13) else S2
-    sweep, kernel = bench.dependent_steps(127, 5, 5, 2, 2, two_sided_but_middle)
-    front_slab = 2 * 13 * S2 + S2
-    middle_slab = 2 * 13 * S2 + S1
-    assert sweep == 2 * 13 * front_slab + middle_slab == 92709
+    # through the 13); every line solve is two-sided, 127 dependent steps.  Per slab 13 lines
+    # forward, the middle line, 13 backward; per sweep 13 slabs forward, the middle slab, 13
+    # backward.
+    S2 = 127
+    sweep, kernel = bench.dependent_steps(127, 5, 5, 2, 2)
+    assert sweep == 27 * 27 * S2 == 92583
     assert kernel == 13 * S2
-    # the default: every line on a middle group one chain
-    sweep_all_middle, _ = bench.dependent_steps(127, 5, 5, 2, 2)
-    assert sweep_all_middle == 2 * 13 * (2 * 13 * S2 + S1) + (2 * 13 * S1 + S1)
-    # one front per axis: 2G - 1 slabs of 2G - 1 lines, all two-sided
+    # a line that took more steps lengthens the chain by what it adds
+    longer = lambda g, l: 253 if (g, l) == (13, 13) else S2
+    assert bench.dependent_steps(127, 5, 5, 2, 2, longer)[0] == 92583 + 126
+    # one front per axis: 2G - 1 slabs of 2G - 1 lines
     G = bench.group_count(127, 5, 5, 1)
     assert bench.dependent_steps(127, 5, 5, 1, 1)[0] == (2 * G - 1) ** 2 * S2

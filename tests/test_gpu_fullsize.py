@@ -79,7 +79,7 @@ def c1_two_front_oracle():
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1.2e-5)])
 def test_c1_two_front_apply_matches_oracle(c1_two_front_oracle, prec, tol):
     """Two fronts at 31^3: the middle slab's lines have blocks of 13 x 7 = 91 unknowns (moving
-    PML on both sides in x3), solved by the one-chain shapes."""
+    PML on both sides in x3), solved with the kernel's second launch shape."""
     wl, M = c1_two_front_oracle
     n = wl["n"]
     x = inputs.random_rhs(n, 2, seed=22)
@@ -103,8 +103,8 @@ def c1_two_inner_front_oracle():
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1.2e-5)])
 def test_c1_two_inner_front_apply_matches_oracle(c1_two_inner_front_oracle, prec, tol):
-    """Two inner fronts at 31^3 (one outer front): three launches per slab; the middle
-    x2-line of every slab has blocks of 13 x 7 = 91 unknowns, solved by one chain."""
+    """Two inner fronts at 31^3 (one outer front): the middle x2-line of every slab has
+    blocks of 13 x 7 = 91 unknowns."""
     wl, M = c1_two_inner_front_oracle
     n = wl["n"]
     x = inputs.random_rhs(n, 2, seed=24)
@@ -184,7 +184,7 @@ def test_c3_sweep_dot_test_and_linearity(c3_handles):
 def test_c3_two_fronts_both_axes():
     """127^3, complex64, two fronts in x3 and in x2 (the launch configuration the benchmark
     times): sampled line factors, including lines on the middle x2-group (two chains up to 64
-    unknowns per block) and the middle-middle line (one chain), against the oracle's; the
+    unknowns per block) and the middle-middle line (81), against the oracle's; the
     adjoint dot test and linearity of the whole sweep."""
     from paper_1502_07266_amd.binding import Helm
     wl, _ = workload("c3")
@@ -197,7 +197,7 @@ def test_c3_two_fronts_both_axes():
              fronts=2, fronts_inner=2)
     for (g, l) in [(0, 0), (mid - 1, mid), (mid, mid), (mid + 3, mid - 1), (len(Gt) - 1, mid + 1)]:
         ln = O.LineFactors(prob, Gt, g, Gt, l, order=H.line_order(g, l))
-        assert (H.line_order(g, l) == "up") == (ln.B > 64), (g, l, ln.B)
+        assert H.line_order(g, l) == "two-sided", (g, l, ln.B)
         ref = np.stack(ln.block_T)
         T = H.line_factors(g, l).cpu().numpy()
         err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
