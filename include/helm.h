@@ -117,6 +117,24 @@ int helm_setup(const helm_grid* grid, const double* c_dev, double omega, const h
 int helm_apply(helm_handle* h, const void* r_dev, void* z_dev, int R, void* stream);
 
 /*
+ * helm_apply_static -- helm_apply (adjoint = 0) or helm_apply_adjoint (adjoint = 1) that
+ * allocates nothing, for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The sweep's scratch (slab
+ * iterates, received layers, exchange words) lives in a static device array of 128 MiB that
+ * each GPU the library runs on holds until the process ends; the right-hand sides are swept
+ * in chunks that fit in it (about 3.8 MB per right-hand side at 127^3 with complex64 factors
+ * and two fronts in both axes).  The launch shape is the handle's or the autotuner's earlier
+ * choice, else the default (this call never tunes).  Does not synchronise `stream` and does
+ * not report an exchange timeout (z then holds NaN there).  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (from different streams or threads) race and
+ * must not be made.
+ *   r_dev, z_dev : R*n^3 complex128 each (may not alias), as for helm_apply.
+ * Errors: HELM_EINVAL (NULL or aliasing vectors, R < 1, one right-hand side's scratch larger
+ * than the array), HELM_EHIP.
+ */
+int helm_apply_static(helm_handle* h, const void* r_dev, void* z_dev, int R, int adjoint, void* stream);
+
+/*
  * helm_apply_adjoint -- z = M^{-H} r: the conjugate transpose of helm_apply's operator (the
  * same forward-then-backward passes with the couplings of A^H and conjugate-transposed block
  * inverses).  Same arguments as helm_apply.

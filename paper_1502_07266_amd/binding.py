@@ -45,6 +45,7 @@ _SIGS = {
                         ctypes.POINTER(_P)]),
     "helm_apply": (_I, [_P, _P, _P, _I, _P]),
     "helm_apply_adjoint": (_I, [_P, _P, _P, _I, _P]),
+    "helm_apply_static": (_I, [_P, _P, _P, _I, _I, _P]),
     "helm_matvec": (_I, [_P, _P, _P, _I, _I, _P]),
     "helm_solve": (_I, [_P, _P, _P, _I, _D, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D), _P]),
     "helm_grad_c": (_I, [_P, _P, _P, _I, _P, _P]),
@@ -206,6 +207,16 @@ class Helm:
         z = torch.empty_like(r)
         fn = lib().helm_apply_adjoint if adjoint else lib().helm_apply
         _check(fn(self.handle, _ptr(r), _ptr(z), r.shape[0], _stream()), "helm_apply")
+        return z
+
+    def apply_static(self, r, adjoint=False):
+        """z = M^{-1} r (or M^{-H} r) with the library's static scratch: no allocation in the
+        library (z is allocated here by torch)."""
+        import torch
+        r = self._batch(r)
+        z = torch.empty_like(r)
+        _check(lib().helm_apply_static(self.handle, _ptr(r), _ptr(z), r.shape[0], int(adjoint), _stream()),
+               "helm_apply_static")
         return z
 
     def matvec(self, u, adjoint=False):

@@ -245,6 +245,17 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
 hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_stride, void* z,
                         bool z64, long long z_stride, int R, const int* rhs_idx, bool adjoint,
                         hipStream_t s);
+// caller-provided device scratch of a sweep: `bytes` at `base`, and the counter its exchange
+// tags are drawn from (shared by every user of that scratch)
+struct FixedScratch {
+  char* base;
+  size_t bytes;
+  unsigned long long* seq;
+};
+// z = M^{-1} r (or M^{-H}) for R right-hand sides, complex128 in and out, with every buffer
+// of the sweep in fx (the right-hand sides are launched in chunks that fit)
+hipError_t launch_apply_fixed(helm_handle* h, const void* r, void* z, int R, bool adjoint,
+                              const FixedScratch& fx, hipStream_t s);
 // device scratch of an apply of R right-hand sides (slab iterates, layers, exchange words)
 size_t apply_scratch_bytes(const helm_handle* h, int R);
 // the sweep's launch shape for R right-hand sides: the handle's, the autotuner's or the default

@@ -251,12 +251,16 @@ SweepArgs base_args(helm_handle* h) {
   return a;
 }
 
+__global__ void k_zero_word(int* w) { *w = 0; }
+
 // one sweep (or line solve) of R right-hand sides with variant k: cooperative launches of as
-// many right-hand sides as can be resident at once.  Input / output of launch slot s:
-// in + idx(s) in_stride, out + idx(s) out_stride, idx = rhs_idx or the identity.
+// many right-hand sides as can be resident at once (and, with fixed scratch, as fit in it).
+// Input / output of launch slot s: in + idx(s) in_stride, out + idx(s) out_stride, idx =
+// rhs_idx or the identity.  Without fixed scratch the handle's buffers are grown from the
+// pool and its own sequence numbers tag the exchanges.
 hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, int R, hipStream_t s,
                         bool timed, double bytes_per_launch_base, double vec_bytes_per_rhs,
-                        double flops_per_rhs) {
+                        double flops_per_rhs, const FixedScratch* fx = nullptr) {
   const Plan& P = h->plan;
   const bool c64 = h->prec == HELM_C64;
   if (!variant_valid(h, k)) return hipErrorInvalidValue;
@@ -269,13 +273,35 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, 
   hipError_t e = slots_per_launch(h, kern, tpc, sm, a.wpr, &slots);
   if (e != hipSuccess) return e;
   slots = std::min(slots, (R + 7) / 8 * 8);
-  e = ensure_buffers(h, slots, a.wpr, a.mode == 0, s);
+  unsigned long long* seq = &h->xseq;
+  if (fx) {
+    // [error word][exchange words][slab iterates][layers] for as many slots as fit
+    const size_t cs = csize(h);
+    const size_t wslot = (size_t)XLayout(P.n, P.maxW, pieces(h), a.wpr).per_slot * sizeof(unsigned long long);
+    const size_t sslot = a.mode == 0 ? (size_t)P.fronts * P.n * P.n * P.maxW * cs : 0;
+    const size_t lslot = a.mode == 0 ? (size_t)P.fronts * P.n * P.n * cs : 0;
+    const size_t per = wslot + sslot + lslot;
+    const long long fit = fx->bytes > kXHead + 3 * 256 ? (long long)((fx->bytes - kXHead - 3 * 256) / per) : 0;
+    if (fit < 1) return hipErrorOutOfMemory;
+    slots = (int)std::min<long long>(slots, fit);
+    char* xb = fx->base;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    a.xerr = reinterpret_cast<int*>(xb);
+    a.xw = reinterpret_cast<unsigned long long*>(xb + kXHead);
+    a.slab = xb + up(kXHead + slots * wslot);
+    a.layer = xb + up(kXHead + slots * wslot) + up(slots * sslot);
+    seq = fx->seq;
+    k_zero_word<<<1, 1, 0, s>>>(a.xerr);
+    e = hipGetLastError();
+  } else {
+    e = ensure_buffers(h, slots, a.wpr, a.mode == 0, s);
+    char* xb = static_cast<char*>(h->xbuf);
+    a.xerr = reinterpret_cast<int*>(xb);
+    a.xw = reinterpret_cast<unsigned long long*>(xb + kXHead);
+    a.slab = h->slab_scratch;
+    a.layer = h->layer;
+  }
   if (e != hipSuccess) return e;
-  char* xb = static_cast<char*>(h->xbuf);
-  a.xerr = reinterpret_cast<int*>(xb);
-  a.xw = reinterpret_cast<unsigned long long*>(xb + kXHead);
-  a.slab = h->slab_scratch;
-  a.layer = h->layer;
   // sequence numbers: every member's lines and slab steps in a launch stay below the span
   const unsigned long long span = (unsigned long long)(2 * P.Gz) * (2 * P.Gy) + 2 * P.Gz + 8;
   const int* idx = a.rhs_idx;
@@ -292,8 +318,8 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, 
       c.in = in0 + (size_t)r0 * a.in_stride * isz;
       c.out = out0 + (size_t)r0 * a.out_stride * osz;
     }
-    c.seq0 = h->xseq;
-    h->xseq += span;
+    c.seq0 = *seq;
+    *seq += span;
     const unsigned grid = (unsigned)(8 * a.wpr * ((Rc + 7) / 8));
     void* args[] = {&c};
     hipEvent_t ev = timed ? h->t_kernel.begin(s) : nullptr;
@@ -303,7 +329,7 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, 
       h->t_kernel.end(ev, s, Rc, bytes_per_launch_base + vec_bytes_per_rhs * Rc, flops_per_rhs * Rc);
     if (e != hipSuccess) return e;
   }
-  h->pairs_used = true;
+  if (!fx) h->pairs_used = true;
   return hipSuccess;
 }
 
@@ -342,6 +368,19 @@ hipError_t launch_apply(helm_handle* h, const void* r, bool r64, long long r_str
                               8.0 * h->sweep_factor_entries);
   h->t_apply.end(ev, s, R, 0.0, 0.0);
   return e;
+}
+
+hipError_t launch_apply_fixed(helm_handle* h, const void* r, void* z, int R, bool adjoint,
+                              const FixedScratch& fx, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  const long long N = (long long)h->n * h->n * h->n;
+  SweepArgs a = base_args(h);
+  a.mode = 0;
+  a.in = r;
+  a.out = z;
+  a.in_stride = a.out_stride = N;
+  a.rhs_idx = nullptr;
+  return run_launches(h, a, sweep_variant_for(h, R), true, adjoint, R, s, false, 0.0, 0.0, 0.0, &fx);
 }
 
 hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad) {
