@@ -104,7 +104,7 @@ def measured_traffic(workload, wl, fronts, fronts_inner):
     import hashlib
     name = traffic_profile_name(fronts, fronts_inner)
     path = os.path.join(ROOT, "profiles", f"{name}_c64_127cubed_32rhs_traffic.json")
-    src = os.path.join(ROOT, "paper_1502_07266_amd", "csrc", "sweep.hip")
+    src = os.path.join(ROOT, "paper_1502_07266_amd", "csrc", "sweep_kernel.h")
     if workload != "c3" or not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -406,6 +406,14 @@ def main():
                 continue
             fr64, fi64 = fr_, fi_
             break
+        # the autotuner's first run for this configuration stays out of the timed step
+        Ht = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c128", fronts=fr64,
+                  fronts_inner=fi64, C_moving=wl.get("C_moving", 0.0))
+        Ht.apply(F[:1])
+        Ht.apply(F)
+        Ht.close()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         H, u64, its64, rel64, rc64, st64 = run_step(Helm, c, wl, F, "c128", fr64, fi64)
         torch.cuda.synchronize()
         t3 = time.perf_counter()

@@ -280,26 +280,30 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
                     int adjoint, void* stream);
 
 /*
- * helm_set_launch -- choose the sweep's launch shape: variant k (0-based) of the library's
- * list (two shapes each: lanes per block row, columns per lane and factor-ring depth for the
- * lines on no middle group and for the others; helm_sweep_shape names them), or -1 for the
- * automatic choice (the autotuner's for this configuration, else the first listed variant
- * that covers the blocks).  Changes summation order only: results agree to rounding.
+ * helm_set_launch -- choose the sweep's launch shape: choice k >= 0 is variant k / 2 of the
+ * library's list (two shapes each: lanes per block row, columns per lane and factor-ring
+ * depth for the lines on no middle group and for the others) with workgroup placement k % 2
+ * (0: the workgroups of a right-hand side on one XCD; 1: each of its workgroups on its own
+ * XCD, so that one XCD serves one part of the factor stream to all right-hand sides);
+ * helm_sweep_shape names it.  -1 restores the automatic choice (the autotuner's for this
+ * configuration, else the first listed variant that covers the blocks, placement 1).
+ * Changes summation order only: results agree to rounding.
  * Errors: HELM_EINVAL (h NULL, k not a variant covering this handle's blocks).
  */
-int helm_set_launch(helm_handle* h, int variant);
+int helm_set_launch(helm_handle* h, int choice);
 
 /*
- * helm_sweep_shape -- the variant a sweep of R right-hand sides on this handle uses now
- * (*variant, may be NULL) and its description "NCxCW/ringD + NCxCW/ringD" (written to name,
- * at most name_len bytes with the terminating zero; name may be NULL).
+ * helm_sweep_shape -- the launch choice a sweep of R right-hand sides on this handle uses now
+ * (*variant, may be NULL) and its description "NCxCW/ringD + NCxCW/ringD, placement" (written
+ * to name, at most name_len bytes with the terminating zero; name may be NULL).
  */
 int helm_sweep_shape(const helm_handle* h, int R, int* variant, char* name, int name_len);
 
 /*
  * helm_autotune -- time one sweep of R right-hand sides (after a warm-up sweep) with each
  * candidate launch shape for this handle (the variants whose two shapes are each among the
- * two smallest covering its blocks, with every ring depth listed for them) and keep the
+ * two smallest covering its blocks, with every ring depth listed for them, in both
+ * placements) and keep the
  * fastest, for this handle (helm_set_launch) and for the process (handles of the same
  * configuration and batch size, rounded up to a multiple of 8, take it on their first
  * sweep).  If cache_path is not NULL the choice is looked up in / appended to that file (one

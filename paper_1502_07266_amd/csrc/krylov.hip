@@ -95,15 +95,19 @@ __global__ void __launch_bounds__(kDotThreads) k_dots(Basis<TX> X, int K,
   }
 }
 
-// out[q*ostride + k] = sum_chunks partial (mode 0), or sqrt(Re sum) (mode 1, norms)
-__global__ void k_dots_final(const double2* __restrict__ partial, int K, int nchunk,
-                             const int* __restrict__ idx, double2* __restrict__ out, int ostride,
-                             int mode) {
-  const int a = blockIdx.x, q = idx[a];
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    double2 s = make_double2(0.0, 0.0);
-    const double2* p = partial + ((long long)a * K + k) * nchunk;
-    for (int c = 0; c < nchunk; ++c) s = cadd(s, p[c]);
+// out[q*ostride + k] = sum_chunks partial (mode 0), or sqrt(Re sum) (mode 1, norms): one
+// workgroup per (k, active vector), the chunks' partial sums reduced across its threads
+__global__ void __launch_bounds__(kDotThreads) k_dots_final(const double2* __restrict__ partial, int K,
+                                                            int nchunk, const int* __restrict__ idx,
+                                                            double2* __restrict__ out, int ostride,
+                                                            int mode) {
+  __shared__ double2 red[kDotThreads / 64];
+  const int k = blockIdx.x, a = blockIdx.y, q = idx[a];
+  const double2* p = partial + ((long long)a * K + k) * nchunk;
+  double2 s = make_double2(0.0, 0.0);
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) s = cadd(s, p[c]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
     // a norm keeps NaN (fmax would turn it into 0 and a broken vector would look converged)
     if (mode == 1) s = make_double2(s.x > 0.0 ? sqrt(s.x) : (s.x == s.x ? 0.0 : s.x), 0.0);
     out[(long long)q * ostride + k] = s;
@@ -356,7 +360,7 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
     dim3 gd(nchunk, (unsigned)a.size());
     k_dots<double2><<<gd, kDotThreads, 0, s>>>(single(const_cast<double2*>(w), R, N), 1, w, N, ws.idx,
                                                ws.partial, nchunk, N);
-    k_dots_final<<<(unsigned)a.size(), 64, 0, s>>>(ws.partial, 1, nchunk, ws.idx, out, 1, 1);
+    k_dots_final<<<dim3(1, (unsigned)a.size()), kDotThreads, 0, s>>>(ws.partial, 1, nchunk, ws.idx, out, 1, 1);
     return hipGetLastError();
   };
 
@@ -438,7 +442,7 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
         double2* hp = pass == 0 ? ws.h1 : ws.h2;
         k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, j + 1, ws.W, N, ws.idx,
                                                                 ws.partial, nchunk, N);
-        k_dots_final<<<a, 64, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, hp, m + 1, 0);
+        k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, hp, m + 1, 0);
         k_axpy_multi<double2><<<dim3(nb, a), 256, 0, s>>>(ws.W, N, ws.V, hp, m + 1, j + 1, nullptr,
                                                           -1.0, ws.idx, N);
       }

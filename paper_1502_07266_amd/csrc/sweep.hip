@@ -150,25 +150,32 @@ std::vector<int> tune_candidates(const helm_handle* h) {
     if (!variant_valid(h, k) || vs[k].capA() < h->plan.maxB_front) continue;
     const bool a = vs[k].capA() == capA[0] || (capA.size() > 1 && vs[k].capA() == capA[1]);
     const bool b = vs[k].capB() == capB[0] || (capB.size() > 1 && vs[k].capB() == capB[1]);
-    if (a && b) out.push_back(k);
+    if (a && b) {
+      out.push_back(2 * k);
+      out.push_back(2 * k + 1);
+    }
   }
   return out;
 }
 
+// A launch choice c is variant c / 2 of sweep_variants with workgroup placement c % 2
+// (sweep_kernel.h, k_sweep): 0 a right-hand side's members on one XCD, 1 one member per XCD.
 int sweep_variant_for(const helm_handle* h, int R) {
   if (h->variant >= 0) return h->variant;
   const int t = tuned_variant(tune_key(h, R));
-  return t >= 0 ? t : default_variant(h);
+  return t >= 0 ? t : 2 * default_variant(h) + 1;
 }
 
-bool sweep_variant_valid(const helm_handle* h, int k) { return variant_valid(h, k); }
+bool sweep_variant_valid(const helm_handle* h, int c) { return c >= 0 && variant_valid(h, c / 2); }
 
-std::string sweep_variant_name(bool c64, int k) {
+std::string sweep_variant_name(bool c64, int c) {
   const auto& vs = sweep_variants(c64);
-  if (k < 0 || k >= (int)vs.size()) return "none";
+  const int k = c / 2;
+  if (c < 0 || k >= (int)vs.size()) return "none";
   const SweepVariant& v = vs[k];
   return std::to_string(v.nca) + "x" + std::to_string(v.cwa) + "/ring" + std::to_string(v.da) + " + " +
-         std::to_string(v.ncb) + "x" + std::to_string(v.cwb) + "/ring" + std::to_string(v.db);
+         std::to_string(v.ncb) + "x" + std::to_string(v.cwb) + "/ring" + std::to_string(v.db) +
+         (c % 2 ? ", one member per XCD" : ", one right-hand side per XCD");
 }
 
 namespace {
@@ -258,12 +265,14 @@ __global__ void k_zero_word(int* w) { *w = 0; }
 // Input / output of launch slot s: in + idx(s) in_stride, out + idx(s) out_stride, idx =
 // rhs_idx or the identity.  Without fixed scratch the handle's buffers are grown from the
 // pool and its own sequence numbers tag the exchanges.
-hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, int R, hipStream_t s,
+hipError_t run_launches(helm_handle* h, SweepArgs a, int choice, bool z64, bool adj, int R, hipStream_t s,
                         bool timed, double bytes_per_launch_base, double vec_bytes_per_rhs,
                         double flops_per_rhs, const FixedScratch* fx = nullptr) {
   const Plan& P = h->plan;
   const bool c64 = h->prec == HELM_C64;
-  if (!variant_valid(h, k)) return hipErrorInvalidValue;
+  if (choice < 0 || !variant_valid(h, choice / 2)) return hipErrorInvalidValue;
+  const int k = choice / 2;
+  a.xmap = choice % 2;
   const SweepVariant v = sweep_variants(c64)[k];
   const void* kern = sweep_kernel(c64, z64, adj, k);
   if (!kern) return hipErrorInvalidValue;
@@ -320,7 +329,7 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int k, bool z64, bool adj, 
     }
     c.seq0 = *seq;
     *seq += span;
-    const unsigned grid = (unsigned)(8 * a.wpr * ((Rc + 7) / 8));
+    const unsigned grid = (unsigned)(a.xmap ? a.wpr * Rc : 8 * a.wpr * ((Rc + 7) / 8));
     void* args[] = {&c};
     hipEvent_t ev = timed ? h->t_kernel.begin(s) : nullptr;
     e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(tpc), args, (unsigned)sm, s);
@@ -419,7 +428,7 @@ hipError_t autotune_sweep(helm_handle* h, int R, int* best_out, double* best_ms,
   std::vector<int> cand = tune_candidates(h);
   *best_out = -1;
   *best_ms = 0.0;
-  if (cand.empty()) cand.push_back(default_variant(h));
+  if (cand.empty()) cand.push_back(2 * default_variant(h) + 1);
   if (cand[0] < 0) return hipErrorInvalidValue;
   const long long N = (long long)h->n * h->n * h->n;
   const bool c64 = h->prec == HELM_C64;

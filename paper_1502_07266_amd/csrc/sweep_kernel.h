@@ -14,8 +14,9 @@
 //   outer front o (two fronts in x3: o = 0 sweeps the x3-groups upwards from x3 = 0, o = 1
 //   downwards from x3 = 1; the middle x3-group is solved by o = 0), inner front f (the same
 //   over the x2-groups of every slab; the middle x2-line is solved by f = 0), half h.
-// All members of a right-hand side sit on one XCD (workgroup ids b with the same b mod 8,
-// which the dispatcher places round-robin over the 8 XCDs), so their exchanges stay in one L2.
+// Two placements over the 8 XCDs (k_sweep): all members of a right-hand side on one XCD, so
+// their exchanges stay in one L2, or each member on its own XCD, so that one XCD's L2 serves
+// one part of the factor stream to every right-hand side.
 //
 // Exchanges.  Members wait for each other only for data, never on a barrier: a value travels
 // in 64-bit words, each holding one 32-bit piece beside a tag (the sequence number of the
@@ -80,6 +81,8 @@ struct SweepArgs {
   unsigned long long seq0;
   unsigned spin_limit;
   int drop_publish;      // failure injection: member 0 of every pair skips publishing E1
+  int xmap;              // workgroup placement: 0 a right-hand side's members on one XCD,
+                         // 1 each member on its own XCD (see k_sweep)
 };
 
 // exchange words per launch slot (all counts in 64-bit words; np = 32-bit pieces per value)
@@ -831,15 +834,27 @@ struct Sweeper {
   }
 };
 
-// Workgroup b: XCD b mod 8; right-hand side slot 8 (b / 8 / wpr) + b mod 8, member
-// (b / 8) mod wpr.  Slots past R (the grid is rounded up to whole groups of 8) exit at once.
+// Workgroup b sits on XCD b mod 8 (the dispatcher's round-robin).  Placement 0: right-hand
+// side slot 8 (b / 8 / wpr) + b mod 8, member (b / 8) mod wpr, so the members of a right-hand
+// side share one XCD's L2 for their exchanges (slots past R, the grid being rounded up to
+// whole groups of 8, exit at once).  Placement 1: slot b / wpr, member b mod wpr, so with
+// eight members every XCD runs one member of each right-hand side: one part of the factor
+// stream (a member's fronts and half of every line) read by all right-hand sides through
+// one L2, the exchanges crossing XCDs.
 template <typename R, typename TI, typename TO, int NCA, int CWA, int DA, int NCB, int CWB, int DB,
           bool ADJ>
 __global__ void __launch_bounds__((kernel_threads_max<NCA, CWA, NCB, CWB>())) k_sweep(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int b = (int)blockIdx.x, k8 = b >> 3;
-  const int grp = k8 / a.wpr, member = k8 - grp * a.wpr;
-  const int slot = grp * 8 + (b & 7);
+  const int b = (int)blockIdx.x;
+  int slot, member;
+  if (a.xmap) {
+    slot = b / a.wpr;
+    member = b - slot * a.wpr;
+  } else {
+    const int k8 = b >> 3, grp = k8 / a.wpr;
+    member = k8 - grp * a.wpr;
+    slot = grp * 8 + (b & 7);
+  }
   if (slot >= a.R) return;
   Sweeper<R, TI, TO, NCA, CWA, DA, NCB, CWB, DB, ADJ> s(a, smem_raw, slot, member);
   if (a.mode == 1) s.single_line(a.line_g, a.line_l);

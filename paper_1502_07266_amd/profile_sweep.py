@@ -1,9 +1,8 @@
 """Driver for hardware-counter runs of the sweep: one plain copy of a known size, then one
-batched sweep (helm_apply) of a workload (the launches of sweep_schedule: one dispatch with
-one front; with two fronts, two of the front kernel and one of the middle slab; with two
-inner fronts, three per slab step).
+batched sweep (helm_apply: one cooperative launch of the sweep kernel) of a workload, with a
+fixed launch shape (no tuning runs in between).
 
-    python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024
+    python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024 --variant 11
 
 Run it under `rocprofv3 --pmc FETCH_SIZE ...` and again under `--pmc WRITE_SIZE ...`: the
 copy kernel reads and writes exactly copy-mib MiB, which calibrates what the counters report
@@ -12,6 +11,7 @@ device times of both (HIP events) and the sweep's algorithmic bytes.
 """
 import argparse
 import json
+import os
 import time
 
 import torch
@@ -28,7 +28,9 @@ def main():
     ap.add_argument("--rhs", type=int, default=0, help="right-hand sides (0: all of the workload)")
     ap.add_argument("--fronts", type=int, default=2, choices=[1, 2])
     ap.add_argument("--fronts-inner", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--variant", type=int, default=-1, help="launch shape (-1: the default one)")
     args = ap.parse_args()
+    os.environ["HELM_AUTOTUNE"] = "0"
 
     wl = inputs.workload(args.workload)
     n = wl["n"]
@@ -53,6 +55,7 @@ def main():
     F = torch.from_numpy(inputs.sources(n, nodes)).to(dev)
     H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=args.prec, fronts=args.fronts,
              fronts_inner=args.fronts_inner, C_moving=wl.get("C_moving", 0.0))
+    H.set_launch(args.variant)
     H.reset_stats()
     t0 = time.perf_counter()
     H.apply(F)
@@ -67,7 +70,9 @@ def main():
                       "apply_ms": st["apply_ms"],
                       "apply_algorithmic_bytes": st["apply_bytes_per_rhs"] * R,
                       "kernel_launches": st["kernel_launches"], "kernel_ms": st["kernel_ms"],
-                      "kernel_algorithmic_bytes_per_launch": st["kernel_bytes_per_rhs"] * R}), flush=True)
+                      "shape": H.sweep_shape(R)[1],
+                      "kernel_algorithmic_bytes_per_launch": st["kernel_bytes"] / max(st["kernel_launches"], 1)}),
+          flush=True)
     H.close()
 
 

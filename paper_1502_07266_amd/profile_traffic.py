@@ -68,7 +68,7 @@ def main():
     out["kernel_ms_per_launch"] = run["kernel_ms"] / launches
     out["algorithmic_bytes_per_launch"] = run["kernel_algorithmic_bytes_per_launch"]
     out["hbm_gbs"] = hbm / (out["kernel_ms_per_launch"] * 1e-3) / 1e9
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "sweep.hip")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "sweep_kernel.h")
     with open(src, "rb") as fh:
         out["sweep_source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
     with open(args.out, "w") as fh:
