@@ -280,11 +280,13 @@ int helm_line_solve(helm_handle* h, int zg, int yg, const void* r_dev, void* x_d
                     int adjoint, void* stream);
 
 /*
- * helm_set_launch -- choose the sweep's launch shape: choice k >= 0 is variant k / 2 of the
+ * helm_set_launch -- choose the sweep's launch shape: choice k >= 0 is variant k / 4 of the
  * library's list (two shapes each: lanes per block row, columns per lane and factor-ring
- * depth for the lines on no middle group and for the others) with workgroup placement k % 2
+ * depth for the lines on no middle group and for the others) with workgroup placement k % 4
  * (0: the workgroups of a right-hand side on one XCD; 1: each of its workgroups on its own
- * XCD, so that one XCD serves one part of the factor stream to all right-hand sides);
+ * XCD, so that one XCD serves one part of the factor stream to all right-hand sides; 2: the
+ * two workgroups of each line solve on one XCD, the pairs of a right-hand side spread; 3 is
+ * not a placement);
  * helm_sweep_shape names it.  -1 restores the automatic choice (the autotuner's for this
  * configuration, else the first listed variant that covers the blocks, placement 1).
  * Changes summation order only: results agree to rounding.

@@ -150,32 +150,34 @@ std::vector<int> tune_candidates(const helm_handle* h) {
     if (!variant_valid(h, k) || vs[k].capA() < h->plan.maxB_front) continue;
     const bool a = vs[k].capA() == capA[0] || (capA.size() > 1 && vs[k].capA() == capA[1]);
     const bool b = vs[k].capB() == capB[0] || (capB.size() > 1 && vs[k].capB() == capB[1]);
-    if (a && b) {
-      out.push_back(2 * k);
-      out.push_back(2 * k + 1);
-    }
+    if (a && b)
+      for (int m = 0; m < 3; ++m) out.push_back(4 * k + m);
   }
   return out;
 }
 
-// A launch choice c is variant c / 2 of sweep_variants with workgroup placement c % 2
-// (sweep_kernel.h, k_sweep): 0 a right-hand side's members on one XCD, 1 one member per XCD.
+// A launch choice c is variant c / 4 of sweep_variants with workgroup placement c % 4
+// (sweep_kernel.h, k_sweep): 0 a right-hand side's members on one XCD, 1 one member per XCD,
+// 2 one line-solve pair per XCD (3 is unused).
 int sweep_variant_for(const helm_handle* h, int R) {
   if (h->variant >= 0) return h->variant;
   const int t = tuned_variant(tune_key(h, R));
-  return t >= 0 ? t : 2 * default_variant(h) + 1;
+  return t >= 0 ? t : 4 * default_variant(h) + 1;
 }
 
-bool sweep_variant_valid(const helm_handle* h, int c) { return c >= 0 && variant_valid(h, c / 2); }
+bool sweep_variant_valid(const helm_handle* h, int c) {
+  return c >= 0 && c % 4 != 3 && variant_valid(h, c / 4);
+}
 
 std::string sweep_variant_name(bool c64, int c) {
   const auto& vs = sweep_variants(c64);
-  const int k = c / 2;
-  if (c < 0 || k >= (int)vs.size()) return "none";
+  const int k = c / 4;
+  if (c < 0 || c % 4 == 3 || k >= (int)vs.size()) return "none";
   const SweepVariant& v = vs[k];
+  static const char* place[] = {", one right-hand side per XCD", ", one member per XCD",
+                                ", one line-solve pair per XCD"};
   return std::to_string(v.nca) + "x" + std::to_string(v.cwa) + "/ring" + std::to_string(v.da) + " + " +
-         std::to_string(v.ncb) + "x" + std::to_string(v.cwb) + "/ring" + std::to_string(v.db) +
-         (c % 2 ? ", one member per XCD" : ", one right-hand side per XCD");
+         std::to_string(v.ncb) + "x" + std::to_string(v.cwb) + "/ring" + std::to_string(v.db) + place[c % 4];
 }
 
 namespace {
@@ -270,9 +272,9 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int choice, bool z64, bool 
                         double flops_per_rhs, const FixedScratch* fx = nullptr) {
   const Plan& P = h->plan;
   const bool c64 = h->prec == HELM_C64;
-  if (choice < 0 || !variant_valid(h, choice / 2)) return hipErrorInvalidValue;
-  const int k = choice / 2;
-  a.xmap = choice % 2;
+  if (!sweep_variant_valid(h, choice)) return hipErrorInvalidValue;
+  const int k = choice / 4;
+  a.xmap = choice % 4;
   const SweepVariant v = sweep_variants(c64)[k];
   const void* kern = sweep_kernel(c64, z64, adj, k);
   if (!kern) return hipErrorInvalidValue;
@@ -329,7 +331,11 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int choice, bool z64, bool 
     }
     c.seq0 = *seq;
     *seq += span;
-    const unsigned grid = (unsigned)(a.xmap ? a.wpr * Rc : 8 * a.wpr * ((Rc + 7) / 8));
+    // placement 0: whole groups of 8 slots; 1: wpr per slot; 2: whole groups of 16 / wpr slots
+    const int per = 16 / a.wpr;
+    const unsigned grid = (unsigned)(a.xmap == 1 ? a.wpr * Rc
+                                     : a.xmap == 2 ? 16 * ((Rc + per - 1) / per)
+                                                   : 8 * a.wpr * ((Rc + 7) / 8));
     void* args[] = {&c};
     hipEvent_t ev = timed ? h->t_kernel.begin(s) : nullptr;
     e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(tpc), args, (unsigned)sm, s);
@@ -428,7 +434,7 @@ hipError_t autotune_sweep(helm_handle* h, int R, int* best_out, double* best_ms,
   std::vector<int> cand = tune_candidates(h);
   *best_out = -1;
   *best_ms = 0.0;
-  if (cand.empty()) cand.push_back(2 * default_variant(h) + 1);
+  if (cand.empty()) cand.push_back(4 * default_variant(h) + 1);
   if (cand[0] < 0) return hipErrorInvalidValue;
   const long long N = (long long)h->n * h->n * h->n;
   const bool c64 = h->prec == HELM_C64;

@@ -14,9 +14,10 @@
 //   outer front o (two fronts in x3: o = 0 sweeps the x3-groups upwards from x3 = 0, o = 1
 //   downwards from x3 = 1; the middle x3-group is solved by o = 0), inner front f (the same
 //   over the x2-groups of every slab; the middle x2-line is solved by f = 0), half h.
-// Two placements over the 8 XCDs (k_sweep): all members of a right-hand side on one XCD, so
-// their exchanges stay in one L2, or each member on its own XCD, so that one XCD's L2 serves
-// one part of the factor stream to every right-hand side.
+// Three placements over the 8 XCDs (k_sweep): all members of a right-hand side on one XCD, so
+// their exchanges stay in one L2; each member on its own XCD, so that one XCD's L2 serves one
+// part of the factor stream to every right-hand side; or the two members of each line solve on
+// one XCD, between the two.
 //
 // Exchanges.  Members wait for each other only for data, never on a barrier: a value travels
 // in 64-bit words, each holding one 32-bit piece beside a tag (the sequence number of the
@@ -81,8 +82,7 @@ struct SweepArgs {
   unsigned long long seq0;
   unsigned spin_limit;
   int drop_publish;      // failure injection: member 0 of every pair skips publishing E1
-  int xmap;              // workgroup placement: 0 a right-hand side's members on one XCD,
-                         // 1 each member on its own XCD (see k_sweep)
+  int xmap;              // workgroup placement over the XCDs (see k_sweep)
 };
 
 // exchange words per launch slot (all counts in 64-bit words; np = 32-bit pieces per value)
@@ -836,20 +836,27 @@ struct Sweeper {
 
 // Workgroup b sits on XCD b mod 8 (the dispatcher's round-robin).  Placement 0: right-hand
 // side slot 8 (b / 8 / wpr) + b mod 8, member (b / 8) mod wpr, so the members of a right-hand
-// side share one XCD's L2 for their exchanges (slots past R, the grid being rounded up to
-// whole groups of 8, exit at once).  Placement 1: slot b / wpr, member b mod wpr, so with
-// eight members every XCD runs one member of each right-hand side: one part of the factor
-// stream (a member's fronts and half of every line) read by all right-hand sides through
-// one L2, the exchanges crossing XCDs.
+// side share one XCD's L2 for their exchanges.  Placement 1: slot b / wpr, member b mod wpr,
+// so with eight members every XCD runs one member of each right-hand side: one part of the
+// factor stream (a member's fronts and half of every line) read by all right-hand sides
+// through one L2, the exchanges crossing XCDs.  Placement 2: the two halves of a line solve
+// (members 2q and 2q + 1) on one XCD, XCD q (8 / P) + slot mod (8 / P) for the P = wpr / 2
+// pairs of a right-hand side, so the exchange inside a line solve stays in one L2 and each
+// XCD reads 1 / P of the factor stream.  Slots past R (the grid is rounded up) exit at once.
 template <typename R, typename TI, typename TO, int NCA, int CWA, int DA, int NCB, int CWB, int DB,
           bool ADJ>
 __global__ void __launch_bounds__((kernel_threads_max<NCA, CWA, NCB, CWB>())) k_sweep(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = (int)blockIdx.x;
   int slot, member;
-  if (a.xmap) {
+  if (a.xmap == 1) {
     slot = b / a.wpr;
     member = b - slot * a.wpr;
+  } else if (a.xmap == 2) {
+    const int per = 16 / a.wpr;                    // right-hand sides sharing an XCD's pair type
+    const int x = b & 7, k = b >> 3, q = x / per;  // k: (slot / per, half)
+    slot = (k >> 1) * per + (x - q * per);
+    member = 2 * q + (k & 1);
   } else {
     const int k8 = b >> 3, grp = k8 / a.wpr;
     member = k8 - grp * a.wpr;

@@ -2,7 +2,7 @@
 batched sweep (helm_apply: one cooperative launch of the sweep kernel) of a workload, with a
 fixed launch shape (no tuning runs in between).
 
-    python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024 --variant 11
+    python -m paper_1502_07266_amd.profile_sweep --workload c3 --prec c64 --copy-mib 1024 --variant 46
 
 Run it under `rocprofv3 --pmc FETCH_SIZE ...` and again under `--pmc WRITE_SIZE ...`: the
 copy kernel reads and writes exactly copy-mib MiB, which calibrates what the counters report

@@ -177,7 +177,7 @@ def test_apply_every_launch_shape(name, prec):
     H = helm(name, prec)
     ref = M.apply(x.reshape(2, -1).T).T.reshape(x.shape)
     tried = []
-    for k in range(40):
+    for k in range(4 * 24):
         try:
             H.set_launch(k)
         except HelmError:
