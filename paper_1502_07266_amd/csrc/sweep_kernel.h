@@ -295,29 +295,26 @@ struct Chain {
 
   // Step t with ring slot S (parity of t = parity of S): P = A - c acc with the table's
   // operand row A and coupling c (A = 0, c = -1 in the middle); the block row gets acc
-  // (forward) or P, and P is published for the next step.
-  template <int S>
+  // (forward steps, t < mid: FWD) or P, and P is published for the next step.
+  template <int S, bool FWD>
   __device__ __forceinline__ void step(int t, C* sb, const C* zme, const C* zot, const int4* tab,
                                        const C* ctab) {
     constexpr int par = (S & 1) * ZS;
     C zr[CW];
 #pragma unroll
     for (int cc = 0; cc < CW; ++cc) zr[cc] = zme[par + c0 + cc];
-    if (t == mid) {
+    if constexpr (!FWD) {
+      if (t == mid) {
 #pragma unroll
-      for (int cc = 0; cc < CW; ++cc) zr[cc] = cadd(zr[cc], zot[par + c0 + cc]);
+        for (int cc = 0; cc < CW; ++cc) zr[cc] = cadd(zr[cc], zot[par + c0 + cc]);
+      }
     }
     const int4 e2 = tab[t + 2];
     const C cn = ctab[t + 1];
     const C acc = dot<S>(zr);
     load<S>((unsigned)ecur.w);
     const C P = csub(Acur, cmul(ccur, acc));
-    // component-wise select (a select of whole complex128 values is lowered through scratch)
-    const bool fwd = t < mid;
-    C out;
-    out.x = fwd ? acc.x : P.x;
-    out.y = fwd ? acc.y : P.y;
-    sb[ecur.y + rowc] = out;
+    sb[ecur.y + rowc] = FWD ? acc : P;
     sb[ecur.z + rowc] = P;
     Acur = sb[enext.x + rowc];   // operand of step t + 1 (never written by step t)
     ccur = cn;
@@ -328,31 +325,32 @@ struct Chain {
 
   // D consecutive steps, one per ring slot, with no branch between them (the wait before
   // each slot's use then covers exactly the loads issued D steps earlier)
-  template <int S = 0>
+  template <bool FWD, int S = 0>
   __device__ __forceinline__ void group(int t0, C* sb, const C* zme, const C* zot, const int4* tab,
                                         const C* ctab) {
     if constexpr (S < D) {
-      step<S>(t0 + S, sb, zme, zot, tab, ctab);
-      group<S + 1>(t0, sb, zme, zot, tab, ctab);
+      step<S, FWD>(t0 + S, sb, zme, zot, tab, ctab);
+      group<FWD, S + 1>(t0, sb, zme, zot, tab, ctab);
     }
   }
-  template <int S = 0>
+  template <bool FWD, int S = 0>
   __device__ __forceinline__ void tail(int t0, int end, C* sb, const C* zme, const C* zot,
                                        const int4* tab, const C* ctab) {
     if constexpr (S < D) {
       if (t0 + S < end) {
-        step<S>(t0 + S, sb, zme, zot, tab, ctab);
-        tail<S + 1>(t0, end, sb, zme, zot, tab, ctab);
+        step<S, FWD>(t0 + S, sb, zme, zot, tab, ctab);
+        tail<FWD, S + 1>(t0, end, sb, zme, zot, tab, ctab);
       }
     }
   }
+  // backward steps from t0 + s0 (t0 a multiple of D)
   template <int S = 0>
   __device__ __forceinline__ void head(int t0, int s0, int end, C* sb, const C* zme,
                                        const C* zot, const int4* tab, const C* ctab) {
     if constexpr (S < D) {
       if (S >= s0) {
         if (t0 + S >= end) return;
-        step<S>(t0 + S, sb, zme, zot, tab, ctab);
+        step<S, false>(t0 + S, sb, zme, zot, tab, ctab);
       }
       head<S + 1>(t0, s0, end, sb, zme, zot, tab, ctab);
     }
@@ -377,11 +375,18 @@ struct Chain {
 
   // Solve on the right-hand side in the member's half of ybuf (complete, after a barrier).
   // LDS regions as element offsets from sb.  On return ybuf holds the solution on the
-  // member's blocks (visible to the whole workgroup).
+  // member's blocks (visible to the whole workgroup).  The step table and the zero padding of
+  // the published vectors depend on B and the shape only: with fresh false they are those of
+  // the member's previous line and are kept.
   __device__ __forceinline__ void run(C* sb, int ybuf, int zb, int zeros, int junk, C* ctab,
-                                      int4* tab, const C* cf, const C* cb, bool idle,
+                                      int4* tab, const C* cf, const C* cb, bool idle, bool fresh,
                                       unsigned long long* xmine, const unsigned long long* xother,
                                       unsigned long long seq, unsigned spin, int* err, bool publish) {
+    if (fresh) tables(sb, ybuf, zb, zeros, junk, ctab, tab, cf, cb);
+    start(sb, ybuf, zb, ctab, tab, idle, xmine, xother, seq, spin, err, publish);
+  }
+  __device__ __forceinline__ void tables(C* sb, int ybuf, int zb, int zeros, int junk, C* ctab,
+                                         int4* tab, const C* cf, const C* cb) {
     const C zero = mk((R)0, (R)0);
     const int B = B_, ts = steps + 2;   // table entries (<= n + 3)
     for (int e = threadIdx.x; e < 4 * ZS; e += blockDim.x)
@@ -420,6 +425,12 @@ struct Chain {
       tab[t] = en;
     }
     lds_barrier();
+  }
+  __device__ __forceinline__ void start(C* sb, int ybuf, int zb, const C* ctab, const int4* tab,
+                                        bool idle, unsigned long long* xmine,
+                                        const unsigned long long* xother, unsigned long long seq,
+                                        unsigned spin, int* err, bool publish) {
+    const int B = B_;
     // each chain starts from the q of its first block (chain 1: block n - 1 at step 2 mid - n + 1)
     if (row < B) {
       if (!lower) sb[zb + row] = sb[ybuf + row];
@@ -442,16 +453,16 @@ struct Chain {
     // forward steps 0 .. mid - 1, the exchange, then mid .. steps - 1 continuing the ring
     // slots where the forward steps left them (step t always uses slot t % D)
     int t0 = 0;
-    for (; t0 + D <= mid; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tab, ctab);
-    if (t0 < mid) tail(__builtin_amdgcn_readfirstlane(t0), mid, sb, zme, zot, tab, ctab);
+    for (; t0 + D <= mid; t0 += D) group<true>(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tab, ctab);
+    if (t0 < mid) tail<true>(__builtin_amdgcn_readfirstlane(t0), mid, sb, zme, zot, tab, ctab);
     exchange(sb, zb, xmine, xother, seq, spin, err, publish);
     t0 = mid - mid % D;
     if (t0 < mid) {
       head(__builtin_amdgcn_readfirstlane(t0), mid - t0, steps, sb, zme, zot, tab, ctab);
       t0 += D;
     }
-    for (; t0 + D <= steps; t0 += D) group(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tab, ctab);
-    if (t0 < steps) tail(__builtin_amdgcn_readfirstlane(t0), steps, sb, zme, zot, tab, ctab);
+    for (; t0 + D <= steps; t0 += D) group<false>(__builtin_amdgcn_readfirstlane(t0), sb, zme, zot, tab, ctab);
+    if (t0 < steps) tail<false>(__builtin_amdgcn_readfirstlane(t0), steps, sb, zme, zot, tab, ctab);
   }
 };
 
@@ -490,6 +501,7 @@ struct Sweeper {
   int n, Gz, Gy, zmid, ymid, fronts, fronts_inner, ofront, ifront, half, ilo, ni, tid, NT;
   bool publish;
   unsigned long long lcount, sstep;           // lines solved, slab steps done (tags)
+  int tab_key;                                // block size and shape of the step table in LDS
 
   __device__ __forceinline__ Sweeper(const SweepArgs& a, unsigned char* smem, int slot, int member)
       : L(a.n, a.maxB, a.maxW, (int)sizeof(C)) {
@@ -508,6 +520,7 @@ struct Sweeper {
     spin = a.spin_limit;
     lcount = 0;
     sstep = 0;
+    tab_key = -1;
     tid = (int)threadIdx.x;
     NT = (int)blockDim.x;
     half = member & 1;
@@ -546,6 +559,7 @@ struct Sweeper {
     return ((long long)(k - 1) * n + (j - 1)) * n + i;
   }
 
+
   // gather (into this member's half of the line vector), solve, with the shape B takes
   template <int NC, int CW, int D, typename G>
   __device__ __forceinline__ void solve(const C* T, int B, G& gather) {
@@ -556,7 +570,10 @@ struct Sweeper {
     gather();
     lds_barrier();   // the gather writes LDS only (its global loads are consumed by then)
     const int par = (int)(lcount & 1);
-    ch.run(sb, L.ybuf, L.zb, L.zeros, L.junk, sb + L.ctab, tab, cf, cb, idle,
+    const int key = B * 2 + (NC == NCA && CW == CWA && D == DA ? 0 : 1);
+    const bool fresh = key != tab_key;
+    tab_key = key;
+    ch.run(sb, L.ybuf, L.zb, L.zeros, L.junk, sb + L.ctab, tab, cf, cb, idle, fresh,
            x1mine + par * kZMax * np, x1other + par * kZMax * np, seq0 + lcount + 1, spin, xerr, publish);
     lcount += 1;
   }
