@@ -12,8 +12,9 @@
 // D_i is the 5-point (x2, x3) operator of the window plus the x1 diagonal and kappa.
 //
 // One workgroup owns a line, or one half of a two-sided line: it forms S_i in LDS, inverts it
-// by Gauss-Jordan elimination with partial pivoting (row interchanges inside the block only),
-// stores T_i = S_i^{-1} and reuses it for the next Schur update.  The blocks are eliminated
+// by Gauss-Jordan elimination with partial pivoting in panels (the eliminations outside each
+// panel as one complex matrix product on the matrix cores), stores T_i = S_i^{-1} and keeps
+// it in registers for the next Schur update.  The blocks are eliminated
 // from both ends towards the middle (see the order below), which halves the dependent chain
 // of the line solve; the two halves do not meet before the middle block, so they are factored
 // by two workgroups and the middle blocks by a launch of their own.  All
@@ -21,7 +22,7 @@
 // problems).  The LDS of a launch is sized by its largest block, so the lines on a middle
 // group (few, with blocks up to 128) get a launch of their own, on a side stream beside the
 // launches of the other lines (split again by block size, so that the many small ones share
-// CUs four at a time).
+// CUs several at a time).
 #include <algorithm>
 
 #include "common.h"
@@ -32,13 +33,12 @@ constexpr int kMaxW = 64;
 constexpr int kMaxB = 128;
 constexpr int kSetupThreads = 256;        // lines with two-chain blocks (B <= 64)
 constexpr int kSetupThreadsBig = 1024;    // lines on a middle group (B up to 128)
-constexpr size_t kSetupLdsBytes = 144 * 1024;   // dynamic LDS the setup may take (of 160 KiB)
-constexpr size_t kSmallLds = 40 * 1024;         // two blocks within this: four workgroups per CU
+constexpr size_t kSetupLdsBytes = 152 * 1024;   // dynamic LDS the setup may take (of 160 KiB)
+constexpr size_t kSmallLds = 20 * 1024;         // a block within this: several workgroups per CU
 
 struct SetupArgs {
   int n, Gz, Gy, p;
   int fronts, zmid, fronts_inner, ymid;
-  int prev_in_lds;   // the previous block's factor is kept in LDS (else re-read from HBM)
   int part;          // 0: whole lines; 1: the two halves of two-sided lines, one workgroup
                      // each (workgroup 2w + h takes half h of line lines[w]); 2: their middle
                      // blocks, after part 1
@@ -63,17 +63,87 @@ __device__ inline double2 window_s(const SetupArgs& a, const GroupInfo& gi, int 
   return a.sbd[t];
 }
 
-// The B x B loops run rows across waves and columns across lanes (c and c + 64), so no
-// element index is divided by B.
-template <typename R, int NTB>
+// ---- matrix-core helpers: one 16 x 16 x 4 real product per call, D = A B + C.  Lane l
+// supplies A[l mod 16][l / 16] and B[l / 16][l mod 16] and holds four elements of column
+// l mod 16 of D: rows 4 (l / 16) + i (fp32) or l / 16 + 4 i (fp64), i = 0..3.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int i) { return 4 * (l >> 4) + i; }
+};
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int i) { return (l >> 4) + 4 * i; }
+};
+
+// ---- wave-level helpers of the pivot search (one wavefront of 64 lanes)
+__device__ __forceinline__ unsigned umax(unsigned a, unsigned b) { return a > b ? a : b; }
+// maximum over the wave: prefix maxima inside each row of 16 lanes (row_shr 1, 2, 4, 8; a
+// lane without a source keeps 0), so lane 15 of each row holds the row's maximum; the four
+// are combined as scalars
+__device__ __forceinline__ unsigned wave_max(unsigned v) {
+  v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false));
+  v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false));
+  v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false));
+  v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 15);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 31);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 47);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+  return umax(umax(a, b), umax(c, d));
+}
+// order-preserving 32-bit key of a magnitude m >= 0 (NaN above every finite value)
+__device__ __forceinline__ unsigned mag_key(float m) { return __float_as_uint(m); }
+__device__ __forceinline__ unsigned mag_key(double m) { return (unsigned)__double2hiint(m); }
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <typename C> __device__ __forceinline__ C lane_value(C v, int l) {
+  return C{lane_value(v.x, l), lane_value(v.y, l)};
+}
+
+// Line setup: per block, S_i = D_i - (coupling) T_prev is formed in LDS and inverted in place
+// by Gauss-Jordan elimination in panels of NB columns:
+//  * the panel: wavefront 0 holds the panel's columns of every row in registers (lane l rows
+//    l and l + 64), chooses each pivot as the largest magnitude in the column among the rows
+//    not yet used (a wave maximum, no barrier), broadcasts the pivot row with readlane and
+//    eliminates the column from all other rows.  Rows are not moved: the pivot of column k is
+//    recorded as piv[k].  The pivot row's scaling is kept as a per-row factor until the panel
+//    is written back;
+//  * the columns outside the panel: every Gauss-Jordan step of the panel is the same left
+//    multiplication of all columns, so they take it at once, A[:, rest] = Z + F G with F the
+//    finished panel (B x NB), G the panel's pivot rows of A[:, rest] before it and Z that
+//    matrix with those rows zero: a complex product on the matrix cores (four real 16 x 16 x
+//    4 products per complex one), tiles spread over all waves.
+// After the last panel, T = S^{-1} is the stored array R read as T[r][piv[k]] = R[piv[r]][k].
+// RPL: rows per lane of the panel wave (B <= 64 RPL); NB: panel width.  LDS: the block
+// (B x B) and the panel's pivot rows (NB x B).
+template <typename R, int NTB, int RPL>
 __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   using C = typename cx<R>::type;
+  using M = Mfma<R>;
+  constexpr int NB = 8 / RPL;
+  constexpr int NW = NTB / 64;
+  constexpr int BMAX = 64 * RPL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double2 syn[kMaxW], syh[kMaxW + 1], szn[kMaxW], szh[kMaxW + 1];
-  __shared__ int perm[kMaxB], rho[kMaxB];
-  __shared__ C fcol[kMaxB];
-  __shared__ C pinv_s;
-  __shared__ int piv_s, bad_s;
+  __shared__ int piv[kMaxB], qinv[kMaxB], pnl[kMaxB];
+  // storage maps: logical row u of the current block is LDS row rmap[u], logical column v
+  // LDS column cmap[v] (rinv, cinv_ the inverses)
+  __shared__ int rmap[kMaxB], cmap[kMaxB], rinv[kMaxB], cinv_[kMaxB];
+  __shared__ int bad_s;
 
   const int w = a.part == 1 ? (int)blockIdx.x >> 1 : (int)blockIdx.x;
   const int half = a.part == 1 ? (int)blockIdx.x & 1 : 0;
@@ -82,11 +152,14 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   const GroupInfo gz = a.groups[g], gy = a.groups[a.Gz + l];
   const int Wz = gz.W, Wy = gy.W, B = Wy * Wz;
   const int n = a.n;
-  const int tid = threadIdx.x, NT = blockDim.x;
-  const int lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int u = tid; u < kMaxB; u += NTB) rmap[u] = cmap[u] = rinv[u] = cinv_[u] = u;
   C* S = reinterpret_cast<C*>(smem_raw);
+  C* Gp = S + B * B;   // the current panel's pivot rows, as they were before the panel
   C* out = reinterpret_cast<C*>(a.factors) + a.line_off[line];
   const double ih2 = 1.0 / (a.h * a.h);
+  const C zero = mk((R)0, (R)0);
 
   if (tid < Wy) syn[tid] = window_s(a, gy, 2 * (gy.w0 + tid));
   if (tid <= Wy) syh[tid] = window_s(a, gy, 2 * (gy.w0 + tid) - 1);
@@ -101,9 +174,6 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
   // block eliminated is an end of the remaining chain, so there is no fill); the sweep runs
   // the two halves of each line solve as two concurrent chains.
   const int mid = n / 2;
-  // the factor of the block eliminated last: an LDS copy, or the block just written to HBM
-  C* Tlds = S + B * B;
-  const C* Tprev = Tlds;
   const bool has_lower = mid + 1 <= n - 1;
   const C* T_mid_minus1 = out + (long long)(mid - 1) * B * B;   // T_{m-1}, stored at t = m - 1
   // steps t0..t1-1 of the order: all, one half (the halves do not meet before the middle
@@ -115,8 +185,10 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
     t1 = half ? n - 1 : mid;
   } else if (a.part == 2) {
     t0 = n - 1;
-    Tprev = has_lower ? out + (long long)(mid + 1) * B * B : T_mid_minus1;
   }
+  // The factor of the previous block of this workgroup's order stays in LDS where the
+  // inversion left it: T[u][v] at row rmap[u], column cmap[v].  The next Schur complement is
+  // formed in place, element by element, so the storage order is carried along.
   for (int t = t0; t < t1; ++t) {
     const int i = t < mid ? t : (t < n - 1 ? n - 1 - (t - mid) : mid);
     const int m = i + 1;  // global x1 node of block i
@@ -126,110 +198,202 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
     // update from the block above: u_i l_{i+1} = (s_m s_{m+1/2} / h^2)(s_{m+1} s_{m+1/2} / h^2)
     const C sc_below = cvt<C>(cmul(cscale(cmul(sxn, sxd), ih2), cscale(cmul(a.sbd[2 * m - 2], sxd), ih2)));
     const C sc_above = cvt<C>(cmul(cscale(cmul(sxn, sxu), ih2), cscale(cmul(a.sbd[2 * m + 2], sxu), ih2)));
-    // (scale, factor) pairs of the Schur update; Tprev holds the factor computed last
     const bool is_mid = t == n - 1;
     const bool use_a = (t > 0 && t < mid) || (t > mid && t < n - 1) || is_mid;
     const C scA = (t < mid || is_mid) ? sc_below : sc_above;
-    const C* TA = (is_mid && has_lower) ? T_mid_minus1 : Tprev;
-    const bool use_b = is_mid && has_lower;
-    for (int r = wv; r < B; r += nw) {
+    // The previous block of this workgroup's order is in LDS (a workgroup's first block has
+    // none); the middle block of a two-sided line is a launch's first block and reads both
+    // neighbours' factors from HBM (T_{m-1} and T_{m+1}, or only T_{m-1} when nothing lies
+    // above it), as does the whole-line order for T_{m-1}.
+    const bool prev_lds = use_a && t > t0;
+    const C* TA = is_mid ? T_mid_minus1 : nullptr;                      // scale sc_below
+    const C* TB = (is_mid && has_lower && t == t0) ? out + (long long)(mid + 1) * B * B : nullptr;
+    const C scL = is_mid ? sc_above : scA;   // scale of the factor in LDS
+    for (int sr_ = wv; sr_ < B; sr_ += NW) {   // LDS row, logical row r
+      const int r = rinv[sr_];
       const int jr = r / Wz, kr = r - jr * Wz;
-      for (int c = lane; c < B; c += 64) {
-      const int e = r * B + c;
-      const int jc = c / Wz, kc = c - jc * Wz;
-      double2 val = make_double2(0.0, 0.0);
-      if (r == c) {
-        const int k = gz.w0 + kr, j = gy.w0 + jr;
-        const double kap = a.kappa[((long long)(k - 1) * n + (j - 1)) * n + i];
-        double2 dy = cscale(cmul(syn[jr], cadd(syh[jr + 1], syh[jr])), -ih2);
-        double2 dz = cscale(cmul(szn[kr], cadd(szh[kr + 1], szh[kr])), -ih2);
-        val = cadd(cadd(dx, dy), dz);
-        val.x += kap;
-      } else if (jr == jc) {
-        if (kc == kr + 1) val = cscale(cmul(szn[kr], szh[kr + 1]), ih2);
-        else if (kc == kr - 1) val = cscale(cmul(szn[kr], szh[kr]), ih2);
-      } else if (kr == kc) {
-        if (jc == jr + 1) val = cscale(cmul(syn[jr], syh[jr + 1]), ih2);
-        else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
-      }
-      C v = cvt<C>(val);
-      if (use_a) v = csub(v, cmul(scA, TA[e]));
-      if (use_b) v = csub(v, cmul(sc_above, Tprev[e]));
-      S[e] = v;
+      for (int sc_ = lane; sc_ < B; sc_ += 64) {   // LDS column, logical column c
+        const int c = cinv_[sc_];
+        const int e = r * B + c, se = sr_ * B + sc_;
+        const int jc = c / Wz, kc = c - jc * Wz;
+        double2 val = make_double2(0.0, 0.0);
+        if (r == c) {
+          const int k = gz.w0 + kr, jj = gy.w0 + jr;
+          const double kap = a.kappa[((long long)(k - 1) * n + (jj - 1)) * n + i];
+          double2 dy = cscale(cmul(syn[jr], cadd(syh[jr + 1], syh[jr])), -ih2);
+          double2 dz = cscale(cmul(szn[kr], cadd(szh[kr + 1], szh[kr])), -ih2);
+          val = cadd(cadd(dx, dy), dz);
+          val.x += kap;
+        } else if (jr == jc) {
+          if (kc == kr + 1) val = cscale(cmul(szn[kr], szh[kr + 1]), ih2);
+          else if (kc == kr - 1) val = cscale(cmul(szn[kr], szh[kr]), ih2);
+        } else if (kr == kc) {
+          if (jc == jr + 1) val = cscale(cmul(syn[jr], syh[jr + 1]), ih2);
+          else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
+        }
+        C v = cvt<C>(val);
+        if (prev_lds) v = csub(v, cmul(scL, S[se]));
+        if (TA) v = csub(v, cmul(sc_below, TA[e]));
+        if (TB) v = csub(v, cmul(sc_above, TB[e]));
+        S[se] = v;
       }
     }
+    for (int r = tid; r < B; r += NTB) pnl[r] = -1;
     __syncthreads();
 
-    // ---- in-place Gauss-Jordan inversion with partial pivoting ----
-    for (int k = 0; k < B; ++k) {
-      if (tid < 64) {
-        R best = (R)-1;
-        int bi = B;
-        for (int r = k + tid; r < B; r += 64) {
-          R mg = cabs2(S[r * B + k]);
-          if (mg > best) { best = mg; bi = r; }
+    // ---- Gauss-Jordan in panels
+    bool done[RPL];
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) done[rr] = lane + 64 * rr >= B;
+    for (int K = 0; K < B; K += NB) {
+      const int nbp = B - K < NB ? B - K : NB;
+      if (wv == 0) {
+        C x[RPL][NB], sr[RPL];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int row = lane + 64 * rr;
+          sr[rr] = mk((R)1, (R)0);
+#pragma unroll
+          for (int c = 0; c < NB; ++c) x[rr][c] = (row < B && c < nbp) ? S[row * B + K + c] : zero;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-          R ob = __shfl_xor(best, off);
-          int oi = __shfl_xor(bi, off);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+          if (kk < nbp) {
+            // pivot: the largest |s x| in column kk among this lane's rows not yet used
+            unsigned key = 0;
+            int sel = 0;
+            bool any = false;
+  #pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+              if (done[rr]) continue;
+              const unsigned kb = mag_key(cabs2(sr[rr]) * cabs2(x[rr][kk]));
+              if (!any || kb > key) {
+                key = kb;
+                sel = rr;
+              }
+              any = true;
+            }
+            const unsigned mk_ = wave_max(any ? key : 0u);
+            unsigned long long bal = __ballot(any && key == mk_);
+            if (bal == 0) bal = __ballot(any);   // (not reached: some lane holds the maximum)
+            const int p = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(bal));
+            const int rsel = __builtin_amdgcn_readlane(sel, p);
+            const int pr = p + 64 * rsel;
+            C prow[NB];
+  #pragma unroll
+            for (int c = 0; c < NB; ++c) {
+              C v = x[0][c];
+  #pragma unroll
+              for (int rr = 1; rr < RPL; ++rr)
+                if (rsel == rr) v = x[rr][c];
+              prow[c] = lane_value(v, p);
+            }
+            C sv = sr[0];
+  #pragma unroll
+            for (int rr = 1; rr < RPL; ++rr)
+              if (rsel == rr) sv = sr[rr];
+            const C sp = lane_value(sv, p);
+            C pv = cmul(sp, prow[kk]);
+            const R pm = cabs2(pv);
+            if (!(pm > (R)0) || !isfinite(pm)) {   // singular block: flagged, finished with a unit pivot
+              if (lane == 0) bad_s = 1;
+              pv = mk((R)1, (R)0);
+            }
+            const C pinv = cinv(pv);
+            const C spn = cmul(pinv, sp);   // the pivot row's scale after the step
+  #pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+              if (lane == p && rr == rsel) {
+                // stored * scale is the row's value: column kk becomes pinv
+                sr[rr] = spn;
+                x[rr][kk] = cinv(sp);
+                done[rr] = true;
+              } else {
+                const C f = x[rr][kk];
+                const C gg = cmul(f, spn);
+  #pragma unroll
+                for (int c = 0; c < NB; ++c) x[rr][c] = csub(x[rr][c], cmul(gg, prow[c]));
+                x[rr][kk] = C{-(f.x * pinv.x - f.y * pinv.y), -(f.x * pinv.y + f.y * pinv.x)};
+              }
+            }
+            if (lane == 0) {
+              piv[K + kk] = pr;
+              pnl[pr] = K;
+            }
+            for (int c = lane; c < B; c += 64) Gp[kk * B + c] = S[pr * B + c];
+            }
         }
-        if (tid == 0) {
-          C pv = S[bi * B + k];
-          if (!(best > (R)0) || !isfinite(best)) { bad_s = 1; pv = mk((R)1, (R)0); }
-          piv_s = bi;
-          perm[k] = bi;
-          pinv_s = cinv(pv);
+        // the finished panel, with each row's scale applied
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+          const int row = lane + 64 * rr;
+          if (row >= B) continue;
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            if (c < nbp) S[row * B + K + c] = cmul(sr[rr], x[rr][c]);
         }
       }
       __syncthreads();
-      const int pr = piv_s;
-      if (pr != k) {
-        for (int c = tid; c < B; c += NT) {
-          C tmp = S[k * B + c];
-          S[k * B + c] = S[pr * B + c];
-          S[pr * B + c] = tmp;
+      // A[:, rest] = Z + F G on the matrix cores, tile by tile (16 x 16, K steps of 4): G
+      // comes from the copy of the pivot rows, so a tile's result can go straight back
+      const int RT = (B + 15) >> 4, ntile = RT * RT;
+      for (int tile = wv; tile < ntile; tile += NW) {
+        const int ti = tile / RT, tj = tile - ti * RT;
+        const int col = tj * 16 + (lane & 15);
+        if (tj * 16 >= K && tj * 16 + 15 < K + nbp) continue;   // all inside the panel
+        typename M::acc are, aim;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int row = ti * 16 + M::row(lane, ii);
+          const C z = (row < B && col < B && pnl[row] != K) ? S[row * B + col] : zero;
+          are[ii] = z.x;
+          aim[ii] = z.y;
         }
-      }
-      __syncthreads();
-      const C pinv = pinv_s;
-      for (int c = tid; c < B; c += NT) S[k * B + c] = (c == k) ? pinv : cmul(S[k * B + c], pinv);
-      for (int r = tid; r < B; r += NT)
-        if (r != k) fcol[r] = S[r * B + k];
-      __syncthreads();
-      for (int r = wv; r < B; r += nw) {
-        if (r == k) continue;
-        const C fr = fcol[r];
-        for (int c = lane; c < B; c += 64) {
-          const int e = r * B + c;
-          const C old = (c == k) ? mk((R)0, (R)0) : S[e];
-          S[e] = csub(old, cmul(fr, S[k * B + c]));
+        const int frow = ti * 16 + (lane & 15);
+        for (int k0 = 0; k0 < nbp; k0 += 4) {
+          const int k = k0 + (lane >> 4);
+          const C f = (frow < B && k < nbp) ? S[frow * B + K + k] : zero;
+          const C gv = (k < nbp && col < B) ? Gp[k * B + col] : zero;
+          are = M::mac(f.x, gv.x, are);
+          are = M::mac(-f.y, gv.y, are);
+          aim = M::mac(f.x, gv.y, aim);
+          aim = M::mac(f.y, gv.x, aim);
+        }
+        if (col < B && (col < K || col >= K + nbp)) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int row = ti * 16 + M::row(lane, ii);
+            if (row < B) S[row * B + col] = mk(are[ii], aim[ii]);
+          }
         }
       }
       __syncthreads();
     }
-    // column order of the inverse: (PS)^{-1} P = S^{-1}, i.e. T[r][rho(m)] = X[r][m]
-    if (tid == 0) {
-      for (int q = 0; q < B; ++q) rho[q] = q;
-      for (int k = 0; k < B; ++k) {
-        int tmp = rho[k];
-        rho[k] = rho[perm[k]];
-        rho[perm[k]] = tmp;
-      }
+    // The LDS array X (= the block with rows and columns in storage order) now holds R with
+    // X^{-1}[a][b] = R[piv[a]][qinv[b]], qinv the inverse of piv; the block's inverse is
+    // T[u][v] = X^{-1}[cmap[u]][rmap[v]], so T sits at row piv[cmap[u]], column
+    // qinv[rmap[v]]: the storage maps of the next block
+    for (int k = tid; k < B; k += NTB) qinv[piv[k]] = k;
+    __syncthreads();
+    int nr = 0, nc = 0;
+    if (tid < B) {
+      nr = piv[cmap[tid]];
+      nc = qinv[rmap[tid]];
+    }
+    __syncthreads();
+    if (tid < B) {
+      rmap[tid] = nr;
+      cmap[tid] = nc;
+      rinv[nr] = tid;
+      cinv_[nc] = tid;
     }
     __syncthreads();
     C* dst = out + (long long)i * B * B;
-    if (a.prev_in_lds) {
-      for (int r = wv; r < B; r += nw)
-        for (int q = lane; q < B; q += 64) Tlds[r * B + rho[q]] = S[r * B + q];
-      __syncthreads();
-      for (int e = tid; e < B * B; e += NT) dst[e] = Tlds[e];
-    } else {
-      for (int r = wv; r < B; r += nw)
-        for (int q = lane; q < B; q += 64) dst[r * B + rho[q]] = S[r * B + q];
-      __syncthreads();   // the next block's Schur update reads dst (workgroup-scope fence)
-      Tprev = dst;
+    for (int u = wv; u < B; u += NW) {
+      const int ru = rmap[u];
+      for (int v = lane; v < B; v += 64) dst[u * B + v] = S[ru * B + cmap[v]];
     }
+    __syncthreads();   // the whole-line order's middle block reads T_{m-1} back from HBM
   }
   if (tid == 0 && bad_s) {
     atomicOr(&a.err[0], 1);
@@ -252,28 +416,32 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
   }
   a.lines = d_lines;
   const size_t csz = h->prec == HELM_C64 ? sizeof(float2) : sizeof(double2);
-  // keep the previous factor in LDS when two B x B blocks fit, else re-read it from HBM
-  a.prev_in_lds = 2 * (size_t)maxB * maxB * csz <= kSetupLdsBytes;
-  const size_t sm = (a.prev_in_lds ? 2 : 1) * (size_t)maxB * maxB * csz;
+  // the block being inverted and the panel's pivot rows (the previous factor stays in the
+  // block's array)
+  constexpr int RPL = NTB == kSetupThreads ? 1 : 2;
+  const size_t sm = ((size_t)maxB * maxB + (size_t)(8 / RPL) * maxB) * csz;
+  if (sm > kSetupLdsBytes) return hipErrorInvalidValue;
+  if (maxB > 64 * RPL) return hipErrorInvalidValue;
   if (h->prec == HELM_C64) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float, NTB>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<float, NTB, RPL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    k_line_setup<float, NTB><<<count, NTB, sm, s>>>(a);
+    k_line_setup<float, NTB, RPL><<<count, NTB, sm, s>>>(a);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double, NTB>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_setup<double, NTB, RPL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    k_line_setup<double, NTB><<<count, NTB, sm, s>>>(a);
+    k_line_setup<double, NTB, RPL><<<count, NTB, sm, s>>>(a);
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-// The setup's line classes, each with LDS for its own largest block: lines whose two B x B
-// blocks take at most kSmallLds (several workgroups share a CU), the other lines with blocks
-// up to 64, and the larger blocks (those of the lines on a middle group; 1024 threads).
+// The setup's line classes, each with LDS for its own largest block: lines whose B x B block
+// takes at most kSmallLds (several workgroups share a CU), the other lines with blocks up to
+// 64, and the larger blocks (those of the lines on a middle group; 1024 threads, two rows per
+// lane in the panel wave).
 SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subset) {
   SetupClasses c;
   std::vector<int> all;
@@ -288,7 +456,7 @@ SetupClasses setup_classes(const Plan& P, int csz, const std::vector<int>* subse
   for (int k = 0; k < 3; ++k)
     for (int line : *subset) {
       const int B = P.line_B[line];
-      const int cls = B > 64 ? 2 : (2 * (size_t)B * B * csz <= kSmallLds ? 0 : 1);
+      const int cls = B > 64 ? 2 : ((size_t)B * B * csz <= kSmallLds ? 0 : 1);
       if (cls != k) continue;
       c.order.push_back(line);
       c.count[k] += 1;
