@@ -91,6 +91,21 @@ def dependent_steps(n, b, d, fronts, fronts_inner, line_steps=None):
     return sweep, kernel
 
 
+def setup_mfma(wl, fronts, fronts_inner, setup_ms):
+    """Block inversions of the setup against the fp32 matrix-core peak: 8 B^3 real flops per
+    block (its Gauss-Jordan inverse), every block of every line, over the setup's time."""
+    from paper_1502_07266_amd.profile_setup import window_widths
+    n = wl["n"]
+    wz = window_widths(n, wl["b"], wl["p"], wl["d"], fronts)
+    wy = window_widths(n, wl["b"], wl["p"], wl["d"], fronts_inner)
+    flops = 8.0 * n * sum(float(a * b) ** 3 for a in wz for b in wy)
+    tf = flops / (setup_ms * 1e-3) / 1e12
+    return {"inversion_flops": flops, "tflops": round(tf, 2), "peak_tflops": 157.3,
+            "frac": round(tf / 157.3, 4),
+            "note": "panel Gauss-Jordan: pivots on one wavefront (vector unit), the eliminations "
+                    "outside each panel as complex 16x16x4 fp32 matrix-core products"}
+
+
 def traffic_profile_name(fronts, fronts_inner):
     return {(1, 1): "k_sweep", (2, 1): "k_sweep_front", (1, 2): "k_sweep_inner_fronts",
             (2, 2): "k_sweep_fronts_both_axes"}[(fronts, fronts_inner)]
@@ -368,6 +383,7 @@ def main():
         "first_step_s": round(first_step_s, 4),
         "step_s_min_max": [round(min(step_s), 4), round(max(step_s), 4)],
         "setup_ms": round(tot["setup_ms"] / args.steps, 2),
+        "setup_matrix_cores": setup_mfma(wl, args.fronts, args.fronts_inner, tot["setup_ms"] / args.steps),
         "apply_ms_total_per_step": round(tot["apply_ms"] / args.steps, 1),
         "matvec_ms_total_per_step": round(tot["matvec_ms"] / args.steps, 2),
         "timed_kernels_frac_of_step": round(kernels_ms / (sec_per_step * 1e3), 3),

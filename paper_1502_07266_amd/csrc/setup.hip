@@ -100,6 +100,12 @@ __device__ __forceinline__ unsigned wave_max(unsigned v) {
   const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
   return umax(umax(a, b), umax(c, d));
 }
+// 1 / a: fp32 with the hardware reciprocal of |a|^2 (one ulp), fp64 exact
+__device__ __forceinline__ float2 cinv_fast(float2 a) {
+  const float r = __builtin_amdgcn_rcpf(a.x * a.x + a.y * a.y);
+  return make_float2(a.x * r, -a.y * r);
+}
+__device__ __forceinline__ double2 cinv_fast(double2 a) { return cinv(a); }
 // order-preserving 32-bit key of a magnitude m >= 0 (NaN above every finite value)
 __device__ __forceinline__ unsigned mag_key(float m) { return __float_as_uint(m); }
 __device__ __forceinline__ unsigned mag_key(double m) { return (unsigned)__double2hiint(m); }
@@ -131,10 +137,11 @@ template <typename C> __device__ __forceinline__ C lane_value(C v, int l) {
 // RPL: rows per lane of the panel wave (B <= 64 RPL); NB: panel width.  LDS: the block
 // (B x B) and the panel's pivot rows (NB x B).
 template <typename R, int NTB, int RPL>
-__global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
+__global__ void __launch_bounds__(NTB) __attribute__((amdgpu_waves_per_eu(NTB == 256 && sizeof(R) == 4 ? 5 : 1)))
+k_line_setup(SetupArgs a) {
   using C = typename cx<R>::type;
   using M = Mfma<R>;
-  constexpr int NB = 8 / RPL;
+  constexpr int NB = sizeof(R) == 8 && RPL == 2 ? 4 : 8;
   constexpr int NW = NTB / 64;
   constexpr int BMAX = 64 * RPL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -242,16 +249,18 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
     __syncthreads();
 
     // ---- Gauss-Jordan in panels
-    bool done[RPL];
-#pragma unroll
-    for (int rr = 0; rr < RPL; ++rr) done[rr] = lane + 64 * rr >= B;
     for (int K = 0; K < B; K += NB) {
       const int nbp = B - K < NB ? B - K : NB;
-      if (wv == 0) {
+      // the panel wave changes from panel to panel and between workgroups, so that the
+      // workgroups sharing a CU do not all load the same SIMD with their serial parts
+      if (wv == ((int)blockIdx.x + K / NB) % NW) {
         C x[RPL][NB], sr[RPL];
+        bool done[RPL];   // pivot row of an earlier column
+        int prs[NB];      // the panel's pivot rows
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
           const int row = lane + 64 * rr;
+          done[rr] = row >= B || pnl[row] >= 0;
           sr[rr] = mk((R)1, (R)0);
 #pragma unroll
           for (int c = 0; c < NB; ++c) x[rr][c] = (row < B && c < nbp) ? S[row * B + K + c] : zero;
@@ -299,14 +308,15 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
               if (lane == 0) bad_s = 1;
               pv = mk((R)1, (R)0);
             }
-            const C pinv = cinv(pv);
+            const C pinv = cinv_fast(pv);
             const C spn = cmul(pinv, sp);   // the pivot row's scale after the step
+            const C isp = cmul(pinv, prow[kk]);   // 1 / sp
   #pragma unroll
             for (int rr = 0; rr < RPL; ++rr) {
               if (lane == p && rr == rsel) {
                 // stored * scale is the row's value: column kk becomes pinv
                 sr[rr] = spn;
-                x[rr][kk] = cinv(sp);
+                x[rr][kk] = isp;
                 done[rr] = true;
               } else {
                 const C f = x[rr][kk];
@@ -316,13 +326,18 @@ __global__ void __launch_bounds__(NTB) k_line_setup(SetupArgs a) {
                 x[rr][kk] = C{-(f.x * pinv.x - f.y * pinv.y), -(f.x * pinv.y + f.y * pinv.x)};
               }
             }
+            prs[kk] = pr;
             if (lane == 0) {
               piv[K + kk] = pr;
               pnl[pr] = K;
             }
-            for (int c = lane; c < B; c += 64) Gp[kk * B + c] = S[pr * B + c];
-            }
+          }
         }
+        // the panel's pivot rows as they were before it (the columns outside the panel)
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk)
+          if (kk < nbp)
+            for (int c = lane; c < B; c += 64) Gp[kk * B + c] = S[prs[kk] * B + c];
         // the finished panel, with each row's scale applied
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
@@ -419,7 +434,7 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
   // the block being inverted and the panel's pivot rows (the previous factor stays in the
   // block's array)
   constexpr int RPL = NTB == kSetupThreads ? 1 : 2;
-  const size_t sm = ((size_t)maxB * maxB + (size_t)(8 / RPL) * maxB) * csz;
+  const size_t sm = ((size_t)maxB * maxB + (size_t)8 * maxB) * csz;
   if (sm > kSetupLdsBytes) return hipErrorInvalidValue;
   if (maxB > 64 * RPL) return hipErrorInvalidValue;
   if (h->prec == HELM_C64) {
