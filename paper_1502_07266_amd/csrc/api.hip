@@ -13,7 +13,6 @@
 namespace {
 thread_local std::string g_last_error;
 
-constexpr size_t kSetupLds = 144 * 1024; // dynamic LDS of the setup (one B x B block at least)
 constexpr size_t kFactorPad = 64;        // complex entries of zeros after the factor array
 
 int fail(int code, const std::string& msg) {
@@ -34,7 +33,7 @@ int validate(const helm_grid* grid, const helm_pml* pml, int d, int prec, Plan& 
   const int fronts_inner = pml->fronts_inner == 0 ? 1 : pml->fronts_inner;
   int rc = build_plan(grid->n, pml->b, pml->p, d, fronts, fronts_inner, prec, plan, msg);
   if (rc != HELM_OK) return fail(rc, msg);
-  if ((size_t)plan.maxB * plan.maxB * csize(prec) > kSetupLds)
+  if (!setup_fits(plan.maxB, (int)csize(prec)))
     return fail(HELM_EINVAL, "a B x B block does not fit in LDS for the setup");
   if (!sweep_plan_supported(plan, prec, msg)) return fail(HELM_EINVAL, msg);
   return HELM_OK;

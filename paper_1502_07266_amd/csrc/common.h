@@ -230,6 +230,10 @@ hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables,
 hipError_t launch_setup(helm_handle* h, hipStream_t s);
 // the setup's launches: lines in class order (blocks whose two B x B copies fit a quarter of
 // the LDS, other blocks up to 64, larger blocks), the count and largest block of each class
+// dynamic LDS a setup workgroup takes for blocks up to maxB (complex element size csz), and
+// whether the setup supports such blocks
+size_t setup_lds_bytes(int maxB, int csz);
+bool setup_fits(int maxB, int csz);
 struct SetupClasses {
   std::vector<int> order;
   int count[3];

@@ -434,7 +434,7 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
   // the block being inverted and the panel's pivot rows (the previous factor stays in the
   // block's array)
   constexpr int RPL = NTB == kSetupThreads ? 1 : 2;
-  const size_t sm = ((size_t)maxB * maxB + (size_t)8 * maxB) * csz;
+  const size_t sm = setup_lds_bytes(maxB, (int)csz);
   if (sm > kSetupLdsBytes) return hipErrorInvalidValue;
   if (maxB > 64 * RPL) return hipErrorInvalidValue;
   if (h->prec == HELM_C64) {
@@ -452,6 +452,10 @@ hipError_t setup_launch(const helm_handle* h, SetupArgs a, const int* d_lines, i
 }
 
 }  // namespace
+
+// dynamic LDS of a setup workgroup: the block and the pivot rows of one panel
+size_t setup_lds_bytes(int maxB, int csz) { return ((size_t)maxB * maxB + (size_t)8 * maxB) * csz; }
+bool setup_fits(int maxB, int csz) { return maxB <= 128 && setup_lds_bytes(maxB, csz) <= kSetupLdsBytes; }
 
 // The setup's line classes, each with LDS for its own largest block: lines whose B x B block
 // takes at most kSmallLds (several workgroups share a CU), the other lines with blocks up to
