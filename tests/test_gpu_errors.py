@@ -24,9 +24,9 @@ def test_solve_beyond_device_memory_is_enomem_before_allocating():
     H.set_launch(H.sweep_shape(1)[0])   # a fixed launch shape: no tuning sweeps before the solve
     n = H.n
     total = torch.cuda.mem_get_info()[1]
-    per_rhs = H.workspace_bytes(1, 200, 200)["solve"]
-    R = int(total // per_rhs) + 2
-    assert H.workspace_bytes(R, 200, 200)["solve"] > total
+    R = int(total // H.workspace_bytes(1, 200, 200)["solve"]) + 2
+    while H.workspace_bytes(R, 200, 200)["solve"] <= total:   # the planned bytes are not linear in R
+        R = R + R // 16 + 1
     f = torch.zeros((R, n, n, n), dtype=torch.complex128, device="cuda")
     f[:, n // 2, n // 2, n // 2] = 1.0
     live_before = pool_stats()[1]
