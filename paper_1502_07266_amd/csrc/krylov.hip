@@ -95,6 +95,69 @@ __global__ void __launch_bounds__(kDotThreads) k_dots(Basis<TX> X, int K,
   }
 }
 
+// One Gram-Schmidt update followed by the next reduction over the updated vector, in one pass
+// over w: w_q -= sum_{k < K} coef[q][k] X_{q,k}, then (NORM false) the chunk's partial sums of
+// conj(X_k) w for every k, as k_dots writes them (the basis chunk just read comes back from
+// L2), or (NORM true) the partial sum of |w|^2, as k_dots of w with itself.  The arithmetic
+// of each element is that of k_axpy_multi followed by k_dots.
+template <typename TX, bool NORM>
+__global__ void __launch_bounds__(kDotThreads) k_update_dots(double2* __restrict__ w, long long wr,
+                                                             Basis<TX> X, const double2* __restrict__ coef,
+                                                             int cstride, int K, const int* __restrict__ idx,
+                                                             double2* __restrict__ partial, int nchunk,
+                                                             long long N) {
+  __shared__ double2 red[kDotThreads / 64];
+  __shared__ double2 c[kMaxRestart + 1];
+  const int a = blockIdx.y, q = idx[a], chunk = blockIdx.x;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double2 v = coef[(long long)q * cstride + k];
+    c[k] = make_double2(-v.x, -v.y);
+  }
+  __syncthreads();
+  const long long base = (long long)chunk * kDotChunk + threadIdx.x;
+  double2 wv[kDotPerThread];
+#pragma unroll
+  for (int t = 0; t < kDotPerThread; ++t) {
+    const long long e = base + (long long)t * kDotThreads;
+    wv[t] = e < N ? w[(long long)q * wr + e] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < K; ++k) {
+    const TX* xp = X.at(k, q);
+#pragma unroll
+    for (int t = 0; t < kDotPerThread; ++t) {
+      const long long e = base + (long long)t * kDotThreads;
+      if (e < N) wv[t] = cfma(wv[t], c[k], cvt<double2>(xp[e]));
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kDotPerThread; ++t) {
+    const long long e = base + (long long)t * kDotThreads;
+    if (e < N) w[(long long)q * wr + e] = wv[t];
+  }
+  if constexpr (NORM) {
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kDotPerThread; ++t) {
+      const long long e = base + (long long)t * kDotThreads;
+      if (e < N) sum = cfma_conj(sum, wv[t], wv[t]);
+    }
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) partial[(long long)a * nchunk + chunk] = sum;
+  } else {
+    for (int k = 0; k < K; ++k) {
+      const TX* xp = X.at(k, q);
+      double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < kDotPerThread; ++t) {
+        const long long e = base + (long long)t * kDotThreads;
+        if (e < N) sum = cfma_conj(sum, cvt<double2>(xp[e]), wv[t]);
+      }
+      sum = block_sum(sum, red);
+      if (threadIdx.x == 0) partial[((long long)a * K + k) * nchunk + chunk] = sum;
+    }
+  }
+}
+
 // out[q*ostride + k] = sum_chunks partial (mode 0), or sqrt(Re sum) (mode 1, norms): one
 // workgroup per (k, active vector), the chunks' partial sums reduced across its threads
 __global__ void __launch_bounds__(kDotThreads) k_dots_final(const double2* __restrict__ partial, int K,
@@ -437,16 +500,17 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
       HIP_MSG(launch_apply(h, ws.V.at(j, 0), true, N, zj, !c64, N, (int)a, ws.idx, adjoint, s));
       // w = A z_j
       HIP_MSG(launch_matvec(h, zj, !c64, nullptr, ws.W, (int)a, ws.idx, N, N, adjoint, 0, s));
-      // two classical Gram-Schmidt passes
-      for (int pass = 0; pass < 2; ++pass) {
-        double2* hp = pass == 0 ? ws.h1 : ws.h2;
-        k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, j + 1, ws.W, N, ws.idx,
-                                                                ws.partial, nchunk, N);
-        k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, hp, m + 1, 0);
-        k_axpy_multi<double2><<<dim3(nb, a), 256, 0, s>>>(ws.W, N, ws.V, hp, m + 1, j + 1, nullptr,
-                                                          -1.0, ws.idx, N);
-      }
-      HIP_MSG(norms(ws.W, act, ws.nrm));
+      // two classical Gram-Schmidt passes: h1 = V^H w; w -= V h1 and h2 = V^H w in one pass;
+      // w -= V h2 and ||w||^2 in one pass
+      k_dots<double2><<<dim3(nchunk, a), kDotThreads, 0, s>>>(ws.V, j + 1, ws.W, N, ws.idx,
+                                                              ws.partial, nchunk, N);
+      k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, ws.h1, m + 1, 0);
+      k_update_dots<double2, false><<<dim3(nchunk, a), kDotThreads, 0, s>>>(
+          ws.W, N, ws.V, ws.h1, m + 1, j + 1, ws.idx, ws.partial, nchunk, N);
+      k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, ws.h2, m + 1, 0);
+      k_update_dots<double2, true><<<dim3(nchunk, a), kDotThreads, 0, s>>>(
+          ws.W, N, ws.V, ws.h2, m + 1, j + 1, ws.idx, ws.partial, nchunk, N);
+      k_dots_final<<<dim3(1, a), kDotThreads, 0, s>>>(ws.partial, 1, nchunk, ws.idx, ws.nrm, 1, 1);
       k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V.at(j + 1, 0), N, ws.W, N, ws.nrm, ws.idx, N);
       k_givens<<<(a + 63) / 64, 64, 0, s>>>(j, m, ws.h1, ws.h2, ws.nrm, ws.H, ws.cs, ws.sn, ws.g,
                                            ws.resid, ws.idx, (int)a);
