@@ -118,6 +118,40 @@ template <int NC, typename T> __device__ __forceinline__ T lane_sum(T v) {
   return v;
 }
 
+// Walk over e = tid, tid + NT, ... of a (hi, lo, ii) index space, e = (hi W + lo) ni + ii,
+// with ii < ni and lo < W: the three indices are kept by additions (a division per element
+// would cost more than the element's own work).
+struct Walk {
+  int ii, lo, hi;          // current element
+  int di, dlo, dhi;        // step of NT elements
+  int ni, W;
+  __device__ __forceinline__ Walk(int tid, int NT, int ni_, int W_) : ni(ni_), W(W_) {
+    const int ro = tid / ni, dq = NT / ni;
+    ii = tid - ro * ni;
+    hi = ro / W;
+    lo = ro - hi * W;
+    di = NT - dq * ni;
+    dhi = dq / W;
+    dlo = dq - dhi * W;
+  }
+  __device__ __forceinline__ void next() {
+    ii += di;
+    lo += dlo;
+    hi += dhi;
+    if (ii >= ni) {
+      ii -= ni;
+      ++lo;
+    }
+    if (lo >= W) {
+      lo -= W;
+      ++hi;
+    }
+  }
+};
+
+// elements per thread whose input loads a line's gather issues together
+constexpr int kGatherU = 4;
+
 // Loads from the factor array through an explicitly global pointer (global_load, counted by
 // vmcnt only; a generic pointer would give flat loads, which also count against lgkmcnt and
 // would make every LDS wait drain the factor ring).
@@ -603,11 +637,31 @@ struct Sweeper {
     const bool in_above = (lkind == kFwdHigh && l < Gy - 1) || lkind == kFwdMid;
     const C* T = factors + line_off[(size_t)g * Gy + l];
     C* yb = sb + L.ybuf;
+    // The elements are taken kGatherU per thread at a time: the loads of f (the bulk of the
+    // gather) for the whole batch are issued first, so a batch waits for one memory latency.
     auto gather = [&]() {
       const C zero = mk((R)0, (R)0);
-      for (int e = tid; e < ni * B; e += NT) {
-        const int qq = e / ni, i = ilo + e - qq * ni;
-        const int jj = qq / Wz, kk = qq - jj * Wz;
+      const bool need_f = ifwd && ofwd;
+      Walk wk(tid, NT, ni, Wz);
+      for (int e0 = tid; e0 < ni * B; e0 += kGatherU * NT) {
+        Walk w2 = wk;
+        TI fr[kGatherU];
+#pragma unroll
+        for (int r = 0; r < kGatherU; ++r) {
+          const int e = e0 + r * NT;
+          fr[r] = TI{};
+          if (e < ni * B && need_f) {
+            const int j = yw0 + wk.hi, k = zw0 + wk.lo;
+            if (j >= j0 && j <= j1 && k >= k0 && k <= k1) fr[r] = f[gidx(ilo + wk.ii, j, k)];
+          }
+          wk.next();
+        }
+#pragma unroll
+        for (int r = 0; r < kGatherU; ++r) {
+        const int e = e0 + r * NT;
+        if (e >= ni * B) break;
+        const int jj = w2.hi, kk = w2.lo, qq = jj * Wz + kk, i = ilo + w2.ii;
+        w2.next();
         const int j = yw0 + jj, k = zw0 + kk;
         C val = zero;
         if (ifwd) {
@@ -620,7 +674,7 @@ struct Sweeper {
                              : zero;
             if (ofwd) {
               if (k >= k0 && k <= k1) {
-                val = cvt<C>(f[gidx(i, j, k)]);
+                val = cvt<C>(fr[r]);
                 val = csub(val, cmul(cf[k0], ub));
                 val = csub(val, cmul(cb[k1], ua));
               }
@@ -638,12 +692,14 @@ struct Sweeper {
           val = cmul(cf[j0], x_below ? xrow[kk * ni + (i - ilo)] : v[((long long)kk * n + (j0 - 2)) * n + i]);
         }
         yb[(i - ilo) * B + qq] = val;
+        }
       }
     };
     solve_any(T, B, gather);
     const int npy = j1 - j0 + 1;
-    for (int e = tid; e < ni * Wz * npy; e += NT) {
-      const int i = ilo + e % ni, kk = (e / ni) % Wz, jp = e / (ni * Wz);
+    Walk wk(tid, NT, ni, Wz);
+    for (int e = tid; e < ni * Wz * npy; e += NT, wk.next()) {
+      const int i = ilo + wk.ii, kk = wk.lo, jp = wk.hi;
       const int qq = (j0 - yw0 + jp) * Wz + kk;
       C* p = v + ((long long)kk * n + (j0 + jp - 1)) * n + i;
       *p = ifwd ? yb[(i - ilo) * B + qq] : csub(*p, yb[(i - ilo) * B + qq]);
@@ -736,8 +792,9 @@ struct Sweeper {
     const bool ofwd = kind <= kFwdMid;
     const int k0 = gz.first, k1 = gz.last, zw0 = gz.w0;
     const int nph = k1 - k0 + 1, nr = r1 - r0 + 1;
-    for (int e = tid; e < ni * nr * nph; e += NT) {
-      const int i = ilo + e % ni, jm = r0 - 1 + (e / ni) % nr, kp = e / (ni * nr);
+    Walk wk(tid, NT, ni, nr);
+    for (int e = tid; e < ni * nr * nph; e += NT, wk.next()) {
+      const int i = ilo + wk.ii, jm = r0 - 1 + wk.lo, kp = wk.hi;
       const int kk = k0 - zw0 + kp;
       const C val = v[((long long)kk * n + jm) * n + i];
       const long long id = gidx(i, jm + 1, k0 + kp);
