@@ -353,3 +353,51 @@ def test_c2_solve_matches_oracle_reference(prec):
     print(f"c2 {prec}: {its[0]} iterations, rel-L2 vs oracle {err:.2e}, norm {nerr:.2e}, true residual {tres:.2e}")
     assert err <= 1e-5 and nerr <= 1e-5
     assert tres <= 1.01e-6
+
+
+def test_c5_largest_workload_factors_sweep_and_solve():
+    """255^3 (the largest single-GPU workload: 8 sources, d = 1, p = 4, two fronts in both
+    axes, complex64 factors of 80 GB), where the oracle cannot run whole: sampled line
+    factors (a boundary line, a front line, the middle-middle line) against the oracle's,
+    the adjoint dot test and linearity of the whole sweep, and a 1-source FGMRES solve whose
+    true residual, recomputed with the library's matvec (pinned against the oracle's A at the
+    other sizes), is <= 1e-6."""
+    from paper_1502_07266_amd.binding import Helm
+    wl = inputs.workload("c5")
+    n = wl["n"]
+    cm = wl.get("C_moving", 0.0)
+    prob = O.Problem(n=n, c=wl["c"], omega=wl["omega"], b=wl["b"], C=wl["C"], p=wl["p"], d=wl["d"],
+                     C_moving=cm, fronts=2, fronts_inner=2)
+    Gt = O.groups_two_fronts(n, wl["b"], wl["d"])
+    mid = len(Gt) // 2
+    H = Helm(torch.from_numpy(wl["c"]).cuda(), wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec="c64",
+             C_moving=cm, fronts=2, fronts_inner=2)
+    H.set_launch(H.sweep_shape(8)[0])   # the default launch shape: no tuning sweeps (4 s each here)
+    for (g, l) in [(0, 0), (mid - 7, mid + 5), (mid, mid)]:
+        ln = O.LineFactors(prob, Gt, g, Gt, l, order=H.line_order(g, l))
+        ref = np.stack(ln.block_T)
+        T = H.line_factors(g, l).cpu().numpy()
+        err = max(float(np.linalg.norm(T[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(len(ref)))
+        print(f"c5 line ({g}, {l}) B={ln.B}: worst block rel err {err:.2e}")
+        assert err <= 1e-5
+    x = torch.from_numpy(inputs.random_rhs(n, 1, seed=35)).cuda()
+    y = torch.from_numpy(inputs.random_rhs(n, 1, seed=36)).cuda()
+    Mx = H.apply(x)
+    print("c5: first apply done", flush=True)
+    My = H.apply(y)
+    MHy = H.apply(y, adjoint=True)
+    print("c5: adjoint apply done", flush=True)
+    lhs, rhs_ = cdot(Mx, y), cdot(x, MHy)
+    dot_err = abs(lhs - rhs_) / abs(lhs)
+    comb = H.apply(2 * x + 3j * y)
+    lin_err = float((comb - (2 * Mx + 3j * My)).norm() / comb.norm())
+    print(f"c5 complex64 sweep: dot test {dot_err:.2e}, linearity {lin_err:.2e}", flush=True)
+    assert dot_err <= 1.2e-5
+    assert lin_err <= 3.5e-6
+    del Mx, My, MHy, comb
+    f = torch.from_numpy(inputs.sources(n, wl["nodes"][:1])).cuda()
+    u, its, relres, rc = H.solve(f, tol=1e-6, restart=50, maxit=60)
+    res = float((f - H.matvec(u)).norm() / f.norm())
+    print(f"c5 solve: {its.tolist()} iterations, estimate {relres.max():.2e}, true residual {res:.2e}")
+    H.close()
+    assert rc == 0 and res <= 1e-6
