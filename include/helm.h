@@ -354,7 +354,29 @@ typedef struct {
                                /* its output written once                                     */
   double kernel_flops;         /* useful real flops: 8 per factor entry visited per           */
                                /* right-hand side (one complex multiply-add)                  */
+  double nd_setup_ms;          /* device time of the last nested-dissection factorisation    */
+                               /* (helm_set_line_solver, helm_update_medium)                  */
 } helm_stats;
+
+/*
+ * helm_set_line_solver -- how the forward complex64 sweeps solve their line problems.
+ *   HELM_LINE_LDU (default): the block LDU of Algorithm 3 with the x1-blocks eliminated from
+ *     both ends towards the middle block, two chains of n/2 dependent block steps.
+ *   HELM_LINE_ND: 1D nested dissection in x1 (Sec. 6), done as block cyclic reduction: with
+ *     n = 2^k - 1 the line's blocks fall into k levels (block i at the number of trailing
+ *     zero bits of i + 1); each level is eliminated at once, the middle block last.  A line
+ *     solve then takes 2k - 1 dependent phases of independent block products instead of a
+ *     chain; the result is the same solve up to rounding.
+ * The first switch to HELM_LINE_ND factors every line in that order (complex64, about 2.9 x
+ * the memory of the block LDU factors, kept with them; 5 x that memory of work arrays during
+ * the call).  helm_update_medium then refactors both; adjoint sweeps and helm_line_factors
+ * keep using the block LDU.  Requires HELM_C64, n = 2^k - 1 and blocks of at most 96
+ * unknowns.  Errors: HELM_EINVAL (unsupported plan or solver), HELM_ENOMEM, HELM_ESINGULAR,
+ * HELM_EHIP.  Synchronises `stream`.
+ */
+#define HELM_LINE_LDU 0
+#define HELM_LINE_ND 1
+int helm_set_line_solver(helm_handle* h, int solver, void* stream);
 
 /* helm_get_stats -- fill *out (waits for the recorded events); helm_reset_stats -- zero them. */
 int helm_get_stats(helm_handle* h, helm_stats* out);

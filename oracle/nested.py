@@ -16,7 +16,9 @@ rounding, and the two halves of every level are independent: a solve has ceil(lo
 dependent levels instead of the n steps of the block LDU.
 
 Parity status: pinned (tests/test_oracle_nested.py) against a sparse direct solve of K, the
-block LDU solve of ``LineFactors``, and the level count; no HIP counterpart is built yet.
+block LDU solve of ``LineFactors``, and the level count.  The HIP line solver of the same
+elimination order (block cyclic reduction, helm_set_line_solver) is checked against the
+oracle's line solves and sweeps in tests/test_gpu_nd.py.
 """
 import math
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 
 HELM_OK, HELM_ENOTCONV, HELM_EINVAL, HELM_ENOMEM, HELM_ESINGULAR, HELM_EHIP = 0, 1, -1, -2, -3, -4
 HELM_C64, HELM_C128 = 0, 1
+HELM_LINE_LDU, HELM_LINE_ND = 0, 1
 
 
 class helm_grid(ctypes.Structure):
@@ -34,7 +35,8 @@ class helm_stats(ctypes.Structure):
                 ("matvec_rhs", ctypes.c_longlong), ("matvec_ms", ctypes.c_double),
                 ("matvec_bytes_per_rhs", ctypes.c_double), ("kernel_launches", ctypes.c_longlong),
                 ("kernel_rhs", ctypes.c_longlong), ("kernel_ms", ctypes.c_double),
-                ("kernel_bytes", ctypes.c_double), ("kernel_flops", ctypes.c_double)]
+                ("kernel_bytes", ctypes.c_double), ("kernel_flops", ctypes.c_double),
+                ("nd_setup_ms", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -62,6 +64,7 @@ _SIGS = {
     "helm_line_factors": (_I, [_P, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "helm_line_solve": (_I, [_P, _I, _I, _P, _P, _I, _I, _P]),
     "helm_set_launch": (_I, [_P, _I]),
+    "helm_set_line_solver": (_I, [_P, _I, _P]),
     "helm_sweep_shape": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_char_p, _I]),
     "helm_set_exchange_test": (_I, [_P, _I, ctypes.c_uint]),
     "helm_get_stats": (_I, [_P, ctypes.POINTER(helm_stats)]),
@@ -332,6 +335,12 @@ class Helm:
         _check(lib().helm_autotune(self.handle, int(R), path, ctypes.byref(v), ctypes.byref(ms), _stream()),
                "helm_autotune")
         return v.value, ms.value
+
+    def set_line_solver(self, solver):
+        """Line problems of the forward complex64 sweeps: "ldu" (block LDU chains) or "nd"
+        (nested dissection; factors them on the first switch)."""
+        kind = {"ldu": HELM_LINE_LDU, "nd": HELM_LINE_ND}[solver]
+        _check(lib().helm_set_line_solver(self.handle, kind, _stream()), "helm_set_line_solver")
 
     def set_launch(self, variant):
         """Use launch-shape variant k for the sweeps (-1: automatic)."""

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libhelm.so")
 
 # the sweep kernel's instantiations come first: they take longest
 SOURCES = ["sweep_c64_fwd.hip", "sweep_c64_fwd_z32.hip", "sweep_c64_adj.hip", "sweep_c64_adj_z32.hip",
-           "sweep_c128.hip", "api.hip", "plan.cpp", "pool.cpp", "coeffs.hip", "setup.hip", "sweep.hip",
+           "sweep_c128.hip", "sweep_c64_nd.hip", "api.hip", "plan.cpp", "pool.cpp", "coeffs.hip", "setup.hip", "sweep.hip",
            "stencil.hip", "krylov.hip", "static_apply.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -72,12 +72,30 @@ void release(helm_handle* h) {
   h->t_kernel.reset();
   void* ptrs[] = {h->kappa, h->sbd, h->smv, h->coef, h->diag, h->d_groups, h->d_line_off,
                   h->d_setup_lines, h->factors, h->d_err, h->slab_scratch, h->layer,
-                  h->d_rhs_idx, h->xbuf};
+                  h->d_rhs_idx, h->xbuf, h->nd, h->d_nd_off};
   for (void* p : ptrs)
     if (p) pool_free(p, h->last_stream);
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// the nested-dissection factors of every line (timed); on failure none are kept
+int nd_factor(helm_handle* h, hipStream_t s, std::string& why) {
+  LaunchTimer t;
+  hipEvent_t ev = t.begin(s);
+  const int rc = nd_build(h, s, why);
+  t.end(ev, s, 1);
+  t.flush();
+  h->nd_setup_ms = t.ms;
+  if (rc != HELM_OK) {
+    if (h->nd) pool_free(h->nd, s);
+    if (h->d_nd_off) pool_free(h->d_nd_off, s);
+    h->nd = nullptr;
+    h->d_nd_off = nullptr;
+    h->nd_on = false;
+  }
+  return rc;
+}
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -304,6 +322,25 @@ int helm_misfit(helm_handle* h, const void* u_dev, const void* d_dev, int R, int
   return HELM_OK;
 }
 
+int helm_set_line_solver(helm_handle* h, int solver, void* stream) {
+  if (!h) return fail(HELM_EINVAL, "handle must not be NULL");
+  if (solver == HELM_LINE_LDU) {
+    h->nd_on = false;
+    return HELM_OK;
+  }
+  if (solver != HELM_LINE_ND) return fail(HELM_EINVAL, "solver must be HELM_LINE_LDU or HELM_LINE_ND");
+  std::string why;
+  if (!nd_supported(h->plan, h->prec, why)) return fail(HELM_EINVAL, why);
+  hipStream_t s = S(stream);
+  h->last_stream = s;
+  if (!h->nd) {
+    const int rc = nd_factor(h, s, why);
+    if (rc != HELM_OK) return fail(rc, why);
+  }
+  h->nd_on = true;
+  return HELM_OK;
+}
+
 int helm_set_medium(helm_handle* h, const double* c_dev, void* stream) {
   if (!h || !c_dev) return fail(HELM_EINVAL, "handle and c_dev must not be NULL");
   hipStream_t s = S(stream);
@@ -355,6 +392,11 @@ int helm_update_medium(helm_handle* h, const double* c_dev, const int* box_host,
   h->setup_ms = t.ms;
   if (n_refactored) *n_refactored = (int)lines.size();
   if (err[0]) return fail(HELM_ESINGULAR, "singular block in line " + std::to_string(err[1]));
+  if (h->nd) {   // the nested-dissection factors, all lines again
+    std::string why;
+    const int rc = nd_factor(h, s, why);
+    if (rc != HELM_OK) return fail(rc, why);
+  }
   return HELM_OK;
 }
 
@@ -520,6 +562,7 @@ int helm_get_stats(helm_handle* h, helm_stats* out) {
   out->kernel_ms = h->t_kernel.ms;
   out->kernel_bytes = h->t_kernel.bytes;
   out->kernel_flops = h->t_kernel.flops;
+  out->nd_setup_ms = h->nd_setup_ms;
   return HELM_OK;
 }
 

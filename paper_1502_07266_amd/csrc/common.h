@@ -188,6 +188,14 @@ struct helm_handle {
   int* d_setup_lines = nullptr;    // [Gz*Gy] line indices in setup_classes order
   long long* d_line_off = nullptr; // [Gz*Gy]
   void* factors = nullptr;         // total_elems complex64 or complex128
+  // nested-dissection line solver (complex64 forward sweeps): its factors, per-line offsets,
+  // levels k (n = 2^k - 1); used by the forward sweeps while nd_on
+  void* nd = nullptr;
+  long long* d_nd_off = nullptr;
+  int nd_k = 0;
+  bool nd_on = false;
+  size_t nd_bytes = 0;
+  double nd_setup_ms = 0.0;
   int* d_err = nullptr;            // [2]: error flag, first failing line
 
   // timing
@@ -228,6 +236,11 @@ hipError_t take_exchange_error(helm_handle* h, hipStream_t s, int* bad);
 // ---------------------------------------------------------------------------------------
 hipError_t launch_coefficients(helm_handle* h, const double* c_dev, bool tables, hipStream_t s);
 hipError_t launch_setup(helm_handle* h, hipStream_t s);
+// nested-dissection line solver: support of a plan, entries per line (times B^2), and the
+// factorisation of every line into h->nd (HELM_OK or an error code with msg)
+bool nd_supported(const Plan& P, int prec, std::string& why);
+long long nd_line_blocks(int n);
+int nd_build(helm_handle* h, hipStream_t s, std::string& msg);
 // the setup's launches: lines in class order (blocks whose two B x B copies fit a quarter of
 // the LDS, other blocks up to 64, larger blocks), the count and largest block of each class
 // dynamic LDS a setup workgroup takes for blocks up to maxB (complex element size csz), and

@@ -544,3 +544,427 @@ hipError_t launch_setup_lines(helm_handle* h, const int* d_lines, const SetupCla
   if (start) (void)hipEventDestroy(start);
   return e;
 }
+
+// ==========================================================================================
+// Nested-dissection factors of the line problems (complex64): block cyclic reduction in x1.
+//
+// Sec. 6 suggests replacing the line's block LDU by a 1D nested dissection, whose halves are
+// independent at every level.  With n = 2^k - 1 blocks, block i belongs to level
+// l_i = (trailing zeros of i + 1); level 0 are the even blocks, level k - 1 the middle block
+// n / 2 alone.  Eliminating level 0, then 1, ... is Gaussian elimination of the line in the
+// nested-dissection order (each level's separators after the halves they split).  Before
+// level l the reduced system couples block i only to i - 2^l (L_i) and i + 2^l (U_i); at
+// level 0 these are the scalar x1-couplings l_i I and u_i I.  Eliminating the level-l blocks
+// e (s = 2^l) with Inv_e = D_e^{-1}, G_e = Inv_e L_e, H_e = Inv_e U_e leaves, for each
+// remaining block r with e1 = r - s, e2 = r + s,
+//     D_r <- D_r - L_r H_e1 - U_r G_e2,   L_r <- -L_r G_e1,   U_r <- -U_r H_e2,
+// and a solve reduces the right-hand sides level by level (b_r -= P_r b_e1 + Q_r b_e2 with
+// P_r = L_r Inv_e1, Q_r = U_r Inv_e2), solves the middle block, and substitutes back
+// (x_e = Inv_e b_e - G_e x_{e-s} - H_e x_{e+s}).
+//
+// Stored per line, blocks B x B column-major (element (r, c) at c B + r), block i's matrices
+// from (3 i - 2 popcount(i)) B^2 on: Inv_i, and for l_i >= 1 also G_i, H_i and P_i, Q_i of
+// the levels 1 .. l_i - 1 (at level 0, P and Q are the neighbours' Inv times a scalar).  A
+// line takes (3 n - 2 popcount(n)) B^2 entries, about 2.9 times its block LDU factors.
+// ==========================================================================================
+namespace {
+
+constexpr size_t kNdPad = 64;   // complex zeros after the factors (the solve's row clamp reads stay inside)
+
+__host__ __device__ inline long long nd_first(int i) { return 3LL * i - 2LL * __builtin_popcount((unsigned)i); }
+
+struct NdArgs {
+  int n, k, Gz, Gy, level;
+  double h;
+  const GroupInfo* groups;
+  const long long* woff;   // per line: offset of its n dense work blocks (the block LDU layout)
+  const long long* foff;   // per line: offset of its nested-dissection factors
+  const int* lines;        // lines of this launch (blockIdx.y)
+  const double2* sbd;
+  float2* F;
+  float2 *Wd, *Wl, *Wu, *Wl2, *Wu2;
+  int* err;
+};
+
+__device__ inline float2 nd_l(const NdArgs& a, int i) {   // K_{i,i-1} = l_i I
+  const int m = i + 1;
+  return cvt<float2>(cscale(cmul(a.sbd[2 * m], a.sbd[2 * m - 1]), 1.0 / (a.h * a.h)));
+}
+__device__ inline float2 nd_u(const NdArgs& a, int i) {   // K_{i,i+1} = u_i I
+  const int m = i + 1;
+  return cvt<float2>(cscale(cmul(a.sbd[2 * m], a.sbd[2 * m + 1]), 1.0 / (a.h * a.h)));
+}
+
+// D_i of every block of the launch's lines, dense, column-major into Wd (workgroup: block
+// blockIdx.x of line lines[blockIdx.y]); the entries are those of the block LDU's D_i
+__global__ void __launch_bounds__(256) k_nd_form(SetupArgs s, NdArgs a) {
+  __shared__ double2 syn[kMaxW], syh[kMaxW + 1], szn[kMaxW], szh[kMaxW + 1];
+  const int line = a.lines[blockIdx.y], i = blockIdx.x;
+  const int g = line / a.Gy, l = line % a.Gy;
+  const GroupInfo gz = a.groups[g], gy = a.groups[a.Gz + l];
+  const int Wz = gz.W, Wy = gy.W, B = Wy * Wz, n = a.n, tid = threadIdx.x;
+  if (tid < Wy) syn[tid] = window_s(s, gy, 2 * (gy.w0 + tid));
+  if (tid <= Wy) syh[tid] = window_s(s, gy, 2 * (gy.w0 + tid) - 1);
+  if (tid < Wz) szn[tid] = window_s(s, gz, 2 * (gz.w0 + tid));
+  if (tid <= Wz) szh[tid] = window_s(s, gz, 2 * (gz.w0 + tid) - 1);
+  __syncthreads();
+  const double ih2 = 1.0 / (a.h * a.h);
+  const int m = i + 1;
+  const double2 dx = cscale(cmul(a.sbd[2 * m], cadd(a.sbd[2 * m + 1], a.sbd[2 * m - 1])), -ih2);
+  float2* out = a.Wd + a.woff[line] + (long long)i * B * B;
+  for (int e = tid; e < B * B; e += blockDim.x) {
+    const int c = e / B, r = e - c * B;   // column-major
+    const int jr = r / Wz, kr = r - jr * Wz, jc = c / Wz, kc = c - jc * Wz;
+    double2 val = make_double2(0.0, 0.0);
+    if (r == c) {
+      const int k = gz.w0 + kr, jj = gy.w0 + jr;
+      const double kap = s.kappa[((long long)(k - 1) * n + (jj - 1)) * n + i];
+      const double2 dy = cscale(cmul(syn[jr], cadd(syh[jr + 1], syh[jr])), -ih2);
+      const double2 dz = cscale(cmul(szn[kr], cadd(szh[kr + 1], szh[kr])), -ih2);
+      val = cadd(cadd(dx, dy), dz);
+      val.x += kap;
+    } else if (jr == jc) {
+      if (kc == kr + 1) val = cscale(cmul(szn[kr], szh[kr + 1]), ih2);
+      else if (kc == kr - 1) val = cscale(cmul(szn[kr], szh[kr]), ih2);
+    } else if (kr == kc) {
+      if (jc == jr + 1) val = cscale(cmul(syn[jr], syh[jr + 1]), ih2);
+      else if (jc == jr - 1) val = cscale(cmul(syn[jr], syh[jr]), ih2);
+    }
+    out[e] = cvt<float2>(val);
+  }
+}
+
+// Inv_e = D_e^{-1} for the level's blocks e = (2 j + 1) 2^level - 1 (j = blockIdx.x):
+// Gauss-Jordan elimination with partial pivoting (row exchanges) on [D_e | I] in LDS
+__global__ void __launch_bounds__(256) k_nd_invert(NdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ float2 fcol[kMaxB];
+  __shared__ int piv_s;
+  const int line = a.lines[blockIdx.y];
+  const int e = (2 * (int)blockIdx.x + 1) * (1 << a.level) - 1;
+  const int g = line / a.Gy, l = line % a.Gy;
+  const int B = a.groups[g].W * a.groups[a.Gz + l].W, W2 = 2 * B;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  float2* M = reinterpret_cast<float2*>(smem_raw);   // B rows of 2B: row r at M + r 2B
+  const float2* src = a.Wd + a.woff[line] + (long long)e * B * B;
+  for (int x = tid; x < B * W2; x += NT) {
+    const int r = x / W2, c = x - r * W2;
+    M[x] = c < B ? src[(long long)c * B + r] : make_float2(c - B == r ? 1.f : 0.f, 0.f);
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < B; ++k) {
+    if (tid < 64) {
+      float best = -1.f;
+      int br = k;
+      for (int r = k + tid; r < B; r += 64) {
+        const float m = cabs2(M[r * W2 + k]);
+        if (m > best || m != m) {
+          best = m != m ? __builtin_huge_valf() : m;
+          br = r;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off);
+        const int orr = __shfl_xor(br, off);
+        if (ob > best || (ob == best && orr < br)) {
+          best = ob;
+          br = orr;
+        }
+      }
+      if (tid == 0) piv_s = br;
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != k)
+      for (int c = k + tid; c < W2; c += NT) {
+        const float2 t = M[k * W2 + c];
+        M[k * W2 + c] = M[p * W2 + c];
+        M[p * W2 + c] = t;
+      }
+    __syncthreads();
+    const float2 pv = M[k * W2 + k];
+    const float pm = cabs2(pv);
+    if (!(pm > 0.f) || !(pm < __builtin_huge_valf())) bad = true;
+    const float2 pinv = (pm > 0.f && pm < __builtin_huge_valf()) ? cinv(pv) : make_float2(1.f, 0.f);
+    for (int r = tid; r < B; r += NT) fcol[r] = M[r * W2 + k];
+    __syncthreads();
+    for (int c = k + tid; c < W2; c += NT) M[k * W2 + c] = cmul(M[k * W2 + c], pinv);
+    __syncthreads();
+    const int span = W2 - k;
+    for (int x = tid; x < B * span; x += NT) {
+      const int r = x / span, c = k + (x - r * span);
+      if (r != k) M[r * W2 + c] = csub(M[r * W2 + c], cmul(fcol[r], M[k * W2 + c]));
+    }
+    __syncthreads();
+  }
+  if (bad && tid == 0) {
+    atomicOr(&a.err[0], 1);
+    atomicExch(&a.err[1], line);
+  }
+  float2* dst = a.F + a.foff[line] + nd_first(e) * B * B;
+  for (int x = tid; x < B * B; x += NT) {
+    const int c = x / B, r = x - c * B;
+    dst[x] = M[r * W2 + B + c];
+  }
+}
+
+// after level 0: for the odd blocks r, D_r -= l_r u_{r-1} Inv_{r-1} + u_r l_{r+1} Inv_{r+1},
+// L_r = -l_r l_{r-1} Inv_{r-1} (0 when r - 2 < 0), U_r = -u_r u_{r+1} Inv_{r+1} (0 past the end)
+__global__ void __launch_bounds__(256) k_nd_level0(NdArgs a) {
+  const int line = a.lines[blockIdx.y];
+  const int r = 2 * (int)blockIdx.x + 1;
+  const int g = line / a.Gy, l = line % a.Gy;
+  const int B = a.groups[g].W * a.groups[a.Gz + l].W;
+  const long long BB = (long long)B * B;
+  const float2 lr = nd_l(a, r), ur = nd_u(a, r);
+  const float2 c1 = cmul(lr, nd_u(a, r - 1)), c2 = cmul(ur, nd_l(a, r + 1));
+  const float2 cl = r - 2 >= 0 ? cmul(make_float2(-lr.x, -lr.y), nd_l(a, r - 1)) : make_float2(0.f, 0.f);
+  const float2 cu = r + 2 <= a.n - 1 ? cmul(make_float2(-ur.x, -ur.y), nd_u(a, r + 1)) : make_float2(0.f, 0.f);
+  const float2* I1 = a.F + a.foff[line] + nd_first(r - 1) * BB;
+  const float2* I2 = a.F + a.foff[line] + nd_first(r + 1) * BB;
+  const long long w = a.woff[line] + r * BB;
+  for (int x = threadIdx.x; x < B * B; x += blockDim.x) {
+    const float2 i1 = I1[x], i2 = I2[x];
+    a.Wd[w + x] = csub(csub(a.Wd[w + x], cmul(c1, i1)), cmul(c2, i2));
+    a.Wl[w + x] = cmul(cl, i1);
+    a.Wu[w + x] = cmul(cu, i2);
+  }
+}
+
+// one output C (B x B, column-major) = beta C + s1 A1 B1 + s2 A2 B2 on the matrix cores:
+// 16 x 16 tiles over the four waves, complex products as four real 16 x 16 x 4 products
+__device__ inline void nd_gemm(float2* C, bool beta, const float2* A1, const float2* B1, float2 s1,
+                               const float2* A2, const float2* B2, float2 s2, int B) {
+  using M = Mfma<float>;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const int RT = (B + 15) >> 4;
+  for (int tile = wv; tile < RT * RT; tile += NW) {
+    const int ti = tile / RT, tj = tile - ti * RT;
+    const int col = tj * 16 + (lane & 15), arow = ti * 16 + (lane & 15);
+    f32x4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 2; ++t) {
+      const float2* A = t ? A2 : A1;
+      const float2* Bm = t ? B2 : B1;
+      if (!A) continue;
+      const float2 sc = t ? s2 : s1;
+      f32x4 pre = {0.f, 0.f, 0.f, 0.f}, pim = {0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < B; k0 += 4) {
+        const int kk = k0 + (lane >> 4);
+        const float2 av = (arow < B && kk < B) ? A[(long long)kk * B + arow] : make_float2(0.f, 0.f);
+        const float2 bv = (kk < B && col < B) ? Bm[(long long)col * B + kk] : make_float2(0.f, 0.f);
+        pre = M::mac(av.x, bv.x, pre);
+        pre = M::mac(-av.y, bv.y, pre);
+        pim = M::mac(av.x, bv.y, pim);
+        pim = M::mac(av.y, bv.x, pim);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cre[q] += sc.x * pre[q] - sc.y * pim[q];
+        cim[q] += sc.x * pim[q] + sc.y * pre[q];
+      }
+    }
+    if (col < B) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = ti * 16 + M::row(lane, q);
+        if (row < B) {
+          float2 v = make_float2(cre[q], cim[q]);
+          if (beta) v = cadd(v, C[(long long)col * B + row]);
+          C[(long long)col * B + row] = v;
+        }
+      }
+    }
+  }
+}
+
+// level >= 1, after the inversions: G_e, H_e of the level's blocks (blockIdx.x = 2 j + kind)
+__global__ void __launch_bounds__(256) k_nd_gh(NdArgs a) {
+  const int line = a.lines[blockIdx.y];
+  const int j = (int)blockIdx.x >> 1, kind = (int)blockIdx.x & 1;
+  const int e = (2 * j + 1) * (1 << a.level) - 1;
+  const int g = line / a.Gy, l = line % a.Gy;
+  const int B = a.groups[g].W * a.groups[a.Gz + l].W;
+  const long long BB = (long long)B * B;
+  float2* f = a.F + a.foff[line] + nd_first(e) * BB;
+  const float2* W = (kind ? a.Wu : a.Wl) + a.woff[line] + e * BB;
+  nd_gemm(f + (1 + kind) * BB, false, f, W, make_float2(1.f, 0.f), nullptr, nullptr, make_float2(0.f, 0.f), B);
+}
+
+// level >= 1: for the remaining blocks r = 2 (m + 1) 2^level - 1 (blockIdx.x = 5 m + kind):
+// P_r, Q_r (kinds 0, 1), the new D_r (2), L_r and U_r into the second buffers (3, 4)
+__global__ void __launch_bounds__(256) k_nd_reduce(NdArgs a) {
+  const int line = a.lines[blockIdx.y];
+  const int m = (int)blockIdx.x / 5, kind = (int)blockIdx.x - 5 * m;
+  const int s = 1 << a.level, r = 2 * (m + 1) * s - 1, e1 = r - s, e2 = r + s;
+  const int g = line / a.Gy, l = line % a.Gy;
+  const int B = a.groups[g].W * a.groups[a.Gz + l].W;
+  const long long BB = (long long)B * B, wo = a.woff[line];
+  const float2* Fl = a.F + a.foff[line];
+  const float2* I1 = Fl + nd_first(e1) * BB;
+  const float2* I2 = Fl + nd_first(e2) * BB;
+  const float2* Lr = a.Wl + wo + r * BB;
+  const float2* Ur = a.Wu + wo + r * BB;
+  const float2 one = make_float2(1.f, 0.f), mone = make_float2(-1.f, 0.f), zero = make_float2(0.f, 0.f);
+  float2* Pr = a.F + a.foff[line] + (nd_first(r) + 3 + 2 * (a.level - 1)) * BB;
+  switch (kind) {
+    case 0: nd_gemm(Pr, false, Lr, I1, one, nullptr, nullptr, zero, B); break;
+    case 1: nd_gemm(Pr + BB, false, Ur, I2, one, nullptr, nullptr, zero, B); break;
+    case 2: nd_gemm(a.Wd + wo + r * BB, true, Lr, I1 + 2 * BB, mone, Ur, I2 + BB, mone, B); break;
+    case 3: nd_gemm(a.Wl2 + wo + r * BB, false, Lr, I1 + BB, mone, nullptr, nullptr, zero, B); break;
+    default: nd_gemm(a.Wu2 + wo + r * BB, false, Ur, I2 + 2 * BB, mone, nullptr, nullptr, zero, B); break;
+  }
+}
+
+}  // namespace
+
+long long nd_line_blocks(int n) { return nd_first(n); }
+
+bool nd_supported(const Plan& P, int prec, std::string& why) {
+  if (prec != HELM_C64) {
+    why = "the nested-dissection line solver is built for complex64 factors";
+    return false;
+  }
+  if (P.n < 3 || ((P.n + 1) & P.n) != 0) {
+    why = "the nested-dissection line solver needs n = 2^k - 1 blocks per line";
+    return false;
+  }
+  if (P.maxB > 96) {
+    why = "the nested-dissection setup inverts blocks of at most 96 unknowns";
+    return false;
+  }
+  return true;
+}
+
+// the factors of every line (see above) into h->nd; the work arrays come from the pool and go
+// back to it
+int nd_build(helm_handle* h, hipStream_t s, std::string& msg) {
+  const Plan& P = h->plan;
+  if (!nd_supported(P, h->prec, msg)) return HELM_EINVAL;
+  const int n = P.n, lines = P.Gz * P.Gy;
+  int k = 0;
+  while ((1 << k) < n + 1) ++k;
+  std::vector<long long> foff(lines);
+  long long total = 0;
+  for (int line = 0; line < lines; ++line) {
+    foff[line] = total;
+    total += nd_line_blocks(n) * (long long)P.line_B[line] * P.line_B[line];
+  }
+  // lines by block size: each launch of the inversion sized by its largest block
+  std::vector<int> order(lines);
+  for (int i = 0; i < lines; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return P.line_B[x] < P.line_B[y]; });
+  std::vector<std::pair<int, int>> cls;   // [first, count) ranges of `order` with maxB <= 48, 64, 96
+  for (int lim : {48, 64, 96}) {
+    int first = cls.empty() ? 0 : cls.back().first + cls.back().second, cnt = 0;
+    while (first + cnt < lines && P.line_B[order[first + cnt]] <= lim) ++cnt;
+    if (cnt) cls.push_back({first, cnt});
+  }
+  const size_t W = (size_t)P.total_elems * sizeof(float2);
+  const size_t fbytes = ((size_t)total + kNdPad) * sizeof(float2);
+  void *F = nullptr, *Wd = nullptr, *Wl = nullptr, *Wu = nullptr, *Wl2 = nullptr, *Wu2 = nullptr;
+  long long* d_foff = nullptr;
+  int* d_order = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : {Wd, Wl, Wu, Wl2, Wu2, (void*)d_order})
+      if (p) pool_free(p, s);
+  };
+  if (h->nd) {
+    pool_free(h->nd, s);
+    h->nd = nullptr;
+  }
+  if (h->d_nd_off) {
+    pool_free(h->d_nd_off, s);
+    h->d_nd_off = nullptr;
+  }
+  if (pool_alloc(&F, fbytes, s) != hipSuccess || pool_alloc((void**)&d_foff, lines * sizeof(long long), s) != hipSuccess ||
+      pool_alloc(&Wd, W, s) != hipSuccess || pool_alloc(&Wl, W, s) != hipSuccess ||
+      pool_alloc(&Wu, W, s) != hipSuccess || pool_alloc(&Wl2, W, s) != hipSuccess ||
+      pool_alloc(&Wu2, W, s) != hipSuccess || pool_alloc((void**)&d_order, lines * sizeof(int), s) != hipSuccess) {
+    cleanup();
+    if (F) pool_free(F, s);
+    if (d_foff) pool_free(d_foff, s);
+    msg = "device allocation failed for the nested-dissection factors (" + std::to_string(fbytes) +
+          " bytes) and their work arrays (5 x " + std::to_string(W) + " bytes)";
+    return HELM_ENOMEM;
+  }
+  h->nd = F;
+  h->d_nd_off = d_foff;
+  h->nd_k = k;
+  h->nd_bytes = fbytes;
+  hipError_t e = hipMemsetAsync((char*)F + (size_t)total * sizeof(float2), 0, kNdPad * sizeof(float2), s);
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_err, 0, 2 * sizeof(int), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_foff, foff.data(), lines * sizeof(long long), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), lines * sizeof(int), hipMemcpyHostToDevice, s);
+  SetupArgs sa{};
+  sa.n = n;
+  sa.Gz = P.Gz;
+  sa.Gy = P.Gy;
+  sa.p = P.p;
+  sa.h = h->h;
+  sa.groups = h->d_groups;
+  sa.sbd = h->sbd;
+  sa.smv = h->smv;
+  sa.kappa = h->kappa;
+  NdArgs a{};
+  a.n = n;
+  a.k = k;
+  a.Gz = P.Gz;
+  a.Gy = P.Gy;
+  a.h = h->h;
+  a.groups = h->d_groups;
+  a.woff = h->d_line_off;
+  a.foff = d_foff;
+  a.lines = d_order;
+  a.sbd = h->sbd;
+  a.F = static_cast<float2*>(F);
+  a.Wd = static_cast<float2*>(Wd);
+  a.Wl = static_cast<float2*>(Wl);
+  a.Wu = static_cast<float2*>(Wu);
+  a.Wl2 = static_cast<float2*>(Wl2);
+  a.Wu2 = static_cast<float2*>(Wu2);
+  a.err = h->d_err;
+  if (e == hipSuccess) {
+    k_nd_form<<<dim3(n, lines), 256, 0, s>>>(sa, a);
+    e = hipGetLastError();
+  }
+  for (int lev = 0; lev < k && e == hipSuccess; ++lev) {
+    a.level = lev;
+    const int nelim = 1 << (k - 1 - lev);   // blocks of this level
+    for (const auto& c : cls) {
+      const int maxB = P.line_B[order[c.first + c.second - 1]];
+      const size_t sm = (size_t)2 * maxB * maxB * sizeof(float2);
+      NdArgs ac = a;
+      ac.lines = d_order + c.first;
+      e = hipFuncSetAttribute((const void*)k_nd_invert, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+      if (e != hipSuccess) break;
+      k_nd_invert<<<dim3(nelim, c.second), 256, sm, s>>>(ac);
+      e = hipGetLastError();
+      if (e != hipSuccess) break;
+    }
+    if (e != hipSuccess || lev == k - 1) break;
+    const int nrem = nelim - 1;   // blocks above this level
+    if (lev == 0) {
+      k_nd_level0<<<dim3(nrem, lines), 256, 0, s>>>(a);
+    } else {
+      k_nd_gh<<<dim3(2 * nelim, lines), 256, 0, s>>>(a);
+      k_nd_reduce<<<dim3(5 * nrem, lines), 256, 0, s>>>(a);
+      std::swap(a.Wl, a.Wl2);
+      std::swap(a.Wu, a.Wu2);
+    }
+    e = hipGetLastError();
+  }
+  int err[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(err, h->d_err, sizeof(err), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) {
+    msg = std::string("nested-dissection setup: ") + hipGetErrorString(e);
+    return HELM_EHIP;
+  }
+  if (err[0]) {
+    msg = "singular reduced block in line " + std::to_string(err[1]) + " (nested-dissection setup)";
+    return HELM_ESINGULAR;
+  }
+  return HELM_OK;
+}

@@ -117,7 +117,8 @@ std::string tune_key(const helm_handle* h, int R) {
   return "n=" + std::to_string(P.n) + ",front=" + std::to_string(P.maxB_front) + ",maxB=" +
          std::to_string(P.maxB) + ",maxW=" + std::to_string(P.maxW) + ",fronts=" +
          std::to_string(P.fronts) + std::to_string(P.fronts_inner) + ",prec=" +
-         (h->prec == HELM_C64 ? "c64" : "c128") + ",R=" + std::to_string((R + 7) / 8 * 8);
+         (h->prec == HELM_C64 ? "c64" : "c128") + ",R=" + std::to_string((R + 7) / 8 * 8) +
+         (h->nd_on ? ",nd" : "");
 }
 
 int tuned_variant(const std::string& key) {
@@ -146,6 +147,10 @@ std::vector<int> tune_candidates(const helm_handle* h) {
   std::sort(capB.begin(), capB.end());
   capB.erase(std::unique(capB.begin(), capB.end()), capB.end());
   std::vector<int> out;
+  if (h->nd_on) {   // the nested-dissection kernel has one shape: only its placement varies
+    for (int m = 0; m < 3; ++m) out.push_back(4 * default_variant(h) + m);
+    return out;
+  }
   for (int k = 0; k < (int)vs.size(); ++k) {
     if (!variant_valid(h, k) || vs[k].capA() < h->plan.maxB_front) continue;
     const bool a = vs[k].capA() == capA[0] || (capA.size() > 1 && vs[k].capA() == capA[1]);
@@ -276,9 +281,14 @@ hipError_t run_launches(helm_handle* h, SweepArgs a, int choice, bool z64, bool 
   const int k = choice / 4;
   a.xmap = choice % 4;
   const SweepVariant v = sweep_variants(c64)[k];
-  const void* kern = sweep_kernel(c64, z64, adj, k);
+  // line solves by nested dissection (forward complex64 sweeps, once its factors exist)
+  const bool nd = h->nd_on && h->nd && c64 && !adj;
+  const void* kern = nd ? sweep_kernel_c64_nd(z64) : sweep_kernel(c64, z64, adj, k);
   if (!kern) return hipErrorInvalidValue;
-  const int tpc = variant_threads(P, v);
+  const int tpc = nd ? sweepk::kNdThreads : variant_threads(P, v);
+  a.nd = nd ? h->nd : nullptr;
+  a.nd_off = nd ? h->d_nd_off : nullptr;
+  a.nd_k = nd ? h->nd_k : 0;
   const size_t sm = MemberLds(P.n, P.maxB, P.maxW, (int)csize(h)).bytes;
   int slots = 0;
   hipError_t e = slots_per_launch(h, kern, tpc, sm, a.wpr, &slots);

@@ -83,6 +83,9 @@ struct SweepArgs {
   unsigned spin_limit;
   int drop_publish;      // failure injection: member 0 of every pair skips publishing E1
   int xmap;              // workgroup placement over the XCDs (see k_sweep)
+  const void* nd;        // nested-dissection factors (k_sweep_nd), per line at nd_off[line]
+  const long long* nd_off;
+  int nd_k;              // levels: n = 2^nd_k - 1
 };
 
 // exchange words per launch slot (all counts in 64-bit words; np = 32-bit pieces per value)
@@ -511,8 +514,11 @@ template <int NCA, int CWA, int NCB, int CWB> constexpr int kernel_threads_max()
 // One member's part of the sweep (see the top of this file).  Everything is inlined into the
 // kernel (each step of the program is reached from a single call site), so the member's
 // state stays in registers: a call taking the object's address would put it in scratch.
+// first of block i's nested-dissection matrices, in B^2 units from the line's start
+__device__ __forceinline__ long long nd_first(int i) { return 3LL * i - 2LL * __popc((unsigned)i); }
+
 template <typename R, typename TI, typename TO, int NCA, int CWA, int DA, int NCB, int CWB, int DB,
-          bool ADJ>
+          bool ADJ, bool ND = false>
 struct Sweeper {
   using C = typename cx<R>::type;
   static constexpr int np = sizeof(C) / 4;   // 32-bit pieces per value
@@ -527,6 +533,9 @@ struct Sweeper {
   const GroupInfo* groups;
   const long long* line_off;
   const C* factors;
+  const C* ndf;               // nested-dissection factors (ND)
+  const long long* nd_off;
+  int nd_k;
   unsigned long long *x1mine, *x1other, *xs;
   int* xerr;
   long long e23, e45;
@@ -549,6 +558,9 @@ struct Sweeper {
     groups = a.groups;
     line_off = a.line_off;
     factors = reinterpret_cast<const C*>(a.factors);
+    ndf = reinterpret_cast<const C*>(a.nd);
+    nd_off = a.nd_off;
+    nd_k = a.nd_k;
     xerr = a.xerr;
     seq0 = a.seq0;
     spin = a.spin_limit;
@@ -612,8 +624,185 @@ struct Sweeper {
     lcount += 1;
   }
   template <typename G> __device__ __forceinline__ void solve_any(const C* T, int B, G& gather) {
-    if (B <= NCA * CWA) solve<NCA, CWA, DA>(T, B, gather);
-    else solve<NCB, CWB, DB>(T, B, gather);
+    if constexpr (ND) {
+      gather();
+      __syncthreads();
+      if (B <= 64) nd_solve<1>(T, B);
+      else nd_solve<2>(T, B);
+      lcount += 1;
+    } else {
+      if (B <= NCA * CWA) solve<NCA, CWA, DA>(T, B, gather);
+      else solve<NCB, CWB, DB>(T, B, gather);
+    }
+  }
+  // the factors of line (g, l): its block LDU factors, or its nested-dissection matrices
+  __device__ __forceinline__ const C* line_factors(int g, int l) const {
+    const size_t line = (size_t)g * Gy + l;
+    return ND ? ndf + nd_off[line] : factors + line_off[line];
+  }
+
+  // ---- nested-dissection line solve (block cyclic reduction; the factor layout is described
+  // with the setup).  acc[rr] (row lane + 64 rr) += sc (M v), M column-major B x B in HBM, v
+  // in LDS: a wave per product, 16 (8 with two rows per lane) columns' loads in flight
+  template <int RPL>
+  __device__ __forceinline__ void nd_mv(C (&acc)[RPL], const C* M, C sc, const C* v, int B) const {
+    const int lane = tid & 63;
+    int rows[RPL];
+    C t[RPL];
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+      rows[rr] = lane + 64 * rr < B ? lane + 64 * rr : B - 1;
+      t[rr] = mk((R)0, (R)0);
+    }
+    constexpr int U = RPL == 1 ? 16 : 8;
+    for (int j0 = 0; j0 < B; j0 += U) {
+      C mv[U][RPL], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u < B ? j0 + u : B - 1;
+        xv[u] = v[j];
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) mv[u][rr] = M[(long long)j * B + rows[rr]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u < B)
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) t[rr] = cfma(t[rr], mv[u][rr], xv[u]);
+    }
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) acc[rr] = cfma(acc[rr], sc, t[rr]);
+  }
+  // acc[rr] = M (b - c1 x1 - c2 x2), or M (b + x1) with sum (the two halves' middle parts)
+  template <int RPL>
+  __device__ __forceinline__ void nd_mv3(C (&acc)[RPL], const C* M, const C* b, const C* x1, C c1,
+                                         const C* x2, C c2, int B) const {
+    const int lane = tid & 63;
+    int rows[RPL];
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+      rows[rr] = lane + 64 * rr < B ? lane + 64 * rr : B - 1;
+      acc[rr] = mk((R)0, (R)0);
+    }
+    constexpr int U = RPL == 1 ? 16 : 8;
+    for (int j0 = 0; j0 < B; j0 += U) {
+      C mv[U][RPL], xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u < B ? j0 + u : B - 1;
+        xv[u] = csub(csub(b[j], cmul(c1, x1[j])), cmul(c2, x2[j]));
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) mv[u][rr] = M[(long long)j * B + rows[rr]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u < B)
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) acc[rr] = cfma(acc[rr], mv[u][rr], xv[u]);
+    }
+  }
+  template <int RPL> __device__ __forceinline__ void nd_load(C (&acc)[RPL], const C* v, int B) const {
+    const int lane = tid & 63;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) acc[rr] = v[lane + 64 * rr < B ? lane + 64 * rr : B - 1];
+  }
+  template <int RPL> __device__ __forceinline__ void nd_store(C* v, const C (&acc)[RPL], int B) const {
+    const int lane = tid & 63;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr)
+      if (lane + 64 * rr < B) v[lane + 64 * rr] = acc[rr];
+  }
+
+  // Solve on the right-hand side in the member's half of ybuf (complete, after a barrier); on
+  // return ybuf holds the solution on the member's blocks.  Half 0 takes blocks 0 .. mid - 1
+  // and the middle block's reduction from below, half 1 blocks mid + 1 .. n - 1 and the
+  // reduction from above (its copy of the middle block in the first published-vector slot);
+  // the two partial right-hand sides of the middle block are summed through E1, and both
+  // halves solve the middle block.  Every level is one phase: its products spread over the
+  // waves, one barrier after it.
+  template <int RPL> __device__ void nd_solve(const C* F, int B) {
+    const int k = nd_k, mid = n / 2, wv = tid >> 6, NW = NT >> 6;
+    const long long BB = (long long)B * B;
+    C* yb = sb + L.ybuf;
+    C* own = half ? sb + L.zb : yb + (mid - ilo) * B;   // this half's copy of the middle block
+    C* oth = sb + L.zb + kZMax;                         // the partner's partial
+    const C* zv = sb + L.zeros;
+    const C zero = mk((R)0, (R)0), one = mk((R)1, (R)0), mone = mk((R)-1, (R)0);
+    auto vec = [&](int i) -> C* { return i == mid ? own : yb + (i - ilo) * B; };
+    auto mat = [&](int i, int q) -> const C* { return F + (nd_first(i) + q) * BB; };
+    if (half)
+      for (int x = tid; x < B; x += NT) own[x] = zero;
+    __syncthreads();
+    // forward: level l reduces the right-hand sides of the blocks above it (r = m 2^{l+1} - 1)
+    // and, for l >= 2, turns those of level l - 1 into y = Inv b
+    for (int l = 0; l <= k - 2; ++l) {
+      const int s = 1 << l, mh = 1 << (k - 2 - l);
+      const int m0 = half ? mh : 1, ny = l >= 2 ? 2 * mh : 0, o0 = half ? 4 * mh + 1 : 1;
+      for (int t = wv; t < mh + ny; t += NW) {
+        C acc[RPL];
+        if (t < mh) {
+          const int r = (m0 + t) * 2 * s - 1;
+          nd_load<RPL>(acc, vec(r), B);
+          if (r != mid || !half)
+            nd_mv<RPL>(acc, l == 0 ? mat(r - 1, 0) : mat(r, 3 + 2 * (l - 1)), l == 0 ? csub(zero, cf[r + 1]) : mone,
+                       vec(r - s), B);
+          if (r != mid || half)
+            nd_mv<RPL>(acc, l == 0 ? mat(r + 1, 0) : mat(r, 4 + 2 * (l - 1)), l == 0 ? csub(zero, cb[r + 1]) : mone,
+                       vec(r + s), B);
+          nd_store<RPL>(vec(r), acc, B);
+        } else {
+          const int e = (o0 + 2 * (t - mh)) * (s >> 1) - 1;
+          nd_mv3<RPL>(acc, mat(e, 0), vec(e), zv, zero, zv, zero, B);
+          nd_store<RPL>(vec(e), acc, B);
+        }
+      }
+      __syncthreads();
+    }
+    // E1: the partial right-hand side of the middle block to the partner, the partner's in
+    {
+      const int par = (int)(lcount & 1);
+      unsigned long long* mine = x1mine + par * kZMax * np;
+      const unsigned long long* other = x1other + par * kZMax * np;
+      const unsigned long long tag = ((seq0 + lcount + 1) & 0xffffffffull) << 32;
+      const unsigned* src = reinterpret_cast<const unsigned*>(own);
+      unsigned* dst = reinterpret_cast<unsigned*>(oth);
+      if (publish)
+        for (int e = tid; e < B * np; e += NT) put_word(mine + e, tag, src[e]);
+      for (int e = tid; e < B * np; e += NT) dst[e] = get_word(other + e, tag, spin, xerr);
+      __syncthreads();
+    }
+    // the middle block, and y of this half's level k - 2 block
+    for (int t = wv; t < 2; t += NW) {
+      C acc[RPL];
+      if (t == 0) {
+        nd_mv3<RPL>(acc, mat(mid, 0), own, oth, mone, zv, zero, B);
+        nd_store<RPL>(own, acc, B);
+      } else if (k >= 3) {
+        const int e = (half ? 3 : 1) * (1 << (k - 2)) - 1;
+        nd_mv3<RPL>(acc, mat(e, 0), vec(e), zv, zero, zv, zero, B);
+        nd_store<RPL>(vec(e), acc, B);
+      }
+    }
+    __syncthreads();
+    // backward: level l's blocks e = odd 2^l - 1 from the solution of the levels above
+    for (int l = k - 2; l >= 0; --l) {
+      const int s = 1 << l, ne = 1 << (k - 2 - l), o0 = half ? 2 * ne + 1 : 1;
+      for (int t = wv; t < ne; t += NW) {
+        const int e = (o0 + 2 * t) * s - 1;
+        const bool hl = e - s >= 0, hu = e + s <= n - 1;
+        C acc[RPL];
+        if (l >= 1) {
+          nd_load<RPL>(acc, vec(e), B);
+          if (hl) nd_mv<RPL>(acc, mat(e, 1), mone, vec(e - s), B);
+          if (hu) nd_mv<RPL>(acc, mat(e, 2), mone, vec(e + s), B);
+        } else {
+          nd_mv3<RPL>(acc, mat(e, 0), vec(e), hl ? vec(e - 1) : zv, hl ? cf[e + 1] : zero,
+                      hu ? vec(e + 1) : zv, hu ? cb[e + 1] : zero, B);
+        }
+        nd_store<RPL>(vec(e), acc, B);
+      }
+      __syncthreads();
+    }
   }
 
   // Line (g, l) of slab g.  Input: forward, the slab input on the line's rows minus the
@@ -635,7 +824,7 @@ struct Sweeper {
     const bool from_above = (kind == kFwdHigh && g < Gz - 1) || kind == kFwdMid || kind == kBwdLow;
     const bool in_below = (lkind == kFwdLow && l > 0) || lkind == kFwdMid;
     const bool in_above = (lkind == kFwdHigh && l < Gy - 1) || lkind == kFwdMid;
-    const C* T = factors + line_off[(size_t)g * Gy + l];
+    const C* T = line_factors(g, l);
     C* yb = sb + L.ybuf;
     // The elements are taken kGatherU per thread at a time: the loads of f (the bulk of the
     // gather) for the whole batch are issued first, so a batch waits for one memory latency.
@@ -888,7 +1077,7 @@ struct Sweeper {
   // window row, then the x3 window layer), input and output complex128
   __device__ __forceinline__ void single_line(int g, int l) {
     const int Wz = groups[g].W, Wy = groups[Gz + l].W, B = Wy * Wz;
-    const C* T = factors + line_off[(size_t)g * Gy + l];
+    const C* T = line_factors(g, l);
     C* yb = sb + L.ybuf;
     const double2* r = reinterpret_cast<const double2*>(f);
     auto gather = [&]() {
@@ -917,12 +1106,7 @@ struct Sweeper {
 // (members 2q and 2q + 1) on one XCD, XCD q (8 / P) + slot mod (8 / P) for the P = wpr / 2
 // pairs of a right-hand side, so the exchange inside a line solve stays in one L2 and each
 // XCD reads 1 / P of the factor stream.  Slots past R (the grid is rounded up) exit at once.
-template <typename R, typename TI, typename TO, int NCA, int CWA, int DA, int NCB, int CWB, int DB,
-          bool ADJ>
-__global__ void __launch_bounds__((kernel_threads_max<NCA, CWA, NCB, CWB>())) k_sweep(SweepArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int b = (int)blockIdx.x;
-  int slot, member;
+__device__ __forceinline__ void member_of(const SweepArgs& a, int b, int& slot, int& member) {
   if (a.xmap == 1) {
     slot = b / a.wpr;
     member = b - slot * a.wpr;
@@ -936,8 +1120,30 @@ __global__ void __launch_bounds__((kernel_threads_max<NCA, CWA, NCB, CWB>())) k_
     member = k8 - grp * a.wpr;
     slot = grp * 8 + (b & 7);
   }
+}
+
+template <typename R, typename TI, typename TO, int NCA, int CWA, int DA, int NCB, int CWB, int DB,
+          bool ADJ>
+__global__ void __launch_bounds__((kernel_threads_max<NCA, CWA, NCB, CWB>())) k_sweep(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int slot, member;
+  member_of(a, (int)blockIdx.x, slot, member);
   if (slot >= a.R) return;
   Sweeper<R, TI, TO, NCA, CWA, DA, NCB, CWB, DB, ADJ> s(a, smem_raw, slot, member);
+  if (a.mode == 1) s.single_line(a.line_g, a.line_l);
+  else s.sweep();
+}
+
+// The same sweep with every line solved by nested dissection (complex64, forward sweeps):
+// the members, their exchanges and the placements are those of k_sweep
+constexpr int kNdThreads = 512;
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(kNdThreads) k_sweep_nd(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int slot, member;
+  member_of(a, (int)blockIdx.x, slot, member);
+  if (slot >= a.R) return;
+  Sweeper<float, TI, TO, 8, 7, 2, 8, 11, 2, false, true> s(a, smem_raw, slot, member);
   if (a.mode == 1) s.single_line(a.line_g, a.line_l);
   else s.sweep();
 }

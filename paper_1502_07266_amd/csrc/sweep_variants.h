@@ -31,6 +31,8 @@ const std::vector<SweepVariant>& sweep_variants(bool c64);
 // the kernel of variant k (sweep_c64_{fwd,adj}{,_z32}.hip, sweep_c128.hip): complex64
 // sweeps writing complex128 (z64) or complex64 output, or complex128 sweeps; forward or adjoint
 const void* sweep_kernel(bool c64, bool z64, bool adj, int k);
+// the nested-dissection sweep kernel (complex64 forward sweeps; sweep_c64_nd.hip)
+const void* sweep_kernel_c64_nd(bool z64);
 const void* sweep_kernel_c64_fwd(bool z64, int k);
 const void* sweep_kernel_c64_adj(bool z64, int k);
 const void* sweep_kernel_c64_fwd_z32(int k);
