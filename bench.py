@@ -39,10 +39,12 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_step(Helm, c, wl, F, prec, fronts, fronts_inner):
+def run_step(Helm, c, wl, F, prec, fronts, fronts_inner, line_solver="ldu"):
     import torch
     H = Helm(c, wl["omega"], wl["b"], wl["C"], wl["p"], wl["d"], prec=prec, fronts=fronts,
              fronts_inner=fronts_inner, C_moving=wl.get("C_moving", 0.0))
+    if line_solver != "ldu":
+        H.set_line_solver(line_solver)
     u, its, rel, rc = H.solve(F, tol=wl["tol"], restart=wl["restart"], maxit=wl.get("maxit", 400))
     torch.cuda.synchronize()
     st = H.stats()
@@ -256,6 +258,9 @@ def main():
                     help="after the FP64 solve, continue it to this residual for a reference "
                          "solution the two 1e-6 solves are measured against (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
+    ap.add_argument("--line-solver", default="ldu", choices=["ldu", "nd"],
+                    help="line problems of the complex64 sweeps: block LDU chains (default) or "
+                         "nested dissection (factored in the step after the block LDU setup)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the sweep for one "
@@ -283,7 +288,7 @@ def main():
     first_step_s = None
     for w in range(args.warmup):
         tw = time.perf_counter()
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner, args.line_solver)
         if first_step_s is None:
             first_step_s = time.perf_counter() - tw
         log(f"warmup {w}: iters {its.tolist()} setup {st['setup_ms']:.1f} ms apply {st['apply_ms']:.0f} ms")
@@ -292,7 +297,7 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot = {"apply_ms": 0.0, "apply_launches": 0, "apply_rhs": 0, "setup_ms": 0.0,
+    tot = {"apply_ms": 0.0, "apply_launches": 0, "apply_rhs": 0, "setup_ms": 0.0, "nd_setup_ms": 0.0,
            "matvec_ms": 0.0, "matvec_launches": 0, "matvec_rhs": 0,
            "kernel_ms": 0.0, "kernel_launches": 0, "kernel_rhs": 0, "kernel_bytes": 0.0,
            "kernel_flops": 0.0}
@@ -300,7 +305,9 @@ def main():
     step_s = []
     for k in range(args.steps):
         ts = time.perf_counter()
-        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner)
+        H, u, its, rel, rc, st = run_step(Helm, c, wl, F, "c64", args.fronts, args.fronts_inner, args.line_solver)
+        if args.line_solver != "nd":
+            st["nd_setup_ms"] = 0.0
         step_s.append(time.perf_counter() - ts)
         for key in tot:
             tot[key] += st[key]
@@ -327,13 +334,21 @@ def main():
     unique_bytes = tot["kernel_bytes"] / kl
     effective_bytes = kst["apply_bytes_per_rhs"] * rhs_per_launch
     flops = tot["kernel_flops"] / kl
+    if args.line_solver == "nd":
+        # the library counts the block LDU factors (n blocks per line visit); nested dissection
+        # reads its own matrices, 3 n - 2 popcount(n) blocks per line visit
+        nd_scale = (3 * n - 2 * bin(n).count("1")) / n
+        vec_bytes = 32.0 * n ** 3 * rhs_per_launch
+        unique_bytes = (unique_bytes - vec_bytes) * nd_scale + vec_bytes
+        effective_bytes = (effective_bytes - vec_bytes) * nd_scale + vec_bytes
+        flops = None
     achieved = unique_bytes / (kernel_avg_ms * 1e-3) / 1e9
     steps_per_sweep, _ = dependent_steps(n, wl["b"], wl["d"], args.fronts, args.fronts_inner)
     steps_per_kernel = steps_per_sweep
     mv_gbs = kst["matvec_bytes_per_rhs"] * tot["matvec_rhs"] / max(tot["matvec_ms"] * 1e-3, 1e-12) / 1e9
     # device time of the step's kernels, from the library's own event pairs (sweeps and
     # matvecs) plus the setup; the rest is Krylov kernels and host work
-    kernels_ms = (tot["apply_ms"] + tot["matvec_ms"] + tot["setup_ms"]) / args.steps
+    kernels_ms = (tot["apply_ms"] + tot["matvec_ms"] + tot["setup_ms"] + tot["nd_setup_ms"]) / args.steps
 
     result = {
         "metric": METRIC,
@@ -358,7 +373,8 @@ def main():
                    "factor_bytes": info["factor_bytes"], "lines": info["n_lines"], "max_block": info["max_block"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_sweep, complex64: the whole sweep of the batch in one cooperative "
+                     "kernel": ("k_sweep_nd (line solves by nested dissection)" if args.line_solver == "nd" else "k_sweep") +
+                               ", complex64: the whole sweep of the batch in one cooperative "
                                f"launch ({tot['kernel_launches'] / max(tot['apply_launches'], 1):g} per "
                                f"sweep), launch shape {shape[1]} (variant {shape[0]})",
                      "avg_launch_ms": round(kernel_avg_ms, 4),
@@ -371,8 +387,8 @@ def main():
                      "effective_note": "the factor stream counted once per right-hand side, as if "
                                        "each chain streamed its own copy",
                      "fp32_flops_per_launch": flops,
-                     "fp32_tflops": round(flops / (kernel_avg_ms * 1e-3) / 1e12, 2),
-                     "fp32_frac": round(flops / (kernel_avg_ms * 1e-3) / 157.3e12, 4),
+                     "fp32_tflops": round(flops / (kernel_avg_ms * 1e-3) / 1e12, 2) if flops else None,
+                     "fp32_frac": round(flops / (kernel_avg_ms * 1e-3) / 157.3e12, 4) if flops else None,
                      "rhs_per_launch": rhs_per_launch},
         "sweep_ms_per_apply": round(apply_avg_ms, 3),
         "ns_per_dependent_step": round(kernel_avg_ms * 1e6 / steps_per_kernel, 1),
@@ -383,6 +399,8 @@ def main():
         "first_step_s": round(first_step_s, 4),
         "step_s_min_max": [round(min(step_s), 4), round(max(step_s), 4)],
         "setup_ms": round(tot["setup_ms"] / args.steps, 2),
+        "line_solver": args.line_solver,
+        "nd_setup_ms": round(tot["nd_setup_ms"] / args.steps, 2) if args.line_solver == "nd" else None,
         "setup_matrix_cores": setup_mfma(wl, args.fronts, args.fronts_inner, tot["setup_ms"] / args.steps),
         "apply_ms_total_per_step": round(tot["apply_ms"] / args.steps, 1),
         "matvec_ms_total_per_step": round(tot["matvec_ms"] / args.steps, 2),
@@ -391,7 +409,7 @@ def main():
         "matvec_gbs": round(mv_gbs, 1),
         "device_pool_bytes": dict(zip(("cached", "live"), pool_stats())),
     }
-    tr = measured_traffic(args.workload, wl, args.fronts, args.fronts_inner)
+    tr = measured_traffic(args.workload, wl, args.fronts, args.fronts_inner) if args.line_solver == "ldu" else None
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
         result["roofline"]["traffic_ratio"] = round(tr["hbm_bytes_per_launch"] / unique_bytes, 3)
