@@ -25,6 +25,7 @@ constexpr int kDotThreads = 256;
 constexpr int kDotPerThread = 8;
 constexpr int kDotChunk = kDotThreads * kDotPerThread;
 constexpr int kMaxRestart = 200;
+constexpr int kFuse = 8;   // k_update_dots keeps up to this many basis values per element in registers
 
 __device__ inline double2 block_sum(double2 v, double2* red) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -115,6 +116,39 @@ __global__ void __launch_bounds__(kDotThreads) k_update_dots(double2* __restrict
   }
   __syncthreads();
   const long long base = (long long)chunk * kDotChunk + threadIdx.x;
+  if (!NORM && K <= kFuse) {
+    // element by element: its K basis values loaded once, the update, then its terms of the
+    // K dot products (the same operations, in the same order, as the general path below)
+    const TX* xp[kFuse];
+#pragma unroll
+    for (int k = 0; k < kFuse; ++k) xp[k] = k < K ? X.at(k, q) : nullptr;
+    double2 acc[kFuse];
+#pragma unroll
+    for (int k = 0; k < kFuse; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int t = 0; t < kDotPerThread; ++t) {
+      const long long e = base + (long long)t * kDotThreads;
+      if (e >= N) break;
+      double2 xv[kFuse];
+#pragma unroll
+      for (int k = 0; k < kFuse; ++k)
+        if (k < K) xv[k] = cvt<double2>(xp[k][e]);
+      double2 wv = w[(long long)q * wr + e];
+#pragma unroll
+      for (int k = 0; k < kFuse; ++k)
+        if (k < K) wv = cfma(wv, c[k], xv[k]);
+      w[(long long)q * wr + e] = wv;
+#pragma unroll
+      for (int k = 0; k < kFuse; ++k)
+        if (k < K) acc[k] = cfma_conj(acc[k], xv[k], wv);
+    }
+#pragma unroll
+    for (int k = 0; k < kFuse; ++k) {
+      if (k >= K) break;
+      const double2 sum = block_sum(acc[k], red);
+      if (threadIdx.x == 0) partial[((long long)a * K + k) * nchunk + chunk] = sum;
+    }
+    return;
+  }
   double2 wv[kDotPerThread];
 #pragma unroll
   for (int t = 0; t < kDotPerThread; ++t) {
