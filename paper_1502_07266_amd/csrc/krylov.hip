@@ -118,13 +118,16 @@ __global__ void __launch_bounds__(kDotThreads) k_update_dots(double2* __restrict
   const long long base = (long long)chunk * kDotChunk + threadIdx.x;
   if (!NORM && K <= kFuse) {
     // element by element: its K basis values loaded once, the update, then its terms of the
-    // K dot products (the same operations, in the same order, as the general path below)
+    // K dot products (the same operations, in the same order, as the general path below) and
+    // of |w|^2 after the update, written as a (K + 1)-th dot product
+    const int KS = K + 1;
     const TX* xp[kFuse];
 #pragma unroll
     for (int k = 0; k < kFuse; ++k) xp[k] = k < K ? X.at(k, q) : nullptr;
     double2 acc[kFuse];
 #pragma unroll
     for (int k = 0; k < kFuse; ++k) acc[k] = make_double2(0.0, 0.0);
+    double2 ww = make_double2(0.0, 0.0);
     for (int t = 0; t < kDotPerThread; ++t) {
       const long long e = base + (long long)t * kDotThreads;
       if (e >= N) break;
@@ -140,13 +143,16 @@ __global__ void __launch_bounds__(kDotThreads) k_update_dots(double2* __restrict
 #pragma unroll
       for (int k = 0; k < kFuse; ++k)
         if (k < K) acc[k] = cfma_conj(acc[k], xv[k], wv);
+      ww = cfma_conj(ww, wv, wv);
     }
 #pragma unroll
     for (int k = 0; k < kFuse; ++k) {
       if (k >= K) break;
       const double2 sum = block_sum(acc[k], red);
-      if (threadIdx.x == 0) partial[((long long)a * K + k) * nchunk + chunk] = sum;
+      if (threadIdx.x == 0) partial[((long long)a * KS + k) * nchunk + chunk] = sum;
     }
+    const double2 sum = block_sum(ww, red);
+    if (threadIdx.x == 0) partial[((long long)a * KS + K) * nchunk + chunk] = sum;
     return;
   }
   double2 wv[kDotPerThread];
@@ -244,6 +250,45 @@ __global__ void __launch_bounds__(256) k_scale(double2* __restrict__ V, long lon
   const double s = nrm[q].x > 0.0 ? 1.0 / nrm[q].x : 0.0;
   const double2 w = W[(long long)q * wr + e];
   V[(long long)q * vr + e] = make_double2(w.x * s, w.y * s);
+}
+
+// ||w''|| = sqrt(|w'|^2 - |h2|^2) for w'' = w' - V h2, h2 = V^H w' (V orthonormal; w' is
+// orthogonal to V up to rounding after the first projection, so there is no cancellation):
+// |w'|^2 sits at h2[K], after the K coefficients.  A negative difference (breakdown, w' = 0 up
+// to rounding) gives 0, NaN stays NaN.
+__global__ void k_norm_after(const double2* __restrict__ h2, int hstride, int K, double2* __restrict__ nrm,
+                             const int* __restrict__ idx, int na) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= na) return;
+  const int q = idx[a];
+  const double2* h = h2 + (long long)q * hstride;
+  double s = h[K].x;
+  for (int k = 0; k < K; ++k) s -= h[k].x * h[k].x + h[k].y * h[k].y;
+  nrm[q] = make_double2(s > 0.0 ? sqrt(s) : (s == s ? 0.0 : s), 0.0);
+}
+
+// V_q = (W_q - sum_{k < K} h2[q][k] X_{q,k}) / nrm_q (0 if the norm vanished)
+template <typename TX>
+__global__ void __launch_bounds__(256) k_update_scale(double2* __restrict__ V, long long vr,
+                                                      const double2* __restrict__ W, long long wr,
+                                                      Basis<TX> X, const double2* __restrict__ coef,
+                                                      int cstride, int K, const double2* __restrict__ nrm,
+                                                      const int* __restrict__ idx, long long N) {
+  __shared__ double2 c[kFuse];
+  const int q = idx[blockIdx.y];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double2 v = coef[(long long)q * cstride + k];
+    c[k] = make_double2(-v.x, -v.y);
+  }
+  __syncthreads();
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double2 acc = W[(long long)q * wr + e];
+#pragma unroll
+  for (int k = 0; k < kFuse; ++k)
+    if (k < K) acc = cfma(acc, c[k], cvt<double2>(X.at(k, q)[e]));
+  const double sc = nrm[q].x > 0.0 ? 1.0 / nrm[q].x : 0.0;
+  V[(long long)q * vr + e] = make_double2(acc.x * sc, acc.y * sc);
 }
 
 // start of a cycle: g = (beta, 0, ..., 0)
@@ -541,11 +586,19 @@ int fgmres_solve(helm_handle* h, const double2* f, double2* u, int R, double tol
       k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, ws.h1, m + 1, 0);
       k_update_dots<double2, false><<<dim3(nchunk, a), kDotThreads, 0, s>>>(
           ws.W, N, ws.V, ws.h1, m + 1, j + 1, ws.idx, ws.partial, nchunk, N);
-      k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, ws.h2, m + 1, 0);
-      k_update_dots<double2, true><<<dim3(nchunk, a), kDotThreads, 0, s>>>(
-          ws.W, N, ws.V, ws.h2, m + 1, j + 1, ws.idx, ws.partial, nchunk, N);
-      k_dots_final<<<dim3(1, a), kDotThreads, 0, s>>>(ws.partial, 1, nchunk, ws.idx, ws.nrm, 1, 1);
-      k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V.at(j + 1, 0), N, ws.W, N, ws.nrm, ws.idx, N);
+      if (j + 1 <= kFuse) {
+        // h2 and |w'|^2 (at h2[j + 1]); then w'' and its normalisation in one pass
+        k_dots_final<<<dim3(j + 2, a), kDotThreads, 0, s>>>(ws.partial, j + 2, nchunk, ws.idx, ws.h2, m + 1, 0);
+        k_norm_after<<<(a + 63) / 64, 64, 0, s>>>(ws.h2, m + 1, j + 1, ws.nrm, ws.idx, (int)a);
+        k_update_scale<double2><<<dim3(nb, a), 256, 0, s>>>(ws.V.at(j + 1, 0), N, ws.W, N, ws.V, ws.h2, m + 1,
+                                                           j + 1, ws.nrm, ws.idx, N);
+      } else {
+        k_dots_final<<<dim3(j + 1, a), kDotThreads, 0, s>>>(ws.partial, j + 1, nchunk, ws.idx, ws.h2, m + 1, 0);
+        k_update_dots<double2, true><<<dim3(nchunk, a), kDotThreads, 0, s>>>(
+            ws.W, N, ws.V, ws.h2, m + 1, j + 1, ws.idx, ws.partial, nchunk, N);
+        k_dots_final<<<dim3(1, a), kDotThreads, 0, s>>>(ws.partial, 1, nchunk, ws.idx, ws.nrm, 1, 1);
+        k_scale<<<dim3(nb, a), 256, 0, s>>>(ws.V.at(j + 1, 0), N, ws.W, N, ws.nrm, ws.idx, N);
+      }
       k_givens<<<(a + 63) / 64, 64, 0, s>>>(j, m, ws.h1, ws.h2, ws.nrm, ws.H, ws.cs, ws.sn, ws.g,
                                            ws.resid, ws.idx, (int)a);
       HIP_MSG(hipGetLastError());
