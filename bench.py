@@ -7,7 +7,7 @@ applied in complex64 and GMRES, matvec and residuals in FP64.  The outer sweep r
 fronts (from both x3-faces, as in the paper's experiments) unless --fronts 1, and so does the
 inner sweep over x2 unless --fronts-inner 1.  Inputs are resident on the GPU before the timed
 region.  Default workload: 127^3 interior points, 5-cell PML (C = 30 b),
-2-cell moving PML of constant C/8, five layers per auxiliary problem, a Gaussian random field
+2-cell moving PML of constant 0.16 C, five layers per auxiliary problem, a Gaussian random field
 in [1, 2] (correlation length 0.1), omega = 2 pi 16, 32 point sources at seeded interior
 nodes, GMRES(50) to relative residual 1e-6.
 

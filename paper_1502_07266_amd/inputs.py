@@ -142,11 +142,11 @@ def workload(name):
         return dict(name=name, n=n, b=b, p=6, d=1, C=30.0 * b, omega=2 * math.pi * 8,
                     c=medium_lens(n), nodes=[node], tol=1e-6, restart=50)
     if name == "c3":      # Gaussian random field in [1, 2], 32 batched point sources
-        # five layers per auxiliary problem and a 2-cell moving PML of an eighth of the boundary
+        # five layers per auxiliary problem and a 2-cell moving PML with 0.16 of the boundary
         # PML's constant (the workload fixes only the 5-cell boundary PML): the fastest solve
         # among the measured (d, p, C_moving) with blocks the sweep supports
         n, b = 127, 5
-        return dict(name=name, n=n, b=b, p=2, d=5, C=30.0 * b, C_moving=30.0 * b / 8, omega=2 * math.pi * 16,
+        return dict(name=name, n=n, b=b, p=2, d=5, C=30.0 * b, C_moving=30.0 * b * 0.16, omega=2 * math.pi * 16,
                     c=medium_grf(n, 0.1, 1.0, 2.0), nodes=random_source_nodes(n, b, 32),
                     tol=1e-6, restart=50)
     if name == "c4":      # two-layer medium, 8 sources at x3 = 0.1, receivers at x3 = 0.9

@@ -4,7 +4,7 @@
 the oracle's Algorithm 6 on seeded right-hand sides (one front and two fronts), and the solve
 with a sparse direct solve.
 127^3 (the batched mixed-precision workload): in the benchmarked configuration (d = 5,
-p = 2, C_moving = C/8, two fronts in x3 and x2) the matvec and the whole preconditioner are
+p = 2, C_moving = 0.16 C, two fronts in x3 and x2) the matvec and the whole preconditioner are
 compared element by element with the oracle's (its setup takes about a minute), and the
 mixed-precision solve with the oracle's solutions to 1e-10 stored under tests/golden; with one
 front per axis, sampled line factorisations are compared block by block, and the sweep is
@@ -231,7 +231,7 @@ def test_c4_gradient_against_central_differences():
 
 
 # ---------------------------------------------------------------------------------------------
-# The benchmarked 127^3 configuration in full: d = 5, p = 2, C_moving = C/8, two fronts in x3
+# The benchmarked 127^3 configuration in full: d = 5, p = 2, C_moving = 0.16 C, two fronts in x3
 # and in x2 (the oracle's setup takes about a minute on 8 cores, one apply 15 s)
 # ---------------------------------------------------------------------------------------------
 @pytest.fixture(scope="module")
