@@ -153,7 +153,8 @@ def cpu_baseline(wl, iters, fronts=2, fronts_inner=2):
     of this workload and scaled to one step.  Sample: the assembly of A (eq. (3)); the setup
     (Algorithm 3: every line factorisation) of three x3-slabs, a boundary slab, an interior
     front slab and the middle slab, and one inner sweep (Algorithm 4) of each on one
-    right-hand side; one matvec; one Gram-Schmidt dot product + update.  Scaled: setup = the
+    right-hand side; one matvec; one Gram-Schmidt dot product + update (each timed several
+    times, the median kept).  Scaled: setup = the
     assembly + every slab's setup (the boundary slabs, the interior ones and the middle one by
     their samples); per GMRES iteration and right-hand side one sweep (each slab applied twice,
     the middle slab once: Algorithm 6 with two fronts; Algorithm 6 as printed applies the last
@@ -176,26 +177,32 @@ def cpu_baseline(wl, iters, fronts=2, fronts_inner=2):
     t0 = time.perf_counter()
     A = O.helmholtz_matrix(prob)
     t_asm = time.perf_counter() - t0
+    def median_time(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    # each piece timed several times (median): about 10 s of host work in all
     samples = {}
     for tag, g in (("boundary", 0), ("interior", mid - 1), ("middle", mid)):
-        t1 = time.perf_counter()
-        slab = O.SlabSweep(prob, Gz, g, Gy)
-        t_set = time.perf_counter() - t1
+        slabs = []
+        t_set = median_time(lambda: slabs.append(O.SlabSweep(prob, Gz, g, Gy)), 3)
+        slab = slabs[-1]
         gv = rng.standard_normal(slab.H.shape[0]) + 1j * rng.standard_normal(slab.H.shape[0])
-        t2 = time.perf_counter()
-        slab.apply(gv)
-        samples[tag] = (t_set, time.perf_counter() - t2)
+        samples[tag] = (t_set, median_time(lambda: slab.apply(gv), 5))
+        del slabs
     N = n ** 3
     x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
-    t3 = time.perf_counter()
-    A @ x
-    t_mv = time.perf_counter() - t3
+    t_mv = median_time(lambda: A @ x, 5)
     y = rng.standard_normal(N) + 1j * rng.standard_normal(N)
-    t4 = time.perf_counter()
-    for _ in range(4):
+
+    def orth():
         hij = np.vdot(x, y)
-        y = y - hij * x
-    t_orth = (time.perf_counter() - t4) / 4
+        return y - hij * x
+    t_orth = median_time(orth, 20)
     nb = 2 if fronts == 2 else 1                  # boundary slabs (one front: slab 0 only)
     n_int = G - nb - 1
     setup = t_asm + nb * samples["boundary"][0] + n_int * samples["interior"][0] + samples["middle"][0]
@@ -209,7 +216,7 @@ def cpu_baseline(wl, iters, fronts=2, fronts_inner=2):
     est = setup + solve
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     sample = (f"oracle on {threads} BLAS threads ({_cpu_model()}, {os.cpu_count()} logical CPUs): "
-              f"assembly of A {t_asm:.2f} s; setup of a boundary / interior / middle x3-slab "
+              f"medians of repeated timings: assembly of A {t_asm:.2f} s; setup of a boundary / interior / middle x3-slab "
               f"{samples['boundary'][0]:.2f} / {samples['interior'][0]:.2f} / {samples['middle'][0]:.2f} s "
               f"and one inner sweep of each {samples['boundary'][1]:.3f} / {samples['interior'][1]:.3f} / "
               f"{samples['middle'][1]:.3f} s; matvec {t_mv:.3f} s; Gram-Schmidt dot + update "
