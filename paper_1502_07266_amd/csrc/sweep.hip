@@ -11,6 +11,7 @@
 // the configuration (helm_autotune, run on the first solve of a configuration), or the first
 // listed variant that covers the blocks.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -482,6 +483,11 @@ hipError_t autotune_sweep(helm_handle* h, int R, int* best_out, double* best_ms,
     if (e == hipSuccess && (*best_out < 0 || ms / 2 < *best_ms)) {
       *best_out = k;
       *best_ms = ms / 2;
+    }
+    if (e == hipSuccess && std::getenv("HELM_VERBOSE")) {
+      std::fprintf(stderr, "[helm tune] R=%d candidate %d (%s): %.2f ms per sweep\n", R, k,
+                   sweep_variant_name(c64, k).c_str(), ms / 2);
+      std::fflush(stderr);
     }
   }
   h->variant = saved;
