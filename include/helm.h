@@ -321,7 +321,8 @@ int helm_autotune(helm_handle* h, int R, const char* cache_path, int* variant_ou
  * helm_set_exchange_test -- failure-injection hook for tests of the sweep's error path:
  * drop_publish = 1 makes the first-half workgroup of every line solve skip publishing its
  * partial middle-block values, so its partner gives up after spin_limit polls (0: the
- * default bound, about a second) and the next helm_apply / helm_solve returns HELM_EHIP;
+ * default bound, 2^28 polls, tens of seconds) and the next helm_apply / helm_solve returns
+ * HELM_EHIP;
  * drop_publish = 0 restores normal operation.  Every kernel still ends normally.
  * Errors: HELM_EINVAL (h NULL, drop_publish not 0 or 1).
  */

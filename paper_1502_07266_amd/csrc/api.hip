@@ -470,7 +470,7 @@ int helm_set_exchange_test(helm_handle* h, int drop_publish, unsigned spin_limit
   if (!h) return fail(HELM_EINVAL, "handle is NULL");
   if (drop_publish != 0 && drop_publish != 1) return fail(HELM_EINVAL, "drop_publish must be 0 or 1");
   h->drop_publish = drop_publish;
-  h->spin_limit = spin_limit ? spin_limit : (1u << 20);
+  h->spin_limit = spin_limit ? spin_limit : kSpinDefault;
   return HELM_OK;
 }
 

@@ -172,6 +172,13 @@ struct LaunchTimer {
 // ---------------------------------------------------------------------------------------
 // the opaque handle
 // ---------------------------------------------------------------------------------------
+// Polls of a partner's exchange word before a sweep's wait gives up (each poll a device-memory
+// round trip and a short sleep; 2^28 of them take tens of seconds).  A wait is only as long as
+// the partner's work before it: at most one slab of the other outer front (the middle slab,
+// for the front that waits for it after its own forward slabs), which at 255^3 with blocks of
+// 126 unknowns is beyond 2^20 polls.
+constexpr unsigned kSpinDefault = 1u << 28;
+
 struct helm_handle {
   Plan plan;
   int n = 0, prec = HELM_C64, device = 0;
@@ -217,7 +224,7 @@ struct helm_handle {
   size_t xbytes = 0;
   unsigned long long xseq = 0;
   bool pairs_used = false;         // a sweep ran since the error word was last taken
-  unsigned spin_limit = 1u << 20;
+  unsigned spin_limit = kSpinDefault;
   int drop_publish = 0;
   int* d_rhs_idx = nullptr;
   int rhs_idx_cap = 0;

@@ -8,8 +8,8 @@ PML 9h, auxiliary (moving) PML 5h, 4 layers per auxiliary problem, two fronts in
 loop, GMRES(40) to relative residual 1e-3; the inner loop runs one front (with two, the
 middle-middle line would have 14 x 14 = 196 unknowns per block, beyond the sweep's one-chain
 limit of 128), and the boundary PML constant is C = 30 b as in the other workloads.  At
-255^3 these windows do not fit: a line vector of 255 blocks of 81 complex64 values exceeds
-the LDS of a workgroup.  Media (Sec. 5; synthetic stand-ins, the paper gives figures only):
+255^3 (52.8 GB of complex64 factors) a solve of one right-hand side takes about a minute.
+Media (Sec. 5; synthetic stand-ins, the paper gives figures only):
 (a) Gaussian lens and (b) vertical Gaussian waveguide with c = 1 + 0.4 exp(-r^2 / 0.02), so
 that q = 8 holds everywhere (c >= 1); (a-) and (b-) the same with c = 1 - 0.4 exp(...), whose
 slow centre has only 4.8 points per wavelength; (c) random field in [1, 2].  Forces: (a) a Gaussian point source at
