@@ -56,10 +56,6 @@
 
 namespace sweepk {
 
-// polls of a partner's word before a wait gives up (each a device-memory round trip and a
-// short sleep: on the order of a second)
-constexpr unsigned kSpinLimit = 1u << 20;
-
 struct SweepArgs {
   int n, Gz, Gy, maxW, maxB;
   int fronts, zmid, fronts_inner, ymid;
