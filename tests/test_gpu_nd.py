@@ -208,3 +208,26 @@ def test_nd_at_the_benchmarked_127cubed_configuration():
     assert np.all(np.abs(np.asarray(its_nd) - np.asarray(its_ldu)) <= 1)
     assert float(true_rel.max()) <= 1.01 * wl["tol"]
     H.close()
+
+
+def test_nd_static_apply_equals_apply():
+    """The allocation-free entry point runs the same nested-dissection kernel: helm_apply_static
+    equals helm_apply bit for bit, twice in a row (the second call with fewer right-hand sides),
+    with neither the library's pool nor torch's allocator growing."""
+    import ctypes
+    from paper_1502_07266_amd.binding import lib, pool_stats
+    sc, prob, M = case("b4p4_2f2i")
+    H = helm("b4p4_2f2i")
+    for R in (5, 2):
+        x = to_gpu(inputs.random_rhs(prob.n, R, seed=40 + R))
+        ref = H.apply(x)
+        z = torch.empty_like(x)
+        torch.cuda.synchronize()
+        pool, mem = pool_stats(), torch.cuda.memory_allocated()
+        rc = lib().helm_apply_static(H.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(z.data_ptr()), R, 0,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert rc == 0
+        assert pool_stats() == pool and torch.cuda.memory_allocated() == mem
+        assert torch.equal(z, ref)
+    H.close()
