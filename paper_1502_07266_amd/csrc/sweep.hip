@@ -167,8 +167,14 @@ std::vector<int> tune_candidates(const helm_handle* h) {
 // 2 one line-solve pair per XCD (3 is unused).
 int sweep_variant_for(const helm_handle* h, int R) {
   if (h->variant >= 0) return h->variant;
-  const int t = tuned_variant(tune_key(h, R));
-  return t >= 0 ? t : 4 * default_variant(h) + 1;
+  // a batch size the tuner has not timed (a solve's last sweeps, once some right-hand sides
+  // have converged) takes the choice tuned for the nearest larger batch of the configuration:
+  // a sweep's time is set by its chain, not by its batch
+  for (int r = (R + 7) / 8 * 8; r <= 4096; r += 8) {
+    const int t = tuned_variant(tune_key(h, r));
+    if (t >= 0) return t;
+  }
+  return 4 * default_variant(h) + 1;
 }
 
 bool sweep_variant_valid(const helm_handle* h, int c) {
